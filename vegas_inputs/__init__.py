@@ -1,0 +1,162 @@
+"""Seeded synthetic inputs for the VEGAS+ iteration.
+
+This module holds workload definitions only: integrand family ids, their
+parameter arrays, domains, budgets and the seeded generator for the batched
+workload.  It contains none of the method's arithmetic, so both the HIP path
+(through its Python binding) and the CPU oracle can be fed from it.
+
+Integrand families and parameter layouts (``params`` is a float64 array):
+
+====  ===========  ====================================================  ==========================
+id    name         f(x)                                                  params
+====  ===========  ====================================================  ==========================
+1     GAUSS_DIAG   A * sum_j exp(-sum_d (x_d - c_j)^2 / (2 s^2))         [A, s, M, c_0 .. c_{M-1}]
+2     GENZ_PPEAK   A * prod_d 1 / (a_d^-2 + (x_d - u_d)^2)               [A, a_0..a_{D-1}, u_0..]
+3     GENZ_GAUSS   A * exp(-sum_d a_d^2 (x_d - u_d)^2)                   [A, a_0..a_{D-1}, u_0..]
+4     GAUSS_CORR   N(x; mu 1, s^2 ((1-rho) I + rho 1 1^T))               [mu, s, rho]
+5     LINEAR       A * sum_d x_d                                         [A]
+6     ROOS         A * prod_d |4 x_d - 2|                                [A]
+7     CONST        A                                                     [A]
+8     COSINE       A * prod_d cos(x_d)                                   [A]
+====  ===========  ====================================================  ==========================
+
+The paper's test integrands are Tab. 3 (Sec. 4.1); the five benchmark
+workloads are defined below with the sizes they are measured at.  The paper
+runs on closed-form integrands only, so no dataset stands behind any of them.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from typing import List
+
+import numpy as np
+
+GAUSS_DIAG, GENZ_PPEAK, GENZ_GAUSS, GAUSS_CORR, LINEAR, ROOS, CONST, COSINE = range(1, 9)
+FAMILY_NAMES = {GAUSS_DIAG: "gauss_diag", GENZ_PPEAK: "genz_ppeak", GENZ_GAUSS: "genz_gauss",
+                GAUSS_CORR: "gauss_corr", LINEAR: "linear", ROOS: "roos", CONST: "const",
+                COSINE: "cosine"}
+
+
+@dataclass
+class Workload:
+    name: str
+    dim: int
+    family: int
+    params: np.ndarray
+    n_g: int
+    n_eval: int
+    n_iter: int
+    n_adapt: int = 0
+    alpha: float = 0.5
+    beta: float = 0.75
+    seed: int = 0
+    precision: str = "f64"          # arithmetic of the sample path: "f64" or "f32"
+    accum: str = "fp64"             # "fp64", "kahan" or "ordered"
+    n_min: int = 2
+    n_strat: int = 0                # 0: derived from the budget
+    lo: np.ndarray = field(default=None)
+    hi: np.ndarray = field(default=None)
+
+    def __post_init__(self):
+        if self.lo is None:
+            self.lo = np.zeros(self.dim)
+        if self.hi is None:
+            self.hi = np.ones(self.dim)
+        self.params = np.asarray(self.params, dtype=np.float64)
+
+    def with_(self, **kw) -> "Workload":
+        return replace(self, **kw)
+
+
+def gauss_diag_params(A: float, s: float, centres) -> np.ndarray:
+    c = np.asarray(centres, dtype=np.float64)
+    return np.concatenate([[A, s, float(c.size)], c])
+
+
+def normal_peak(s: float, dim: int) -> float:
+    """(2 pi s^2)^(-D/2): the value that makes one isotropic Gaussian a density."""
+    return (2.0 * math.pi * s * s) ** (-dim / 2.0)
+
+
+# --------------------------------------------------------------------------
+# the five benchmark workloads
+# --------------------------------------------------------------------------
+def gauss_prod_4d() -> Workload:
+    """d=4 product of exp(-(x_i-0.5)^2/(2*0.1^2)) on [0,1]^4; FP64 throughout;
+    128 intervals, 1e5 evals/iteration, 10 iterations, alpha 0.5, beta 0.75, seed 0."""
+    return Workload("gauss_prod_4d", 4, GAUSS_DIAG, gauss_diag_params(1.0, 0.1, [0.5]),
+                    n_g=128, n_eval=100_000, n_iter=10, precision="f64")
+
+
+def gauss3_8d() -> Workload:
+    """d=8, equal-weight mixture of three normalised isotropic Gaussians,
+    s=0.05, centred at 0.33, 0.5, 0.67 on the diagonal; 1024 intervals,
+    1e8 evals/iteration, 20 iterations; FP32 sample path, FP64 accumulators."""
+    s = 0.05
+    return Workload("gauss3_8d", 8, GAUSS_DIAG,
+                    gauss_diag_params(normal_peak(s, 8) / 3.0, s, [0.33, 0.5, 0.67]),
+                    n_g=1024, n_eval=100_000_000, n_iter=20, precision="f32")
+
+
+def ridge_4d() -> Workload:
+    """d=4 diagonal ridge: mean of 1000 normalised Gaussians, s=0.01, centres
+    at t_j = 0.3 + 0.4 j/999 on the diagonal; 1024 intervals, 2e8
+    evals/iteration, 30 iterations; FP32 sample path, FP64 accumulators."""
+    s = 0.01
+    c = 0.3 + 0.4 * np.arange(1000) / 999.0
+    return Workload("ridge_4d", 4, GAUSS_DIAG,
+                    gauss_diag_params(normal_peak(s, 4) / 1000.0, s, c),
+                    n_g=1024, n_eval=200_000_000, n_iter=30, precision="f32")
+
+
+def corr_gauss_16d() -> Workload:
+    """d=16 correlated Gaussian density, mean 0.5, s=0.03, pairwise rho=0.9;
+    1024 intervals; 1e6 evals/iteration."""
+    return Workload("corr_gauss_16d", 16, GAUSS_CORR, np.array([0.5, 0.03, 0.9]),
+                    n_g=1024, n_eval=1_000_000, n_iter=20, n_adapt=5, precision="f32")
+
+
+@dataclass
+class BatchInstance:
+    family: int
+    dim: int
+    params: np.ndarray
+    n_eval: int
+
+
+def genz_batch(n: int = 4096, seed: int = 0, budget_lo: float = 1e4,
+               budget_hi: float = 1e7) -> List[BatchInstance]:
+    """Seeded parametrised integrals of uneven dimension and budget.
+
+    Half product-peak, half Gaussian (Genz families), d ~ U{3..12},
+    a_d ~ U[5, 20], u_d ~ U[0.1, 0.9], budget ~ logU[budget_lo, budget_hi].
+    The normalisation A is left at 1; the closed form of each instance is
+    computed by the tests.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        fam = GENZ_PPEAK if i % 2 == 0 else GENZ_GAUSS
+        d = int(rng.integers(3, 13))
+        a = rng.uniform(5.0, 20.0, size=d)
+        u = rng.uniform(0.1, 0.9, size=d)
+        b = int(round(math.exp(rng.uniform(math.log(budget_lo), math.log(budget_hi)))))
+        out.append(BatchInstance(fam, d, np.concatenate([[1.0], a, u]), b))
+    return out
+
+
+# --------------------------------------------------------------------------
+# small parity workloads (several tiles, a ragged tail)
+# --------------------------------------------------------------------------
+def small_cases() -> List[Workload]:
+    return [
+        gauss_prod_4d().with_(name="gauss4_small", n_eval=20_011, n_g=16, n_iter=3),
+        Workload("ppeak3", 3, GENZ_PPEAK,
+                 np.array([1.0, 6.0, 9.0, 12.0, 0.3, 0.6, 0.45]), n_g=32,
+                 n_eval=50_003, n_iter=3, precision="f64"),
+        Workload("roos5", 5, ROOS, np.array([1.0]), n_g=8, n_eval=30_001, n_iter=3),
+        Workload("linear1", 1, LINEAR, np.array([2.0]), n_g=64, n_eval=9_999, n_iter=3),
+        gauss3_8d().with_(name="gauss3_8d_small", n_eval=70_001, n_g=64, n_iter=2,
+                          precision="f64"),
+    ]
