@@ -1,0 +1,136 @@
+"""Throughput of the VEGAS+ iteration on one MI355X.
+
+Workload: the d=8 mixture of three normalised Gaussians (s = 0.05, centres
+0.33 / 0.5 / 0.67 on the diagonal), 1024 intervals per axis, 1e8 integrand
+evaluations per iteration, FP32 sample path with FP64 per-cube and total
+accumulators.  One step = one whole iteration (fill, cube fix-up, estimate,
+allocation update, map refinement) over 1e8 synthetic samples; the inputs
+(map, allocation, parameters) are resident in HBM before timing starts.
+
+Prints one JSON line: evals/s, ms per step, the fill kernel's position
+against the VALU issue roofline (timed with HIP events inside the library on
+its stream), and the CPU oracle timed on a bounded sample of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz -> VALU lane-operations/s
+VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
+
+
+def valu_ops_per_eval(dim: int, n_terms: int) -> int:
+    """Algorithmic VALU lane-operations of one sample of the GAUSS_DIAG FP32
+    path: the operations the method itself needs, counted once each.
+
+    Philox4x32-10, per block of 4 axes: 10 rounds x (2 32x32->64 products +
+    2 three-input xors) = 40.  Per axis: fixed-point bin (product, two
+    shifts/masks, stratum multiply-add, divide-by-constant high product and
+    shift, remainder) 7, offset (2 converts, fma, multiply) 4, map (address,
+    difference, fma, two Jacobian products) 5, integrand accumulators 3, two
+    histogram addresses 2 -> 21.  Integrand finish: mean and spread 5, per
+    Gaussian term 3 + 1 transcendental, prefactor 3 + 1 transcendental.
+    Weight, square and FP64 cube moments: 8.
+    """
+    blocks = (dim + 3) // 4
+    return 40 * blocks + 21 * dim + 5 + 4 * n_terms + 4 + 8
+
+
+def cpu_baseline(w, budget_evals: int, iters: int):
+    import oracle
+    ww = w.with_(n_eval=budget_evals, n_iter=iters)
+    t0 = time.perf_counter()
+    oracle.run(ww.dim, ww.n_g, ww.n_eval, ww.family, ww.params, n_iter=ww.n_iter, seed=ww.seed,
+               alpha=ww.alpha, beta=ww.beta)
+    dt = time.perf_counter() - t0
+    return {"value": budget_evals * iters / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} iterations x {budget_evals:.0e} evals of the same integrand, dim and "
+                      f"intervals (single-threaded FP64 C oracle, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n-eval", type=float, default=1e8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-evals", type=float, default=1.5e7)
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the VEGAS+ path here "
+              "runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import vegas_inputs as vi
+    from paper_2408_09229_amd import Vegas, make_config
+
+    w = vi.gauss3_8d().with_(n_eval=int(args.n_eval))
+    torch.cuda.set_device(0)
+    cfg = make_config(w.dim, w.n_g, w.n_eval, alpha=w.alpha, beta=w.beta, seed=w.seed, precision="f32",
+                      max_iter=args.warmup + args.steps + 1)
+    v = Vegas(cfg, w.family, w.params)
+    print(f"[bench] {w.name}: n_eval={w.n_eval} tiles={v.info.n_tiles} wg={v.info.n_workgroups}",
+          file=sys.stderr, flush=True)
+    v.adapt(args.warmup)
+    torch.cuda.synchronize()
+    v.set_timing(True)
+    st = v.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    v.integrate(args.steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    phases, n_timed = v.get_timing()
+    r = v.result()
+    ms_step = ms / args.steps
+    value = w.n_eval * args.steps / (ms / 1e3)
+    fill_ms = phases[0] / max(n_timed, 1)
+    ops = valu_ops_per_eval(w.dim, int(w.params[2])) * w.n_eval
+    ach = ops / (fill_ms / 1e3)
+    print(f"[bench] integral={r.integral:.12f} +- {math.sqrt(r.sigma2):.3e} chi2/dof={r.chi2_dof:.2f} "
+          f"phases ms/it: fill {fill_ms:.3f} fixup+est {phases[1] / n_timed:.3f} alloc "
+          f"{phases[2] / n_timed:.3f} map {phases[3] / n_timed:.3f}", file=sys.stderr, flush=True)
+    out = {
+        "metric": "integrand evals/sec (VEGAS+ iteration)",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "gauss3_8d: d=8 mixture of 3 Gaussians s=0.05, 1024 intervals, "
+                               f"{w.n_eval:.0e} evals/iteration, FP32 sample path + FP64 accumulators",
+                   "n_eval": w.n_eval, "dim": w.dim, "n_intervals": w.n_g, "parallelism": "single-gpu"},
+        "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
+                     "unit": "Tops/s (VALU lane-ops)", "frac": ach / VALU_LANE_OPS_PEAK, "traffic": None,
+                     "kernel": "k_fill", "kernel_ms": fill_ms},
+        "result": {"integral": r.integral, "sigma": math.sqrt(r.sigma2), "chi2_dof": r.chi2_dof},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, int(args.cpu_evals), args.cpu_iters)
+    print(json.dumps(out), flush=True)
+    v.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,275 @@
+"""ctypes binding of libvegas_hip.so (include/vegas.h).
+
+Argument marshalling only: every step of the iteration runs in the HIP
+kernels of the library.  PyTorch supplies device memory (the workspace
+tensor) and the stream.  There is no fallback: if the library is missing,
+importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("VEGAS_HIP_LIB") or os.path.join(_HERE, "libvegas_hip.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+                      "or `python paper_2408_09229_amd/build.py`")
+
+_lib = C.CDLL(LIB_PATH)
+
+VEGAS_OK, VEGAS_EINVAL, VEGAS_ENOMEM, VEGAS_EDEVICE, VEGAS_ESTATE, VEGAS_ENONFINITE, VEGAS_EUNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6
+PREC_FP64, PREC_FP32 = 0, 1
+ACC_FP64, ACC_KAHAN, ACC_ORDERED = 0, 1, 2
+
+
+class vegas_config(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_intervals", C.c_int32), ("n_eval", C.c_int64),
+                ("n_strat", C.c_int32), ("n_min", C.c_int32), ("alpha", C.c_double),
+                ("beta", C.c_double), ("seed", C.c_uint64), ("instance", C.c_uint32),
+                ("precision", C.c_int32), ("accum", C.c_int32), ("adapt_map", C.c_int32),
+                ("adapt_strat", C.c_int32), ("max_iter", C.c_int32)]
+
+
+class vegas_integrand(C.Structure):
+    _fields_ = [("family", C.c_int32), ("n_params", C.c_int32),
+                ("params", C.POINTER(C.c_double)), ("lo", C.POINTER(C.c_double)),
+                ("hi", C.POINTER(C.c_double))]
+
+
+class vegas_estimate(C.Structure):
+    _fields_ = [("integral", C.c_double), ("sigma2", C.c_double), ("chi2_dof", C.c_double),
+                ("n_iter_combined", C.c_int32), ("n_iter_total", C.c_int32),
+                ("n_eval_total", C.c_int64), ("n_nonfinite", C.c_int64)]
+
+
+class vegas_info(C.Structure):
+    _fields_ = [("n_strat", C.c_int64), ("n_cubes", C.c_int64), ("n_rest", C.c_int64),
+                ("tile", C.c_int32), ("n_tiles", C.c_int32), ("n_workgroups", C.c_int32),
+                ("lds_hist", C.c_int32), ("workspace_bytes", C.c_size_t)]
+
+
+_vp = C.c_void_p
+_st = C.c_int
+_DECL = {
+    "vegas_workspace_size": (_st, [C.POINTER(vegas_config), C.POINTER(vegas_integrand), C.POINTER(C.c_size_t)]),
+    "vegas_create": (_st, [C.POINTER(vegas_config), C.POINTER(vegas_integrand), _vp, C.c_size_t, _vp,
+                           C.POINTER(_vp)]),
+    "vegas_adapt": (_st, [_vp, C.c_int32]),
+    "vegas_integrate": (_st, [_vp, C.c_int32]),
+    "vegas_result": (_st, [_vp, C.POINTER(vegas_estimate)]),
+    "vegas_destroy": (None, [_vp]),
+    "vegas_get_info": (_st, [_vp, C.POINTER(vegas_info)]),
+    "vegas_get_map": (_st, [_vp, _vp]),
+    "vegas_set_map": (_st, [_vp, _vp]),
+    "vegas_get_nh": (_st, [_vp, _vp]),
+    "vegas_set_nh": (_st, [_vp, _vp]),
+    "vegas_get_accumulators": (_st, [_vp, _vp, _vp, _vp]),
+    "vegas_set_accumulators": (_st, [_vp, _vp, _vp, _vp]),
+    "vegas_update": (_st, [_vp]),
+    "vegas_get_iterations": (_st, [_vp, _vp, _vp, C.c_int32, C.POINTER(C.c_int32)]),
+    "vegas_get_state": (_st, [_vp, _vp, C.POINTER(C.c_size_t)]),
+    "vegas_set_state": (_st, [_vp, _vp, C.c_size_t]),
+    "vegas_sample_probe": (_st, [_vp, C.c_uint32, C.c_uint64, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "vegas_set_timing": (_st, [_vp, C.c_int32]),
+    "vegas_get_timing": (_st, [_vp, _vp, C.POINTER(C.c_int32)]),
+    "vegas_status_string": (C.c_char_p, [_st]),
+    "vegas_last_error": (C.c_char_p, []),
+}
+for _name, (_res, _args) in _DECL.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+    globals()[_name] = _fn
+
+EXPORTED = tuple(_DECL)
+
+
+class VegasError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        msg = _lib.vegas_last_error().decode()
+        super().__init__(f"{what}: {_lib.vegas_status_string(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def check(status: int, what: str, allow=()):
+    if status != VEGAS_OK and status not in allow:
+        raise VegasError(status, what)
+    return status
+
+
+def _dptr(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def make_config(dim, n_intervals, n_eval, *, n_strat=0, n_min=2, alpha=0.5, beta=0.75, seed=0,
+                instance=0, precision="f64", accum="fp64", adapt_map=True, adapt_strat=True,
+                max_iter=0) -> vegas_config:
+    return vegas_config(dim, n_intervals, n_eval, n_strat, n_min, alpha, beta, seed, instance,
+                        PREC_FP64 if precision == "f64" else PREC_FP32,
+                        {"fp64": ACC_FP64, "kahan": ACC_KAHAN, "ordered": ACC_ORDERED}[accum],
+                        int(adapt_map), int(adapt_strat), max_iter)
+
+
+class _Integrand:
+    """Keeps the numpy arrays behind a vegas_integrand alive."""
+
+    def __init__(self, family, params, lo=None, hi=None):
+        self.params = np.ascontiguousarray(params, dtype=np.float64)
+        self.lo = None if lo is None else np.ascontiguousarray(lo, dtype=np.float64)
+        self.hi = None if hi is None else np.ascontiguousarray(hi, dtype=np.float64)
+        dp = C.POINTER(C.c_double)
+        self.s = vegas_integrand(family, self.params.size, self.params.ctypes.data_as(dp),
+                                 None if self.lo is None else self.lo.ctypes.data_as(dp),
+                                 None if self.hi is None else self.hi.ctypes.data_as(dp))
+
+
+def workspace_size(cfg: vegas_config, family, params, lo=None, hi=None) -> int:
+    it = _Integrand(family, params, lo, hi)
+    n = C.c_size_t()
+    check(vegas_workspace_size(C.byref(cfg), C.byref(it.s), C.byref(n)), "vegas_workspace_size")
+    return n.value
+
+
+class Vegas:
+    """One VEGAS+ problem on the current HIP device.
+
+    ``Vegas(cfg, family, params)`` allocates the workspace as a torch uint8
+    tensor and runs on torch's current stream (or ``stream``).
+    """
+
+    def __init__(self, cfg: vegas_config, family: int, params, lo=None, hi=None, *, stream=None,
+                 device=None):
+        import torch
+        self.cfg = cfg
+        self._it = _Integrand(family, params, lo, hi)
+        n = C.c_size_t()
+        check(vegas_workspace_size(C.byref(cfg), C.byref(self._it.s), C.byref(n)), "vegas_workspace_size")
+        self.device = torch.device(device or "cuda")
+        self.ws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        check(vegas_create(C.byref(cfg), C.byref(self._it.s), C.c_void_p(self.ws.data_ptr()), n.value,
+                           C.c_void_p(self.stream.cuda_stream), C.byref(h)), "vegas_create")
+        self.h = h
+        self.info = vegas_info()
+        check(vegas_get_info(self.h, C.byref(self.info)), "vegas_get_info")
+
+    def close(self):
+        if getattr(self, "h", None):
+            vegas_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    # -- the iteration ----------------------------------------------------
+    def adapt(self, n: int):
+        check(vegas_adapt(self.h, n), "vegas_adapt")
+
+    def integrate(self, n: int):
+        check(vegas_integrate(self.h, n), "vegas_integrate")
+
+    def result(self, allow_nonfinite=False) -> vegas_estimate:
+        r = vegas_estimate()
+        check(vegas_result(self.h, C.byref(r)), "vegas_result",
+              allow=(VEGAS_ENONFINITE,) if allow_nonfinite else ())
+        return r
+
+    def update(self):
+        check(vegas_update(self.h), "vegas_update")
+
+    # -- hooks --------------------------------------------------------------
+    @property
+    def dim(self):
+        return self.cfg.dim
+
+    @property
+    def n_g(self):
+        return self.cfg.n_intervals
+
+    def get_map(self):
+        g = np.zeros((self.dim, self.n_g + 1))
+        check(vegas_get_map(self.h, _dptr(g)), "vegas_get_map")
+        return g
+
+    def set_map(self, g):
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        check(vegas_set_map(self.h, _dptr(g)), "vegas_set_map")
+
+    def get_nh(self):
+        nh = np.zeros(self.info.n_cubes, np.uint32)
+        check(vegas_get_nh(self.h, _dptr(nh)), "vegas_get_nh")
+        return nh
+
+    def set_nh(self, nh):
+        nh = np.ascontiguousarray(nh, dtype=np.uint32)
+        check(vegas_set_nh(self.h, _dptr(nh)), "vegas_set_nh")
+
+    def get_accumulators(self):
+        H = np.zeros((self.dim, self.n_g))
+        Cn = np.zeros((self.dim, self.n_g))
+        v = np.zeros(self.info.n_cubes)
+        check(vegas_get_accumulators(self.h, _dptr(H), _dptr(Cn), _dptr(v)), "vegas_get_accumulators")
+        return H, Cn, v
+
+    def set_accumulators(self, H, Cn, v):
+        H = np.ascontiguousarray(H, dtype=np.float64)
+        Cn = np.ascontiguousarray(Cn, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        check(vegas_set_accumulators(self.h, _dptr(H), _dptr(Cn), _dptr(v)), "vegas_set_accumulators")
+
+    def get_iterations(self):
+        n = C.c_int32()
+        cap = self.cfg.max_iter or 4096
+        I = np.zeros(cap)
+        s2 = np.zeros(cap)
+        check(vegas_get_iterations(self.h, _dptr(I), _dptr(s2), cap, C.byref(n)), "vegas_get_iterations")
+        return I[:n.value].copy(), s2[:n.value].copy()
+
+    def get_state(self) -> bytes:
+        n = C.c_size_t()
+        check(vegas_get_state(self.h, None, C.byref(n)), "vegas_get_state")
+        buf = (C.c_char * n.value)()
+        check(vegas_get_state(self.h, buf, C.byref(n)), "vegas_get_state")
+        return bytes(buf)
+
+    def set_state(self, b: bytes):
+        buf = (C.c_char * len(b)).from_buffer_copy(b)
+        check(vegas_set_state(self.h, buf, len(b)), "vegas_set_state")
+
+    def set_timing(self, on: bool):
+        check(vegas_set_timing(self.h, int(on)), "vegas_set_timing")
+
+    def get_timing(self):
+        """(ms per phase [fill, fixup+estimate, allocation, map], iterations)."""
+        ms = np.zeros(4)
+        n = C.c_int32()
+        check(vegas_get_timing(self.h, _dptr(ms), C.byref(n)), "vegas_get_timing")
+        return ms, n.value
+
+    def probe(self, t: int, k0: int, n: int):
+        """Per-sample path for samples k0..k0+n-1 of iteration t (torch tensors)."""
+        import torch
+        D = self.dim
+        dev = self.device
+        out = dict(cube=torch.empty(n, dtype=torch.int32, device=dev),
+                   bins=torch.empty(n * D, dtype=torch.int32, device=dev),
+                   delta=torch.empty(n * D, dtype=torch.float64, device=dev),
+                   x=torch.empty(n * D, dtype=torch.float64, device=dev),
+                   jac=torch.empty(n, dtype=torch.float64, device=dev),
+                   f=torch.empty(n, dtype=torch.float64, device=dev))
+        p = {k: C.c_void_p(v.data_ptr()) for k, v in out.items()}
+        check(vegas_sample_probe(self.h, t, k0, n, p["cube"], p["bins"], p["delta"], p["x"], p["jac"], p["f"]),
+              "vegas_sample_probe")
+        self.stream.synchronize()
+        res = {k: v.cpu().numpy() for k, v in out.items()}
+        res["cube"] = res["cube"].view(np.uint32)
+        res["bins"] = res["bins"].view(np.uint32).reshape(n, D)
+        res["delta"] = res["delta"].reshape(n, D)
+        res["x"] = res["x"].reshape(n, D)
+        return res

@@ -1,0 +1,881 @@
+// C ABI of the VEGAS+ iteration library (include/vegas.h).
+//
+// Host orchestration of Alg. 1: per iteration the fill (Alg. 2), the cube
+// fix-up and the fixed-order estimate, the allocation update (Eq. 7) and the
+// map refinement, all launched on the caller's stream.  The only host work
+// is validation, workspace carving, and the Eq. 8-9 combination of the
+// per-iteration estimates when a result is requested.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/vegas.h"
+#include "common.hpp"
+#include "launch.hpp"
+
+using namespace vg;
+
+namespace {
+
+thread_local std::string g_err;
+
+vegas_status fail(vegas_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(VEGAS_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+constexpr int kMaxWG = 512;            // histogram slots reserved in the workspace
+constexpr size_t kLdsLimit = 160 * 1024;
+constexpr int kMaxNg = 4096;
+
+// Problem geometry derived from a validated config (no HIP call).
+struct Geometry {
+    int D, ng, n_min, family, n_params;
+    uint32_t n_eval;
+    uint32_t nst;
+    uint32_t n_cubes;
+    uint64_t R;
+    uint32_t magic;
+    int shift;
+    int per_lane, tile, n_tiles;
+    int lds_hist_ok;
+    int n_aux;
+};
+
+// largest m with m^D <= lim, without overflow
+bool pow_at_most(uint64_t m, int D, uint64_t lim, uint64_t* out)
+{
+    uint64_t v = 1;
+    for (int d = 0; d < D; ++d) {
+        if (m != 0 && v > lim / m) return false;
+        v *= m;
+    }
+    if (v > lim) return false;
+    if (out) *out = v;
+    return true;
+}
+
+int family_params(int fam, int D, const vegas_integrand* f)
+{
+    switch (fam) {
+    case VEGAS_GAUSS_DIAG:
+        if (f->n_params < 3 || !f->params) return -1;
+        return 3 + (int)f->params[2];
+    case VEGAS_GENZ_PPEAK:
+    case VEGAS_GENZ_GAUSS: return 1 + 2 * D;
+    case VEGAS_GAUSS_CORR: return 3;
+    case VEGAS_LINEAR:
+    case VEGAS_ROOS:
+    case VEGAS_CONST:
+    case VEGAS_COSINE: return 1;
+    default: return -1;
+    }
+}
+
+vegas_status geometry(const vegas_config* c, const vegas_integrand* f, Geometry* g)
+{
+    if (!c || !f) return fail(VEGAS_EINVAL, "null config or integrand");
+    if (c->dim < 1 || c->dim > kMaxDim) return fail(VEGAS_EINVAL, "dim must be 1..%d", kMaxDim);
+    if (c->n_intervals < 1 || c->n_intervals > kMaxNg)
+        return fail(VEGAS_EINVAL, "n_intervals must be 1..%d", kMaxNg);
+    if (c->n_eval < 2 || c->n_eval >= (int64_t)UINT32_MAX) return fail(VEGAS_EINVAL, "n_eval must be in [2, 2^32-1)");
+    if (c->n_min < 2) return fail(VEGAS_EINVAL, "n_min must be >= 2");
+    if (!(c->alpha >= 0.0) || !std::isfinite(c->alpha)) return fail(VEGAS_EINVAL, "alpha must be finite and >= 0");
+    if (!(c->beta >= 0.0) || !std::isfinite(c->beta)) return fail(VEGAS_EINVAL, "beta must be finite and >= 0");
+    if (c->precision != VEGAS_PREC_FP64 && c->precision != VEGAS_PREC_FP32)
+        return fail(VEGAS_EINVAL, "unknown precision %d", c->precision);
+    if (c->accum != VEGAS_ACC_FP64) return fail(VEGAS_EUNSUPPORTED, "accumulation mode %d not available", c->accum);
+    if (c->instance >= (1u << 24)) return fail(VEGAS_EINVAL, "instance must be < 2^24");
+    if (c->max_iter < 0) return fail(VEGAS_EINVAL, "max_iter must be >= 0");
+    const int np = family_params(f->family, c->dim, f);
+    if (np < 0) return fail(VEGAS_EINVAL, "unknown integrand family %d or bad parameters", f->family);
+    if (f->n_params != np || (np > 0 && !f->params))
+        return fail(VEGAS_EINVAL, "family %d expects %d parameters, got %d", f->family, np, f->n_params);
+    for (int i = 0; i < np; ++i)
+        if (!std::isfinite(f->params[i])) return fail(VEGAS_EINVAL, "parameter %d is not finite", i);
+    for (int d = 0; d < c->dim; ++d) {
+        const double lo = f->lo ? f->lo[d] : 0.0, hi = f->hi ? f->hi[d] : 1.0;
+        if (!std::isfinite(lo) || !std::isfinite(hi) || !(lo < hi)) return fail(VEGAS_EINVAL, "bad box on axis %d", d);
+    }
+    if (f->family == VEGAS_GAUSS_DIAG && !(f->params[1] > 0.0)) return fail(VEGAS_EINVAL, "GAUSS_DIAG needs s > 0");
+    if (f->family == VEGAS_GAUSS_CORR) {
+        const double s = f->params[1], rho = f->params[2];
+        if (!(s > 0.0) || !(rho < 1.0) || !(1.0 + (c->dim - 1) * rho > 0.0))
+            return fail(VEGAS_EINVAL, "GAUSS_CORR covariance not positive definite");
+    }
+
+    g->D = c->dim;
+    g->ng = c->n_intervals;
+    g->n_min = c->n_min;
+    g->family = f->family;
+    g->n_params = np;
+    g->n_eval = (uint32_t)c->n_eval;
+    uint64_t m;
+    if (c->n_strat > 0) {
+        m = (uint64_t)c->n_strat;
+    } else {
+        m = 1;
+        while (pow_at_most(m + 1, c->dim, (uint64_t)c->n_eval / 4, nullptr)) ++m;
+    }
+    uint64_t nc = 0;
+    for (;;) {
+        if (pow_at_most(m, c->dim, (uint64_t)INT32_MAX - 1, &nc) && (uint64_t)c->n_min * nc <= (uint64_t)c->n_eval)
+            break;
+        if (c->n_strat > 0 || m == 1) return fail(VEGAS_EINVAL, "n_eval cannot give n_min samples to every hypercube");
+        --m;
+    }
+    if (m >= (1u << 20)) return fail(VEGAS_EINVAL, "strata per axis must be < 2^20");
+    if (m * (uint64_t)g->ng >= (1ull << 31)) return fail(VEGAS_EINVAL, "n_strat * n_intervals must be < 2^31");
+    g->nst = (uint32_t)m;
+    g->n_cubes = (uint32_t)nc;
+    g->R = (uint64_t)c->n_eval - (uint64_t)c->n_min * nc;
+    if (m == 1) {
+        g->magic = 0;
+        g->shift = -1;
+    } else {
+        int l = 0;
+        while ((1ull << l) < m) ++l;
+        const unsigned __int128 num = (unsigned __int128)1 << (31 + l);
+        g->magic = (uint32_t)((num + m - 1) / m);
+        g->shift = l - 1;
+    }
+    // samples per lane: long enough runs for large budgets, enough tiles to
+    // keep every CU busy for small ones
+    const uint64_t ne = g->n_eval;
+    g->per_lane = ne >= (uint64_t)256 * kLanesPerTile * 8 * 8 ? 8 : (ne >= (uint64_t)256 * kLanesPerTile * 4 * 2 ? 4 : 1);
+    g->tile = kLanesPerTile * g->per_lane;
+    g->n_tiles = (int)((ne + g->tile - 1) / g->tile);
+    const bool fp64 = c->precision == VEGAS_PREC_FP64;
+    g->lds_hist_ok = fill_lds_bytes(g->D, g->ng, fp64, 1, g->tile) <= kLdsLimit;
+    if (!g->lds_hist_ok && fill_lds_bytes(g->D, g->ng, fp64, 0, g->tile) > kLdsLimit)
+        return fail(VEGAS_EUNSUPPORTED, "map of %d x %d intervals does not fit in LDS", g->D, g->ng);
+    if ((size_t)3 * (g->ng + 1) * 8 > kLdsLimit) return fail(VEGAS_EUNSUPPORTED, "n_intervals too large for the map update");
+    g->n_aux = std::max(f->family == VEGAS_GAUSS_DIAG ? (int)f->params[2] : 2 * g->D, 1);
+    return VEGAS_OK;
+}
+
+// Workspace carving: offsets of every device array (256-byte aligned).
+struct Plan {
+    size_t prm, lo, hi, aux_d, aux_f, grid64, grid32, start[2], tfirst[2], v, wg_part, wg_comp, side, fix_part,
+        histH, histC, Hsum, Csum, counters, bsum, boff, iter, total;
+};
+
+Plan plan(const Geometry& g, int max_iter)
+{
+    Plan p;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = (o + bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    const size_t nb = (size_t)g.D * g.ng;
+    const size_t row = (size_t)g.D * (g.ng + 1);
+    const size_t nblk = (g.n_cubes + kAllocPerBlock - 1) / kAllocPerBlock;
+    p.prm = take(sizeof(double) * g.n_params);
+    p.lo = take(sizeof(double) * g.D);
+    p.hi = take(sizeof(double) * g.D);
+    p.aux_d = take(sizeof(double) * g.n_aux);
+    p.aux_f = take(sizeof(float) * g.n_aux);
+    p.grid64 = take(sizeof(double) * row);
+    p.grid32 = take(sizeof(float) * row);
+    for (int b = 0; b < 2; ++b) {
+        p.start[b] = take(sizeof(uint32_t) * ((size_t)g.n_cubes + 1));
+        p.tfirst[b] = take(sizeof(uint32_t) * ((size_t)g.n_tiles + 1));
+    }
+    p.v = take(sizeof(double) * g.n_cubes);
+    p.wg_part = take(sizeof(double) * 2 * kMaxWG);
+    p.wg_comp = take(sizeof(float) * 4 * kMaxWG);
+    p.side = take(sizeof(TileSide) * g.n_tiles);
+    p.fix_part = take(sizeof(double) * 2 * g.n_tiles);
+    const size_t slots = g.lds_hist_ok ? kMaxWG : 1;
+    p.histH = take(sizeof(double) * nb * slots);
+    p.histC = take(sizeof(uint32_t) * nb * slots);
+    p.Hsum = take(sizeof(double) * nb);
+    p.Csum = take(sizeof(double) * nb);
+    p.counters = take(sizeof(unsigned long long) * 8);   // vmax[2], qmax[2], nonfinite
+    p.bsum = take(sizeof(unsigned long long) * nblk);
+    p.boff = take(sizeof(unsigned long long) * (nblk + 1));
+    p.iter = take(sizeof(double) * 2 * (size_t)max_iter);
+    p.total = o;
+    return p;
+}
+
+}  // namespace
+
+struct vegas_ctx {
+    vegas_config cfg;
+    Geometry g;
+    Plan p;
+    std::vector<double> params, lo, hi;
+    hipStream_t stream;
+    unsigned char* ws;
+    int n_wg;
+    int cur;
+    int max_iter;
+    int n_run;
+    std::vector<uint8_t> combined;     // per iteration: 1 = integrate
+    int slots_last;                    // histogram slots written by the last fill
+    bool have_prev;                    // previous estimate valid (FP32 histogram scale)
+    bool timing;
+    std::vector<hipEvent_t> events;    // 5 per timed iteration
+
+    ~vegas_ctx()
+    {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    }
+    hipError_t mark()
+    {
+        if (!timing) return hipSuccess;
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        events.push_back(e);
+        return hipEventRecord(e, stream);
+    }
+
+    template <typename T>
+    T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+    unsigned long long* vmax(int t) const { return at<unsigned long long>(p.counters) + (t & 1); }
+    unsigned long long* qmax(int t) const { return at<unsigned long long>(p.counters) + 2 + (t & 1); }
+    unsigned long long* nonfinite() const { return at<unsigned long long>(p.counters) + 4; }
+};
+
+namespace {
+
+SampleConst sample_const(const vegas_ctx* c)
+{
+    SampleConst s;
+    s.D = c->g.D;
+    s.ng = (uint32_t)c->g.ng;
+    s.nst = c->g.nst;
+    s.nst_magic = c->g.magic;
+    s.nst_shift = c->g.shift;
+    s.n_eval = c->g.n_eval;
+    s.n_cubes = c->g.n_cubes;
+    s.key0 = (uint32_t)c->cfg.seed;
+    s.key1 = (uint32_t)(c->cfg.seed >> 32);
+    s.ctr3 = c->cfg.instance << 8;
+    s.family = c->g.family;
+    s.n_params = c->g.n_params;
+    s.prm = c->at<double>(c->p.prm);
+    s.aux_d = c->at<double>(c->p.aux_d);
+    s.aux_f = c->at<float>(c->p.aux_f);
+    return s;
+}
+
+AllocArgs alloc_args(vegas_ctx* c, int t, int uniform)
+{
+    AllocArgs a;
+    a.n_cubes = c->g.n_cubes;
+    a.n_min = (uint32_t)c->g.n_min;
+    a.R = c->g.R;
+    a.n_eval = c->g.n_eval;
+    a.beta = c->cfg.beta;
+    a.uniform = uniform;
+    a.tile = c->g.tile;
+    a.n_tiles = c->g.n_tiles;
+    a.per_block = kAllocPerBlock;
+    a.v = c->at<double>(c->p.v);
+    a.vmax = c->vmax(t);
+    a.qmax_buf = nullptr;
+    a.bsum = c->at<unsigned long long>(c->p.bsum);
+    a.boff = c->at<unsigned long long>(c->p.boff);
+    a.start = c->at<uint32_t>(c->p.start[1 - c->cur]);
+    a.tile_first = c->at<uint32_t>(c->p.tfirst[1 - c->cur]);
+    return a;
+}
+
+// allocation then map refinement from the accumulators of "slot set" t
+vegas_status run_update(vegas_ctx* c, int t, int n_slots, bool timed)
+{
+    const bool adapt_strat = c->cfg.adapt_strat && c->cfg.beta > 0.0;
+    AllocArgs aa = alloc_args(c, t, adapt_strat ? 0 : 1);
+    HIPCHK(launch_alloc(aa, c->qmax(t), c->stream));
+    c->cur = 1 - c->cur;
+    if (timed) HIPCHK(c->mark());
+    MapArgs m;
+    m.D = c->g.D;
+    m.ng = c->g.ng;
+    m.n_slots = n_slots;
+    m.alpha = c->cfg.adapt_map ? c->cfg.alpha : 0.0;
+    m.hist_H = c->at<double>(c->p.histH);
+    m.hist_C = c->at<uint32_t>(c->p.histC);
+    m.grid64 = c->at<double>(c->p.grid64);
+    m.grid32 = c->at<float>(c->p.grid32);
+    m.Hsum = c->at<double>(c->p.Hsum);
+    m.Csum = c->at<double>(c->p.Csum);
+    HIPCHK(launch_map_update(m, c->stream));
+    if (timed) HIPCHK(c->mark());
+    return VEGAS_OK;
+}
+
+vegas_status run_iteration(vegas_ctx* c, bool integrate)
+{
+    if (c->n_run >= c->max_iter) return fail(VEGAS_ESTATE, "iteration log full (max_iter = %d)", c->max_iter);
+    const int t = c->n_run;
+    const bool fp64 = c->cfg.precision == VEGAS_PREC_FP64;
+    // global-atomic histograms when LDS cannot hold them, and for the first
+    // FP32 iteration (no estimate yet to scale (J f)^2 into FP32 range)
+    const int lds_hist = c->g.lds_hist_ok && (fp64 || c->have_prev) ? 1 : 0;
+    const int nb = c->g.D * c->g.ng;
+    HIPCHK(launch_reset(c->vmax(t), 1, c->stream));
+    HIPCHK(launch_reset(c->qmax(t), 1, c->stream));
+    if (!lds_hist) {
+        HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histH), nb, c->stream));
+        HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histC), (nb + 1) / 2, c->stream));
+    }
+    FillArgs a;
+    a.sc = sample_const(c);
+    a.t = (uint32_t)t;
+    a.tile = c->g.tile;
+    a.per_lane = c->g.per_lane;
+    a.n_tiles = c->g.n_tiles;
+    a.lds_hist = lds_hist;
+    a.flush_every = std::max(1, 65535 / c->g.tile);
+    a.accum = c->cfg.accum;
+    a.grid = fp64 ? (const void*)c->at<double>(c->p.grid64) : (const void*)c->at<float>(c->p.grid32);
+    a.start = c->at<uint32_t>(c->p.start[c->cur]);
+    a.tile_first = c->at<uint32_t>(c->p.tfirst[c->cur]);
+    a.v_out = c->at<double>(c->p.v);
+    a.wg_part = c->at<double>(c->p.wg_part);
+    a.wg_comp = c->at<float>(c->p.wg_comp);
+    a.side = c->at<TileSide>(c->p.side);
+    a.hist_H = c->at<double>(c->p.histH);
+    a.hist_C = c->at<uint32_t>(c->p.histC);
+    a.vmax = c->vmax(t);
+    a.nonfinite = c->nonfinite();
+    a.prev_iter = c->have_prev ? c->at<double>(c->p.iter) + 2 * (t - 1) : nullptr;
+    const size_t lds = fill_lds_bytes(c->g.D, c->g.ng, fp64, lds_hist, c->g.tile);
+    HIPCHK(c->mark());
+    HIPCHK(launch_fill(a, fp64, c->n_wg, lds, c->stream));
+    HIPCHK(c->mark());
+    FixupArgs fx;
+    fx.n_tiles = c->g.n_tiles;
+    fx.side = a.side;
+    fx.v_out = a.v_out;
+    fx.fix_part = c->at<double>(c->p.fix_part);
+    fx.vmax = a.vmax;
+    HIPCHK(launch_fixup(fx, c->stream));
+    FinalArgs fa;
+    fa.n_wg = c->n_wg;
+    fa.n_tiles = c->g.n_tiles;
+    fa.n_cubes = (double)c->g.n_cubes;
+    fa.wg_part = a.wg_part;
+    fa.fix_part = fx.fix_part;
+    fa.iter_out = c->at<double>(c->p.iter) + 2 * t;
+    fa.accum = c->cfg.accum;
+    fa.wg_comp = a.wg_comp;
+    HIPCHK(launch_final(fa, c->stream));
+    HIPCHK(c->mark());
+    const vegas_status s = run_update(c, t, lds_hist ? c->n_wg : 1, true);
+    if (s != VEGAS_OK) return s;
+    c->n_run = t + 1;
+    c->combined.push_back(integrate ? 1 : 0);
+    c->have_prev = true;
+    return VEGAS_OK;
+}
+
+void combine(const std::vector<double>& I, const std::vector<double>& s2, double* Ib, double* s2b, double* chi)
+{
+    // Eq. 8-9; iterations with sigma^2 = 0 are exact and decide the result
+    const size_t n = I.size();
+    int nz = 0;
+    double zs = 0.0;
+    for (size_t t = 0; t < n; ++t)
+        if (s2[t] == 0.0) {
+            ++nz;
+            zs += I[t];
+        }
+    if (n == 0) {
+        *Ib = 0.0;
+        *s2b = INFINITY;
+        *chi = 0.0;
+        return;
+    }
+    if (nz > 0) {
+        *Ib = zs / nz;
+        *s2b = 0.0;
+        *chi = 0.0;
+        return;
+    }
+    double w = 0.0, wi = 0.0;
+    for (size_t t = 0; t < n; ++t) {
+        w += 1.0 / s2[t];
+        wi += I[t] / s2[t];
+    }
+    const double m = wi / w;
+    double c2 = 0.0;
+    for (size_t t = 0; t < n; ++t) {
+        const double u = I[t] - m;
+        c2 += u * u / s2[t];
+    }
+    *Ib = m;
+    *s2b = 1.0 / w;
+    *chi = n > 1 ? c2 / (double)(n - 1) : 0.0;
+}
+
+// host-side start / tile table from an injected allocation
+vegas_status upload_nh(vegas_ctx* c, const uint32_t* nh, int buf)
+{
+    const uint32_t nc = c->g.n_cubes;
+    std::vector<uint32_t> st(nc + 1), tf(c->g.n_tiles + 1);
+    uint64_t run = 0;
+    for (uint32_t h = 0; h < nc; ++h) {
+        if (nh[h] < (uint32_t)c->g.n_min) return fail(VEGAS_EINVAL, "n_h[%u] = %u below n_min", h, nh[h]);
+        st[h] = (uint32_t)run;
+        run += nh[h];
+    }
+    if (run != c->g.n_eval) return fail(VEGAS_EINVAL, "n_h sums to %llu, not n_eval", (unsigned long long)run);
+    st[nc] = c->g.n_eval;
+    uint32_t h = 0;
+    for (int j = 0; j < c->g.n_tiles; ++j) {
+        const uint64_t k = (uint64_t)j * c->g.tile;
+        while (st[h + 1] <= k) ++h;
+        tf[j] = h;
+    }
+    tf[c->g.n_tiles] = nc;
+    HIPCHK(hipMemcpyAsync(c->at<uint32_t>(c->p.start[buf]), st.data(), sizeof(uint32_t) * st.size(),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->at<uint32_t>(c->p.tfirst[buf]), tf.data(), sizeof(uint32_t) * tf.size(),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return VEGAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vegas_status_string(vegas_status s)
+{
+    switch (s) {
+    case VEGAS_OK: return "ok";
+    case VEGAS_EINVAL: return "invalid argument";
+    case VEGAS_ENOMEM: return "workspace too small";
+    case VEGAS_EDEVICE: return "HIP error";
+    case VEGAS_ESTATE: return "invalid state";
+    case VEGAS_ENONFINITE: return "non-finite integrand values";
+    case VEGAS_EUNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* vegas_last_error(void) { return g_err.c_str(); }
+
+vegas_status vegas_workspace_size(const vegas_config* cfg, const vegas_integrand* f, size_t* bytes)
+{
+    Geometry g;
+    const vegas_status s = geometry(cfg, f, &g);
+    if (s != VEGAS_OK) return s;
+    if (!bytes) return fail(VEGAS_EINVAL, "null bytes");
+    *bytes = plan(g, cfg->max_iter > 0 ? cfg->max_iter : 4096).total;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_create(const vegas_config* cfg, const vegas_integrand* f, void* d_workspace, size_t bytes,
+                          void* hip_stream, vegas_ctx** out)
+{
+    if (!out) return fail(VEGAS_EINVAL, "null out");
+    *out = nullptr;
+    Geometry g;
+    vegas_status s = geometry(cfg, f, &g);
+    if (s != VEGAS_OK) return s;
+    const int max_iter = cfg->max_iter > 0 ? cfg->max_iter : 4096;
+    const Plan p = plan(g, max_iter);
+    if (!d_workspace) return fail(VEGAS_EINVAL, "null workspace");
+    if (((uintptr_t)d_workspace & 255u) != 0) return fail(VEGAS_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < p.total) return fail(VEGAS_ENOMEM, "workspace has %zu bytes, needs %zu", bytes, p.total);
+    int dev = 0, cus = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    vegas_ctx* c = new vegas_ctx();
+    c->cfg = *cfg;
+    c->cfg.max_iter = max_iter;
+    c->g = g;
+    c->p = p;
+    c->params.assign(f->params, f->params + g.n_params);
+    c->lo.resize(g.D);
+    c->hi.resize(g.D);
+    for (int d = 0; d < g.D; ++d) {
+        c->lo[d] = f->lo ? f->lo[d] : 0.0;
+        c->hi[d] = f->hi ? f->hi[d] : 1.0;
+    }
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (unsigned char*)d_workspace;
+    c->n_wg = std::max(1, std::min({cus, kMaxWG, g.n_tiles}));
+    c->cur = 0;
+    c->max_iter = max_iter;
+    c->n_run = 0;
+    c->slots_last = 0;
+    c->have_prev = false;
+    c->timing = false;
+    auto cleanup = [&](vegas_status st) {
+        delete c;
+        return st;
+    };
+#define HIPCHK_C(expr)                                                                     \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return cleanup(fail(VEGAS_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_))); \
+    } while (0)
+    HIPCHK_C(hipMemcpyAsync(c->at<double>(p.prm), c->params.data(), sizeof(double) * g.n_params,
+                            hipMemcpyHostToDevice, c->stream));
+    HIPCHK_C(hipMemcpyAsync(c->at<double>(p.lo), c->lo.data(), sizeof(double) * g.D, hipMemcpyHostToDevice,
+                            c->stream));
+    HIPCHK_C(hipMemcpyAsync(c->at<double>(p.hi), c->hi.data(), sizeof(double) * g.D, hipMemcpyHostToDevice,
+                            c->stream));
+    HIPCHK_C(launch_reset(c->at<unsigned long long>(p.counters), 8, c->stream));
+    PrepArgs pa;
+    pa.family = g.family;
+    pa.D = g.D;
+    pa.n_params = g.n_params;
+    pa.prm = c->at<double>(p.prm);
+    pa.lo = c->at<double>(p.lo);
+    pa.hi = c->at<double>(p.hi);
+    pa.ng = g.ng;
+    pa.aux_d = c->at<double>(p.aux_d);
+    pa.aux_f = c->at<float>(p.aux_f);
+    pa.grid64 = c->at<double>(p.grid64);
+    pa.grid32 = c->at<float>(p.grid32);
+    HIPCHK_C(launch_prep(pa, c->stream));
+    // uniform initial allocation into buffer 0
+    c->cur = 1;
+    AllocArgs aa = alloc_args(c, 0, 1);
+    HIPCHK_C(launch_alloc(aa, c->qmax(0), c->stream));
+    c->cur = 0;
+#undef HIPCHK_C
+    *out = c;
+    return VEGAS_OK;
+}
+
+void vegas_destroy(vegas_ctx* ctx)
+{
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    delete ctx;
+}
+
+vegas_status vegas_adapt(vegas_ctx* ctx, int32_t n_iter)
+{
+    if (!ctx || n_iter < 0) return fail(VEGAS_EINVAL, "bad arguments");
+    for (int i = 0; i < n_iter; ++i) {
+        const vegas_status s = run_iteration(ctx, false);
+        if (s != VEGAS_OK) return s;
+    }
+    return VEGAS_OK;
+}
+
+vegas_status vegas_integrate(vegas_ctx* ctx, int32_t n_iter)
+{
+    if (!ctx || n_iter < 0) return fail(VEGAS_EINVAL, "bad arguments");
+    for (int i = 0; i < n_iter; ++i) {
+        const vegas_status s = run_iteration(ctx, true);
+        if (s != VEGAS_OK) return s;
+    }
+    return VEGAS_OK;
+}
+
+vegas_status vegas_get_iterations(vegas_ctx* c, double* I, double* sigma2, int32_t cap, int32_t* n)
+{
+    if (!c || !n) return fail(VEGAS_EINVAL, "bad arguments");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *n = c->n_run;
+    const int m = std::min(cap, c->n_run);
+    if (m > 0) {
+        std::vector<double> buf(2 * (size_t)m);
+        HIPCHK(hipMemcpy(buf.data(), c->at<double>(c->p.iter), sizeof(double) * buf.size(), hipMemcpyDeviceToHost));
+        for (int t = 0; t < m; ++t) {
+            if (I) I[t] = buf[2 * t];
+            if (sigma2) sigma2[t] = buf[2 * t + 1];
+        }
+    }
+    return VEGAS_OK;
+}
+
+vegas_status vegas_result(vegas_ctx* c, vegas_estimate* out)
+{
+    if (!c || !out) return fail(VEGAS_EINVAL, "bad arguments");
+    std::vector<double> I(c->n_run), s2(c->n_run);
+    int32_t n = 0;
+    const vegas_status s = vegas_get_iterations(c, I.data(), s2.data(), c->n_run, &n);
+    if (s != VEGAS_OK) return s;
+    std::vector<double> Ic, s2c;
+    for (int t = 0; t < n; ++t)
+        if (c->combined[t]) {
+            Ic.push_back(I[t]);
+            s2c.push_back(s2[t]);
+        }
+    combine(Ic, s2c, &out->integral, &out->sigma2, &out->chi2_dof);
+    out->n_iter_combined = (int32_t)Ic.size();
+    out->n_iter_total = c->n_run;
+    out->n_eval_total = (int64_t)c->n_run * (int64_t)c->g.n_eval;
+    unsigned long long bad = 0;
+    HIPCHK(hipMemcpy(&bad, c->nonfinite(), sizeof bad, hipMemcpyDeviceToHost));
+    out->n_nonfinite = (int64_t)bad;
+    if (bad) return fail(VEGAS_ENONFINITE, "%llu sample weights were NaN/Inf and counted as 0", bad);
+    return VEGAS_OK;
+}
+
+vegas_status vegas_get_info(const vegas_ctx* c, vegas_info* out)
+{
+    if (!c || !out) return fail(VEGAS_EINVAL, "bad arguments");
+    out->n_strat = c->g.nst;
+    out->n_cubes = c->g.n_cubes;
+    out->n_rest = (int64_t)c->g.R;
+    out->tile = c->g.tile;
+    out->n_tiles = c->g.n_tiles;
+    out->n_workgroups = c->n_wg;
+    out->lds_hist = c->g.lds_hist_ok;
+    out->workspace_bytes = c->p.total;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_get_map(vegas_ctx* c, double* grid)
+{
+    if (!c || !grid) return fail(VEGAS_EINVAL, "bad arguments");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(grid, c->at<double>(c->p.grid64), sizeof(double) * c->g.D * (c->g.ng + 1),
+                     hipMemcpyDeviceToHost));
+    return VEGAS_OK;
+}
+
+vegas_status vegas_set_map(vegas_ctx* c, const double* grid)
+{
+    if (!c || !grid) return fail(VEGAS_EINVAL, "bad arguments");
+    const int row = c->g.ng + 1;
+    for (int d = 0; d < c->g.D; ++d)
+        for (int i = 0; i < row; ++i) {
+            const double v = grid[d * row + i];
+            if (!std::isfinite(v) || (i > 0 && v < grid[d * row + i - 1]))
+                return fail(VEGAS_EINVAL, "grid axis %d is not finite and non-decreasing", d);
+        }
+    const size_t n = (size_t)c->g.D * row;
+    HIPCHK(hipMemcpyAsync(c->at<double>(c->p.grid64), grid, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(launch_grid32(c->at<double>(c->p.grid64), c->at<float>(c->p.grid32), (int)n, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return VEGAS_OK;
+}
+
+vegas_status vegas_get_nh(vegas_ctx* c, uint32_t* nh)
+{
+    if (!c || !nh) return fail(VEGAS_EINVAL, "bad arguments");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::vector<uint32_t> st(c->g.n_cubes + 1);
+    HIPCHK(hipMemcpy(st.data(), c->at<uint32_t>(c->p.start[c->cur]), sizeof(uint32_t) * st.size(),
+                     hipMemcpyDeviceToHost));
+    for (uint32_t h = 0; h < c->g.n_cubes; ++h) nh[h] = st[h + 1] - st[h];
+    return VEGAS_OK;
+}
+
+vegas_status vegas_set_nh(vegas_ctx* c, const uint32_t* nh)
+{
+    if (!c || !nh) return fail(VEGAS_EINVAL, "bad arguments");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return upload_nh(c, nh, c->cur);
+}
+
+vegas_status vegas_get_accumulators(vegas_ctx* c, double* H, double* C, double* v)
+{
+    if (!c) return fail(VEGAS_EINVAL, "bad arguments");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const size_t nb = (size_t)c->g.D * c->g.ng;
+    if (H) HIPCHK(hipMemcpy(H, c->at<double>(c->p.Hsum), sizeof(double) * nb, hipMemcpyDeviceToHost));
+    if (C) HIPCHK(hipMemcpy(C, c->at<double>(c->p.Csum), sizeof(double) * nb, hipMemcpyDeviceToHost));
+    if (v) HIPCHK(hipMemcpy(v, c->at<double>(c->p.v), sizeof(double) * c->g.n_cubes, hipMemcpyDeviceToHost));
+    return VEGAS_OK;
+}
+
+vegas_status vegas_set_accumulators(vegas_ctx* c, const double* H, const double* C, const double* v)
+{
+    if (!c || !H || !C || !v) return fail(VEGAS_EINVAL, "bad arguments");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const size_t nb = (size_t)c->g.D * c->g.ng;
+    std::vector<uint32_t> cu(nb);
+    for (size_t i = 0; i < nb; ++i) {
+        if (!(C[i] >= 0.0) || C[i] != std::floor(C[i]) || C[i] > 4294967295.0)
+            return fail(VEGAS_EINVAL, "counts must be non-negative integers");
+        cu[i] = (uint32_t)C[i];
+    }
+    double vmax = 0.0;
+    for (uint32_t h = 0; h < c->g.n_cubes; ++h) {
+        if (!(v[h] >= 0.0) || !std::isfinite(v[h])) return fail(VEGAS_EINVAL, "v must be finite and >= 0");
+        vmax = std::max(vmax, v[h]);
+    }
+    unsigned long long bits;
+    std::memcpy(&bits, &vmax, sizeof bits);
+    const unsigned long long zero = 0;
+    const int t = c->n_run;
+    HIPCHK(hipMemcpy(c->at<double>(c->p.histH), H, sizeof(double) * nb, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->at<uint32_t>(c->p.histC), cu.data(), sizeof(uint32_t) * nb, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->at<double>(c->p.v), v, sizeof(double) * c->g.n_cubes, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->vmax(t), &bits, sizeof bits, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->qmax(t), &zero, sizeof zero, hipMemcpyHostToDevice));
+    c->slots_last = -1;      // injected: a single slot
+    return VEGAS_OK;
+}
+
+vegas_status vegas_update(vegas_ctx* c)
+{
+    if (!c) return fail(VEGAS_EINVAL, "bad arguments");
+    if (c->slots_last != -1) return fail(VEGAS_ESTATE, "vegas_update needs injected accumulators");
+    const vegas_status s = run_update(c, c->n_run, 1, false);
+    c->slots_last = 0;
+    return s;
+}
+
+vegas_status vegas_set_timing(vegas_ctx* c, int32_t on)
+{
+    if (!c) return fail(VEGAS_EINVAL, "bad arguments");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+    c->events.clear();
+    c->timing = on != 0;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_get_timing(vegas_ctx* c, double* ms, int32_t* n_iter)
+{
+    if (!c || !ms) return fail(VEGAS_EINVAL, "bad arguments");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < 4; ++i) ms[i] = 0.0;
+    // iterations record 5 marks; a lone vegas_update records 2 (alloc, map)
+    size_t i = 0;
+    int n = 0;
+    while (i + 5 <= c->events.size()) {
+        for (int p = 0; p < 4; ++p) {
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, c->events[i + p], c->events[i + p + 1]));
+            ms[p] += t;
+        }
+        i += 5;
+        ++n;
+    }
+    if (n_iter) *n_iter = n;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_sample_probe(vegas_ctx* c, uint32_t t, uint64_t k0, int64_t n, uint32_t* d_cube,
+                                uint32_t* d_bins, double* d_delta, double* d_x, double* d_jac, double* d_f)
+{
+    if (!c || n < 0) return fail(VEGAS_EINVAL, "bad arguments");
+    if (n == 0) return VEGAS_OK;
+    if (k0 + (uint64_t)n > c->g.n_eval) return fail(VEGAS_EINVAL, "sample range beyond n_eval");
+    const bool fp64 = c->cfg.precision == VEGAS_PREC_FP64;
+    ProbeArgs a;
+    a.sc = sample_const(c);
+    a.t = t;
+    a.k0 = k0;
+    a.n = n;
+    a.grid = fp64 ? (const void*)c->at<double>(c->p.grid64) : (const void*)c->at<float>(c->p.grid32);
+    a.start = c->at<uint32_t>(c->p.start[c->cur]);
+    a.cube = d_cube;
+    a.bins = d_bins;
+    a.delta = d_delta;
+    a.x = d_x;
+    a.jac = d_jac;
+    a.f = d_f;
+    HIPCHK(launch_probe(a, fp64, c->stream));
+    return VEGAS_OK;
+}
+
+// state image: header, grid, n_h, iteration log, flags, counters
+struct StateHeader {
+    uint64_t magic;
+    int32_t D, ng;
+    uint32_t n_cubes, n_eval;
+    int32_t n_run, have_prev;
+    uint64_t nonfinite;
+};
+static const uint64_t kStateMagic = 0x5645474153535431ull;   // "VEGASST1"
+
+vegas_status vegas_get_state(vegas_ctx* c, void* buf, size_t* bytes)
+{
+    if (!c || !bytes) return fail(VEGAS_EINVAL, "bad arguments");
+    const size_t ng = (size_t)c->g.D * (c->g.ng + 1);
+    const size_t need = sizeof(StateHeader) + sizeof(double) * ng + sizeof(uint32_t) * c->g.n_cubes +
+                        sizeof(double) * 2 * c->n_run + c->n_run;
+    if (!buf) {
+        *bytes = need;
+        return VEGAS_OK;
+    }
+    if (*bytes < need) return fail(VEGAS_ENOMEM, "state buffer needs %zu bytes", need);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    unsigned char* o = (unsigned char*)buf;
+    StateHeader h;
+    h.magic = kStateMagic;
+    h.D = c->g.D;
+    h.ng = c->g.ng;
+    h.n_cubes = c->g.n_cubes;
+    h.n_eval = c->g.n_eval;
+    h.n_run = c->n_run;
+    h.have_prev = c->have_prev;
+    unsigned long long bad = 0;
+    HIPCHK(hipMemcpy(&bad, c->nonfinite(), sizeof bad, hipMemcpyDeviceToHost));
+    h.nonfinite = bad;
+    std::memcpy(o, &h, sizeof h);
+    o += sizeof h;
+    HIPCHK(hipMemcpy(o, c->at<double>(c->p.grid64), sizeof(double) * ng, hipMemcpyDeviceToHost));
+    o += sizeof(double) * ng;
+    const vegas_status s = vegas_get_nh(c, (uint32_t*)o);
+    if (s != VEGAS_OK) return s;
+    o += sizeof(uint32_t) * c->g.n_cubes;
+    if (c->n_run > 0)
+        HIPCHK(hipMemcpy(o, c->at<double>(c->p.iter), sizeof(double) * 2 * c->n_run, hipMemcpyDeviceToHost));
+    o += sizeof(double) * 2 * c->n_run;
+    std::memcpy(o, c->combined.data(), c->n_run);
+    *bytes = need;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_set_state(vegas_ctx* c, const void* buf, size_t bytes)
+{
+    if (!c || !buf || bytes < sizeof(StateHeader)) return fail(VEGAS_EINVAL, "bad arguments");
+    StateHeader h;
+    std::memcpy(&h, buf, sizeof h);
+    if (h.magic != kStateMagic || h.D != c->g.D || h.ng != c->g.ng || h.n_cubes != c->g.n_cubes ||
+        h.n_eval != c->g.n_eval)
+        return fail(VEGAS_EINVAL, "state image does not match this context");
+    const size_t ng = (size_t)c->g.D * (c->g.ng + 1);
+    const size_t need = sizeof(StateHeader) + sizeof(double) * ng + sizeof(uint32_t) * c->g.n_cubes +
+                        sizeof(double) * 2 * h.n_run + h.n_run;
+    if (bytes < need || h.n_run > c->max_iter) return fail(VEGAS_EINVAL, "state image truncated or too long");
+    const unsigned char* o = (const unsigned char*)buf + sizeof h;
+    vegas_status s = vegas_set_map(c, (const double*)o);
+    if (s != VEGAS_OK) return s;
+    o += sizeof(double) * ng;
+    s = vegas_set_nh(c, (const uint32_t*)o);
+    if (s != VEGAS_OK) return s;
+    o += sizeof(uint32_t) * c->g.n_cubes;
+    if (h.n_run > 0)
+        HIPCHK(hipMemcpy(c->at<double>(c->p.iter), o, sizeof(double) * 2 * h.n_run, hipMemcpyHostToDevice));
+    o += sizeof(double) * 2 * h.n_run;
+    c->combined.assign(o, o + h.n_run);
+    c->n_run = h.n_run;
+    c->have_prev = h.have_prev != 0;
+    unsigned long long bad = h.nonfinite;
+    HIPCHK(hipMemcpy(c->nonfinite(), &bad, sizeof bad, hipMemcpyHostToDevice));
+    return VEGAS_OK;
+}
+
+}  // extern "C"

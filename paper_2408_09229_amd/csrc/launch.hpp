@@ -1,0 +1,57 @@
+// Host-side launchers of the VEGAS+ kernels (defined in fill.hip and
+// update.hip, called by the C ABI in api.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "layout.hpp"
+
+namespace vg {
+
+struct ProbeArgs {
+    SampleConst sc;
+    uint32_t t;
+    uint64_t k0;
+    int64_t n;
+    const void* grid;           // FP64 or FP32 grid per precision
+    const uint32_t* start;      // [N_c+1]
+    uint32_t* cube;
+    uint32_t* bins;
+    double* delta;
+    double* x;
+    double* jac;
+    double* f;
+};
+
+struct PrepArgs {
+    int32_t family;
+    int32_t D;
+    int32_t n_params;
+    const double* prm;
+    const double* lo;
+    const double* hi;
+    int32_t ng;
+    double* aux_d;
+    float* aux_f;
+    double* grid64;             // non-null: write the uniform grid
+    float* grid32;
+};
+
+hipError_t launch_fill(const FillArgs& a, bool fp64, int n_wg, size_t lds, hipStream_t st);
+hipError_t launch_fixup(const FixupArgs& a, hipStream_t st);
+hipError_t launch_final(const FinalArgs& a, hipStream_t st);
+hipError_t launch_probe(const ProbeArgs& a, bool fp64, hipStream_t st);
+size_t fill_lds_bytes(int D, int ng, bool fp64, int lds_hist, int tile);
+
+hipError_t launch_prep(const PrepArgs& a, hipStream_t st);
+hipError_t launch_alloc(const AllocArgs& a, unsigned long long* qmax_bits, hipStream_t st);
+hipError_t launch_map_update(const MapArgs& a, hipStream_t st);
+hipError_t launch_reset(unsigned long long* p, int n, hipStream_t st);
+hipError_t launch_grid32(const double* g64, float* g32, int n, hipStream_t st);
+
+constexpr int kAllocThreads = 1024;
+constexpr int kAllocPerThread = 4;
+constexpr int kAllocPerBlock = kAllocThreads * kAllocPerThread;
+
+}  // namespace vg

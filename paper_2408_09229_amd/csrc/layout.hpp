@@ -1,0 +1,123 @@
+// Launch arguments and workspace records shared by the host library and the
+// kernels.  Plain structs only (passed by value to kernels).
+#pragma once
+#include <stdint.h>
+
+namespace vg {
+
+constexpr int kMaxDim = 16;
+constexpr int kFillThreads = 1024;     // one persistent workgroup per CU
+constexpr int kLanesPerTile = kFillThreads;
+
+// Partial moments of one hypercube's weights over a contiguous run of its
+// samples: count, mean and sum of squared deviations (Chan et al. 1983 form,
+// so that runs merge without cancellation).
+struct Partial {
+    uint32_t h;
+    uint32_t n;
+    double mean;
+    double m2;
+};
+
+// Per-tile side record for cubes that cross tile boundaries.
+enum : uint32_t { kHasHead = 1u, kHasTail = 2u, kSpan = 4u };
+struct TileSide {
+    Partial head;   // the tile's first cube, when it began in an earlier tile
+    Partial tail;   // the tile's last cube, when it continues into a later tile
+    uint32_t flags;
+    uint32_t pad;
+};
+
+// Problem constants used by the per-sample path.
+struct SampleConst {
+    int32_t D;
+    uint32_t ng;
+    uint32_t nst;
+    uint32_t nst_magic;
+    int32_t nst_shift;         // -1: N_st = 1
+    uint32_t n_eval;
+    uint32_t n_cubes;
+    uint32_t key0, key1;       // Philox key = seed
+    uint32_t ctr3;             // instance << 8 (counter word 3 high bits)
+    int32_t family;
+    int32_t n_params;
+    const double* prm;         // raw parameters (device)
+    const double* aux_d;       // derived constants, FP64 (device)
+    const float* aux_f;        // derived constants, FP32 (device)
+};
+
+struct FillArgs {
+    SampleConst sc;
+    uint32_t t;                 // iteration index (counter word 2)
+    int32_t tile;               // samples per tile = kLanesPerTile * per_lane
+    int32_t per_lane;
+    int32_t n_tiles;
+    int32_t lds_hist;           // 1: LDS histograms, 0: global FP64 atomics
+    int32_t flush_every;        // tiles between LDS count flushes (u16 packing)
+    int32_t accum;              // VEGAS_ACC_*
+    const void* grid;           // [D][N_g+1], FP64 or FP32 per precision
+    const uint32_t* start;      // [N_c+1] first sample of each cube
+    const uint32_t* tile_first; // [n_tiles+1] cube holding each tile's first sample
+    double* v_out;              // [N_c] unbiased per-cube variance
+    double* wg_part;            // [n_wg][2]: sum of cube means, sum of v/n
+    float* wg_comp;             // [n_wg][4]: Kahan mode partial (sum, comp) x2
+    TileSide* side;             // [n_tiles]
+    double* hist_H;             // LDS mode: [n_wg][D*N_g]; global mode: [D*N_g]
+    uint32_t* hist_C;           // same layout
+    unsigned long long* vmax;   // max v_h as FP64 bits (v >= 0)
+    unsigned long long* nonfinite;
+    const double* prev_iter;    // (I, s2) of the previous iteration or null
+};
+
+struct FixupArgs {
+    int32_t n_tiles;
+    const TileSide* side;
+    double* v_out;
+    double* fix_part;           // [n_tiles][2]
+    unsigned long long* vmax;
+};
+
+struct FinalArgs {
+    int32_t n_wg;
+    int32_t n_tiles;
+    double n_cubes;
+    const double* wg_part;
+    const double* fix_part;
+    double* iter_out;           // (I_t, sigma_t^2)
+    int32_t accum;
+    const float* wg_comp;
+};
+
+struct AllocArgs {
+    uint32_t n_cubes;
+    uint32_t n_min;
+    uint64_t R;                 // N_ev - n_min N_c
+    uint32_t n_eval;
+    double beta;
+    int32_t uniform;            // 1: Q_h = 1
+    int32_t tile;
+    int32_t n_tiles;
+    int32_t per_block;          // cubes per block
+    const double* v;
+    const unsigned long long* vmax;   // max v (monotone beta)
+    double* qmax_buf;           // [n_blocks] block maxima of q (general beta)
+    unsigned long long* bsum;   // [n_blocks] block sums of Q
+    unsigned long long* boff;   // [n_blocks] exclusive offsets; boff[n_blocks] = T
+    uint32_t* start;            // [N_c+1] out
+    uint32_t* tile_first;       // [n_tiles+1] out
+};
+
+struct MapArgs {
+    int32_t D;
+    int32_t ng;
+    int32_t n_slots;            // histogram slots to reduce (n_wg, or 1)
+    double alpha;
+    const double* hist_H;
+    const uint32_t* hist_C;
+    double* grid64;             // [D][N_g+1] in/out
+    float* grid32;              // [D][N_g+1] out (FP32 copy)
+    double* Hsum;               // [D][N_g] reduced histogram (kept for inspection)
+    double* Csum;
+};
+
+}  // namespace vg

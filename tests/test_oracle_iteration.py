@@ -115,7 +115,7 @@ def test_gauss_prod_4d_full_run_closed_form(orc):
     assert r.s2_t[-1] < 0.05 * r.s2_t[0]
 
 
-@pytest.mark.parametrize("w", vi.small_cases(), ids=lambda w: w.name)
+@pytest.mark.parametrize("w", vi.closed_form_cases(), ids=lambda w: w.name)
 def test_small_cases_closed_form(orc, w):
     r = orc.run(w.dim, w.n_g, w.n_eval, w.family, w.params, n_iter=w.n_iter, seed=w.seed)
     exact = cf.exact(w)

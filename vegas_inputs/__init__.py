@@ -160,3 +160,21 @@ def small_cases() -> List[Workload]:
         gauss3_8d().with_(name="gauss3_8d_small", n_eval=70_001, n_g=64, n_iter=2,
                           precision="f64"),
     ]
+
+
+def closed_form_cases() -> List[Workload]:
+    """Small runs VEGAS+ resolves at their budget (checked across seeds): the
+    combined estimate must land within 3 sigma of the closed form."""
+    s = 0.15
+    return [
+        gauss3_8d().with_(name="gauss3_8d_wide", params=gauss_diag_params(normal_peak(s, 8) / 3.0, s,
+                                                                         [0.33, 0.5, 0.67]),
+                          n_eval=200_000, n_g=64, n_iter=5, precision="f64"),
+        Workload("gauss3_4d", 4, GAUSS_DIAG, gauss_diag_params(normal_peak(0.05, 4) / 3.0, 0.05,
+                                                               [0.33, 0.5, 0.67]),
+                 n_g=64, n_eval=100_000, n_iter=5),
+        gauss_prod_4d().with_(name="gauss4_small", n_eval=20_011, n_g=16, n_iter=5),
+        Workload("ppeak3", 3, GENZ_PPEAK, np.array([1.0, 6.0, 9.0, 12.0, 0.3, 0.6, 0.45]), n_g=32,
+                 n_eval=50_003, n_iter=5),
+        Workload("roos5", 5, ROOS, np.array([1.0]), n_g=8, n_eval=30_001, n_iter=5),
+    ]
