@@ -334,9 +334,8 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
     if (c->n_run >= c->max_iter) return fail(VEGAS_ESTATE, "iteration log full (max_iter = %d)", c->max_iter);
     const int t = c->n_run;
     const bool fp64 = c->cfg.precision == VEGAS_PREC_FP64;
-    // global-atomic histograms when LDS cannot hold them, and for the first
-    // FP32 iteration (no estimate yet to scale (J f)^2 into FP32 range)
-    const int lds_hist = c->g.lds_hist_ok && (fp64 || c->have_prev) ? 1 : 0;
+    // LDS-privatised histograms unless LDS cannot hold them
+    const int lds_hist = c->g.lds_hist_ok ? 1 : 0;
     const int nb = c->g.D * c->g.ng;
     HIPCHK(launch_reset(c->vmax(t), 1, c->stream));
     HIPCHK(launch_reset(c->qmax(t), 1, c->stream));

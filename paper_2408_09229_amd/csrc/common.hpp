@@ -21,21 +21,46 @@ struct W4 {
     uint32_t v[4];
 };
 
+// Round keys k + r W (r = 0..9) of one launch.  Kept in vector registers:
+// as scalars the twenty of them do not fit beside the other uniform values
+// and the compiler spills them to VGPR lanes, paying a readlane per use.
+struct PhiloxKeys {
+    uint32_t k0[10], k1[10];
+};
+
+// VG: pin the keys in vector registers (when the kernel has VGPRs to spare).
+template <bool VG>
+__device__ __forceinline__ PhiloxKeys philox_keys(uint32_t key0, uint32_t key1)
+{
+    PhiloxKeys K;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t a = key0 + (uint32_t)r * 0x9E3779B9u;
+        const uint32_t b = key1 + (uint32_t)r * 0xBB67AE85u;
+        if constexpr (VG) {
+            asm volatile("v_mov_b32 %0, %1" : "=v"(K.k0[r]) : "s"(a));
+            asm volatile("v_mov_b32 %0, %1" : "=v"(K.k1[r]) : "s"(b));
+        } else {
+            K.k0[r] = a;
+            K.k1[r] = b;
+        }
+    }
+    return K;
+}
+
 __device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                       uint32_t k0, uint32_t k1)
+                                       const PhiloxKeys& K)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t a = (uint64_t)c0 * 0xD2511F53u;
         const uint64_t b = (uint64_t)c2 * 0xCD9E8D57u;
-        const uint32_t y0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
-        const uint32_t y2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        const uint32_t y0 = (uint32_t)(b >> 32) ^ c1 ^ K.k0[r];
+        const uint32_t y2 = (uint32_t)(a >> 32) ^ c3 ^ K.k1[r];
         c1 = (uint32_t)b;
         c3 = (uint32_t)a;
         c0 = y0;
         c2 = y2;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
     }
     W4 o;
     o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
@@ -64,36 +89,41 @@ __device__ __forceinline__ uint32_t div_magic(uint32_t q, uint32_t magic, int sh
 struct BinSplit {
     uint32_t bin;
     uint32_t c;       // q mod N_st
-    uint64_t b;       // low 33 bits of N_g (2r+1)
+    uint32_t p_lo;    // N_g (2r+1) = p_hi 2^32 + p_lo
+    uint32_t p_hi;
 };
 
 __device__ __forceinline__ BinSplit bin_split(uint32_t s, uint32_t r, uint32_t ng, uint32_t nst,
                                               uint32_t nst_magic, int nst_shift)
 {
-    const uint64_t P = (uint64_t)ng * ((uint64_t)r * 2u + 1u);
-    const uint32_t a = (uint32_t)(P >> 33);
+    // N_g (2r+1) = r (2 N_g) + N_g in one 32x32+64 multiply-add
+    const uint64_t P = (uint64_t)r * (2u * ng) + ng;
     BinSplit o;
-    o.b = P & ((1ull << 33) - 1u);
+    o.p_lo = (uint32_t)P;
+    o.p_hi = (uint32_t)(P >> 32);
+    const uint32_t a = o.p_hi >> 1;                 // floor(P / 2^33)
     const uint32_t q = ng * s + a;
     o.bin = div_magic(q, nst_magic, nst_shift);
     o.c = q - o.bin * nst;
     return o;
 }
 
-// delta = rho / (N_st 2^33) rounded once: rho 2^-33 is exact in FP64 when
-// rho < 2^53, and dividing the exact value by N_st rounds once.
+// delta = rho / (N_st 2^33) with rho = c 2^33 + (P mod 2^33), rounded once:
+// rho 2^-33 is exact in FP64 when rho < 2^53, and dividing the exact value by
+// N_st rounds once.
 __device__ __forceinline__ double delta_f64(const BinSplit& p, double nst_d)
 {
-    const double num = (double)p.c + (double)p.b * 0x1p-33;
+    const double b = (double)(p.p_hi & 1u) * 4294967296.0 + (double)p.p_lo;
+    const double num = (double)p.c + b * 0x1p-33;
     return num / nst_d;
 }
 
-// FP32 path: delta to float precision.  b >> 1 is the low 32 bits of
-// N_g r + floor(N_g/2); the half-ulp of the dropped bit is immaterial here.
+// FP32 path: delta to float precision from the top 32 of the 33 fractional
+// bits, (P mod 2^33) >> 1.
 __device__ __forceinline__ float delta_f32(const BinSplit& p, float inv_nst)
 {
-    const float frac = (float)(uint32_t)(p.b >> 1) * 0x1p-32f;
-    return ((float)p.c + frac) * inv_nst;
+    const uint32_t frac = __builtin_amdgcn_alignbit(p.p_hi, p.p_lo, 1);
+    return fmaf((float)frac, 0x1p-32f, (float)p.c) * inv_nst;
 }
 
 // ---------------------------------------------------------------------------

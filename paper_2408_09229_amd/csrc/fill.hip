@@ -17,9 +17,10 @@
 // Then w^2 and a count go to the per-axis histograms (LDS-privatised,
 // flushed per workgroup) and w to the running shifted sums of its cube.
 //
-// Per cube (Eq. 5-6): runs of a cube that cross lanes merge in LDS with
-// Chan's pairwise formula; runs that cross tiles go to a side record and a
-// fix-up kernel merges them in tile order.  Each finished cube yields its
+// Per cube (Eq. 5-6): runs of a cube that cross lanes merge with Chan's
+// pairwise formula in a segmented scan over wavefront shuffles, with one
+// carry per wave through LDS; runs that cross tiles go to a side record and
+// a fix-up kernel merges them in tile order.  Each finished cube yields its
 // mean m_h and unbiased variance v_h; the iteration estimate is
 // I = sum m_h / N_c and sigma^2 = sum v_h / (N_c^2 n_h), reduced in a fixed
 // order so that a run is reproducible.
@@ -61,6 +62,7 @@ template <typename R, int FAM, int MAXD>
 struct SamplePath {
     const SampleConst& sc;
     Fn<R, FAM> fn;
+    PhiloxKeys keys;
     R ngR;
     double nst_d;
     float inv_nst_f;
@@ -68,6 +70,7 @@ struct SamplePath {
     __device__ __forceinline__ explicit SamplePath(const SampleConst& c) : sc(c)
     {
         fn.setup(c);
+        keys = philox_keys<std::is_same<R, float>::value && MAXD <= 8>(c.key0, c.key1);
         ngR = (R)c.ng;
         nst_d = (double)c.nst;
         inv_nst_f = (float)(1.0 / (double)c.nst);
@@ -84,15 +87,22 @@ struct SamplePath {
         }
     }
 
+    // digits of h+1 from those of h; the carry reaches axis d once every
+    // N_st^d cubes, so the nested branches are rarely taken past axis 0
     __device__ __forceinline__ void next_digits(uint32_t (&s)[MAXD]) const
     {
-        bool carry = true;
-#pragma unroll
-        for (int d = 0; d < MAXD; ++d) {
-            if (carry) {
-                const uint32_t v = s[d] + 1u;
-                carry = (v == sc.nst);
-                s[d] = carry ? 0u : v;
+        next_digit_from<0>(s);
+    }
+    template <int d>
+    __device__ __forceinline__ void next_digit_from(uint32_t (&s)[MAXD]) const
+    {
+        if constexpr (d < MAXD) {
+            const uint32_t v = s[d] + 1u;
+            if (v == sc.nst) {
+                s[d] = 0u;
+                next_digit_from<d + 1>(s);
+            } else {
+                s[d] = v;
             }
         }
     }
@@ -109,7 +119,7 @@ struct SamplePath {
 #pragma unroll
         for (int b = 0; b < (MAXD + 3) / 4; ++b) {
             if (4 * b < sc.D) {
-                const W4 o = philox10(k, 0u, t, sc.ctr3 | (uint32_t)b, sc.key0, sc.key1);
+                const W4 o = philox10(k, 0u, t, sc.ctr3 | (uint32_t)b, keys);
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     if (4 * b + q < MAXD) wd[4 * b + q] = o.v[q];
@@ -144,35 +154,120 @@ struct SamplePath {
 };
 
 // ---------------------------------------------------------------------------
-// the fill kernel
+// runs of one cube: count, mean, sum of squared deviations
 // ---------------------------------------------------------------------------
-struct LdsPlan {
-    uint32_t grid_off, h_off, c_off, st_off, hp_off, tp_off, fl_off, misc_off, total;
+struct Run {
+    uint32_t n;
+    double mean;
+    double m2;
 };
 
-__host__ __device__ inline LdsPlan lds_plan(int D, int ng, int real_bytes, int lds_hist, int tile, int n_min)
+__device__ __forceinline__ Run run_empty()
+{
+    Run r;
+    r.n = 0;
+    r.mean = 0.0;
+    r.m2 = 0.0;
+    return r;
+}
+
+__device__ __forceinline__ Run run_merge(const Run& a, const Run& b)
+{
+    if (a.n == 0) return b;
+    if (b.n == 0) return a;
+    Run o;
+    o.n = a.n + b.n;
+    const double na = (double)a.n, nb = (double)b.n, n = (double)o.n;
+    const double dm = b.mean - a.mean;
+    o.mean = a.mean + dm * (nb / n);
+    o.m2 = a.m2 + b.m2 + (dm * dm) * (na * nb / n);
+    return o;
+}
+
+__device__ __forceinline__ Run run_shfl_up(const Run& r, int o)
+{
+    Run u;
+    u.n = __shfl_up(r.n, o, 64);
+    u.mean = __shfl_up(r.mean, o, 64);
+    u.m2 = __shfl_up(r.m2, o, 64);
+    return u;
+}
+
+// 1/n to double precision: hardware reciprocal plus one Newton step
+__device__ __forceinline__ double recip(double n)
+{
+    double y = __builtin_amdgcn_rcp(n);
+    y = fma(fma(-n, y, 1.0), y, y);
+    return fma(fma(-n, y, 1.0), y, y);
+}
+
+// shifted sums (c, S1 = sum (w - c), S2 = sum (w - c)^2) of n samples -> run
+__device__ __forceinline__ Run run_from_sums(uint32_t n, double c, double S1, double S2)
+{
+    Run r;
+    r.n = n;
+    const double inv = recip((double)n);
+    const double m1 = S1 * inv;
+    r.mean = c + m1;
+    r.m2 = fma(-S1, m1, S2);
+    return r;
+}
+
+// unbiased variance of a finished cube and its share v/n of sigma^2
+__device__ __forceinline__ void run_finish(const Run& r, double& v, double& v_over_n)
+{
+    const double dn = (double)r.n;
+    const double m2 = r.m2 > 0.0 ? r.m2 : 0.0;
+    v = m2 * recip(dn - 1.0);
+    v_over_n = v * recip(dn);
+}
+
+__device__ __forceinline__ Partial to_partial(const Run& r, uint32_t h)
+{
+    Partial p;
+    p.h = h;
+    p.n = r.n;
+    p.mean = r.mean;
+    p.m2 = r.m2;
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// the fill kernel
+// ---------------------------------------------------------------------------
+constexpr int kWaves = kFillThreads / 64;
+
+struct WaveRec {
+    Run s;            // scanned run at the wave's last lane
+    uint32_t tail;    // last lane ends in a cube that continues
+    uint32_t open;    // that run reaches back past the wave's first lane
+};
+
+struct LdsPlan {
+    uint32_t grid_off, h_off, c_off, st_off, wave_off, cin_off, side_off, red_off, total;
+};
+
+// LDS: map [D][N_g+1] in the sample path's precision; histogram weights
+// [D][N_g] in FP64 (the FP32 LDS atomic add is an order of magnitude slower
+// than the FP64 one on gfx950); counts as packed u16 pairs; the tile's cube
+// starts; per-wave carry records; the tile's side record; a reduction area.
+__host__ __device__ inline LdsPlan lds_plan(int D, int ng, int real_bytes, int lds_hist, int tile)
 {
     LdsPlan p;
     uint32_t o = 0;
     auto al = [](uint32_t v) { return (v + 15u) & ~15u; };
     p.grid_off = o; o = al(o + (uint32_t)(D * (ng + 1) * real_bytes));
     p.h_off = o;
-    if (lds_hist) o = al(o + (uint32_t)(D * ng * real_bytes));
+    if (lds_hist) o = al(o + (uint32_t)(D * ng * 8));
     p.c_off = o;
     if (lds_hist) o = al(o + (uint32_t)(((D * ng + 1) / 2) * 4));
-    p.st_off = o; o = al(o + (uint32_t)((tile / n_min + 4) * 4));
-    p.hp_off = o; o = al(o + (uint32_t)(kLanesPerTile * sizeof(Partial)));
-    p.tp_off = o; o = al(o + (uint32_t)(kLanesPerTile * sizeof(Partial)));
-    p.fl_off = o; o = al(o + (uint32_t)kLanesPerTile);
-    p.misc_off = o; o = al(o + 2 * sizeof(Partial) + 64);
+    p.st_off = o; o = al(o + (uint32_t)((tile / 2 + 4) * 4));
+    p.wave_off = o; o = al(o + (uint32_t)(kWaves * sizeof(WaveRec)));
+    p.cin_off = o; o = al(o + (uint32_t)(kWaves * sizeof(WaveRec)));
+    p.side_off = o; o = al(o + (uint32_t)(2 * sizeof(Partial) + 16));
+    p.red_off = o; o = al(o + (uint32_t)(kWaves * 3 * sizeof(double)));
     p.total = o;
     return p;
-}
-
-template <typename R>
-__device__ __forceinline__ void lds_fadd(R* p, R v)
-{
-    atomicAdd(p, v);
 }
 
 template <typename R, int FAM, int MAXD>
@@ -183,74 +278,36 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs a)
     const int D = sc.D;
     const uint32_t ng = sc.ng;
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
     const int S = a.per_lane;
-    const LdsPlan lp = lds_plan(D, (int)ng, (int)sizeof(R), a.lds_hist, a.tile, 2);
+    const LdsPlan lp = lds_plan(D, (int)ng, (int)sizeof(R), a.lds_hist, a.tile);
     R* gl = reinterpret_cast<R*>(smem + lp.grid_off);
-    R* hl = reinterpret_cast<R*>(smem + lp.h_off);
+    double* hl = reinterpret_cast<double*>(smem + lp.h_off);
     uint32_t* cl = reinterpret_cast<uint32_t*>(smem + lp.c_off);
     uint32_t* st = reinterpret_cast<uint32_t*>(smem + lp.st_off);
-    Partial* HP = reinterpret_cast<Partial*>(smem + lp.hp_off);
-    Partial* TP = reinterpret_cast<Partial*>(smem + lp.tp_off);
-    uint8_t* FL = smem + lp.fl_off;
-    Partial* tside = reinterpret_cast<Partial*>(smem + lp.misc_off);     // [0] head, [1] tail
-    uint32_t* tflags = reinterpret_cast<uint32_t*>(smem + lp.misc_off + 2 * sizeof(Partial));
+    WaveRec* wrec = reinterpret_cast<WaveRec*>(smem + lp.wave_off);
+    WaveRec* cin = reinterpret_cast<WaveRec*>(smem + lp.cin_off);     // open = tile-head chain
+    Partial* tside = reinterpret_cast<Partial*>(smem + lp.side_off);  // [0] head, [1] tail
+    uint32_t* tflags = reinterpret_cast<uint32_t*>(smem + lp.side_off + 2 * sizeof(Partial));
+    double* red = reinterpret_cast<double*>(smem + lp.red_off);
 
     const int nbins = D * (int)ng;
     const int nwords = (nbins + 1) / 2;
     const R* gsrc = reinterpret_cast<const R*>(a.grid);
     for (int i = tid; i < D * (int)(ng + 1); i += kFillThreads) gl[i] = gsrc[i];
     if (a.lds_hist) {
-        for (int i = tid; i < nbins; i += kFillThreads) hl[i] = (R)0;
+        for (int i = tid; i < nbins; i += kFillThreads) hl[i] = 0.0;
         for (int i = tid; i < nwords; i += kFillThreads) cl[i] = 0u;
-    }
-
-    // power-of-two scale for the FP32 histogram (keeps (J f)^2 in range)
-    R hs = (R)1;
-    double inv_hs2 = 1.0;
-    if (std::is_same<R, float>::value && a.prev_iter != nullptr) {
-        const double Ip = fabs(a.prev_iter[0]);
-        if (Ip > 0.0 && Ip < 1e300) {
-            int e = ilogb(Ip);
-            e = e < -60 ? -60 : (e > 60 ? 60 : e);
-            hs = (R)ldexp(1.0, -e);
-            inv_hs2 = ldexp(1.0, 2 * e);
-        }
     }
 
     SamplePath<R, FAM, MAXD> sp(sc);
     double accI = 0.0, accV = 0.0, vmax = 0.0;
     unsigned long long bad = 0;
-    const double* hslotH = nullptr;
-    (void)hslotH;
     double* slotH = a.lds_hist ? a.hist_H + (size_t)blockIdx.x * nbins : a.hist_H;
     uint32_t* slotC = a.lds_hist ? a.hist_C + (size_t)blockIdx.x * nbins : a.hist_C;
     bool first_flush = true;
     int since_flush = 0;
-
-    auto flush = [&]() {
-        // called by all threads between barriers
-        for (int wi = tid; wi < nwords; wi += kFillThreads) {
-            const uint32_t cw = cl[wi];
-            cl[wi] = 0u;
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int i = 2 * wi + q;
-                if (i < nbins) {
-                    const double hv = (double)hl[i] * inv_hs2;
-                    hl[i] = (R)0;
-                    const uint32_t cv = (cw >> (16 * q)) & 0xFFFFu;
-                    if (first_flush) {
-                        slotH[i] = hv;
-                        slotC[i] = cv;
-                    } else {
-                        slotH[i] += hv;
-                        slotC[i] += cv;
-                    }
-                }
-            }
-        }
-        first_flush = false;
-    };
 
     __syncthreads();
 
@@ -268,16 +325,20 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs a)
         const uint32_t k0 = t0 + (uint32_t)(tid * S);
         const uint32_t k1 = min(k0 + (uint32_t)S, t1);
         const int n_active = (int)((t1 - t0 + (uint32_t)S - 1u) / (uint32_t)S);
-        uint8_t fl = 0;
+        // per lane: the run of its first cube when that cube began earlier
+        // (head), and the run of its last cube when it continues (tail)
+        bool has_head = false, has_tail = false, span = false;
+        Run hrun = run_empty(), trun = run_empty();
+        uint32_t h_first = 0, h_last = 0;
         if (k0 < k1) {
-            // largest idx with st[idx] <= k0
-            int lo = 0, hi = nst_load - 1;
+            int lo = 0, hi = nst_load - 1;          // largest idx with st[idx] <= k0
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
                 if (st[mid] <= k0) lo = mid; else hi = mid;
             }
             int idx = lo;
             uint32_t h = h_lo + (uint32_t)idx;
+            h_first = h;
             uint32_t nxt = st[idx + 1];
             bool head = st[idx] < k0;
             uint32_t s[MAXD];
@@ -285,30 +346,23 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs a)
             uint32_t n = 0;
             double c = 0.0, S1 = 0.0, S2 = 0.0;
 
-            auto close_run = [&]() {
-                Partial p;
-                p.h = h;
-                p.n = n;
-                const double dn = (double)n;
-                p.mean = c + S1 / dn;
-                p.m2 = S2 - S1 * (S1 / dn);
-                if (head) {
-                    HP[tid] = p;
-                    fl |= (uint8_t)kHasHead;
-                } else {
-                    const double v = unbiased_var(p);
-                    a.v_out[h] = v;
-                    accI += p.mean;
-                    accV += v / dn;
-                    vmax = v > vmax ? v : vmax;
-                }
-            };
-
             for (int j = 0; j < S; ++j) {
                 const uint32_t k = k0 + (uint32_t)j;
                 if (k >= k1) break;
                 if (k == nxt) {
-                    close_run();
+                    // the current cube ends: shifted sums -> (mean, m2)
+                    const Run r = run_from_sums(n, c, S1, S2);
+                    if (head) {
+                        hrun = r;
+                        has_head = true;
+                    } else {
+                        double v, vn;
+                        run_finish(r, v, vn);
+                        a.v_out[h] = v;
+                        accI += r.mean;
+                        accV += vn;
+                        vmax = v > vmax ? v : vmax;
+                    }
                     ++idx;
                     ++h;
                     nxt = st[idx + 1];
@@ -325,20 +379,18 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs a)
                     w = (R)0;
                     ++bad;
                 }
+                const double wd = (double)w;
+                const double w2 = wd * wd;
                 if (a.lds_hist) {
-                    const R ws = w * hs;
-                    const R w2 = ws * ws;
 #pragma unroll
                     for (int d = 0; d < MAXD; ++d) {
                         if (d < D) {
                             const uint32_t bi = (uint32_t)d * ng + bins[d];
-                            lds_fadd(hl + bi, w2);
+                            atomicAdd(hl + bi, w2);
                             atomicAdd(cl + (bi >> 1), 1u << ((bi & 1u) << 4));
                         }
                     }
                 } else {
-                    const double wd = (double)w;
-                    const double w2 = wd * wd;
 #pragma unroll
                     for (int d = 0; d < MAXD; ++d) {
                         if (d < D) {
@@ -348,120 +400,194 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs a)
                         }
                     }
                 }
-                const double wd = (double)w;
                 if (n == 0) c = wd;
                 const double u = wd - c;
                 S1 += u;
                 S2 = fma(u, u, S2);
                 ++n;
             }
-            if (nxt > k1) {
-                Partial p;
-                p.h = h;
-                p.n = n;
-                const double dn = (double)n;
-                p.mean = c + S1 / dn;
-                p.m2 = S2 - S1 * (S1 / dn);
-                TP[tid] = p;
-                fl |= (uint8_t)(head ? (kHasTail | kSpan) : kHasTail);
+            h_last = h;
+            const Run r = run_from_sums(n, c, S1, S2);
+            if (nxt > k1) {                 // continues into the next lane
+                trun = r;
+                has_tail = true;
+                span = head;
+            } else if (head) {
+                hrun = r;
+                has_head = true;
             } else {
-                close_run();
-            }
-        }
-        FL[tid] = fl;
-        __syncthreads();
-
-        // ---- merge runs of cubes that cross lanes -------------------------
-        if ((fl & kHasTail) && !(fl & kSpan)) {
-            Partial cur = TP[tid];
-            int m = tid + 1;
-            for (;;) {
-                if (m >= n_active) {          // continues into the next tile
-                    tside[1] = cur;
-                    atomicOr(tflags, kHasTail);
-                    break;
-                }
-                const uint8_t fm = FL[m];
-                if (fm & kSpan) {
-                    cur = merge(cur, TP[m]);
-                    ++m;
-                    continue;
-                }
-                cur = merge(cur, HP[m]);
-                const double v = unbiased_var(cur);
-                a.v_out[cur.h] = v;
-                accI += cur.mean;
-                accV += v / (double)cur.n;
+                double v, vn;
+                run_finish(r, v, vn);
+                a.v_out[h] = v;
+                accI += r.mean;
+                accV += vn;
                 vmax = v > vmax ? v : vmax;
-                break;
             }
         }
-        if (tid == 0 && (fl & (kHasHead | kSpan))) {
-            // the tile's first cube began in an earlier tile
-            if (fl & kSpan) {
-                Partial cur = TP[0];
-                int m = 1;
-                uint32_t f2 = kHasHead;
-                for (;;) {
-                    if (m >= n_active) {
-                        f2 = kHasHead | kHasTail | kSpan;
-                        break;
+
+        // ---- runs that cross lanes: segmented scan inside the wavefront ---
+        // S_l = merge(S_{l-1}, tail_l) while lane l continues the cube of
+        // lane l-1 (span), else tail_l.  Hillis-Steele over shuffles, stopping
+        // as soon as every chain has reached its first lane.
+        Run sv = has_tail ? trun : run_empty();
+        int sf = (has_tail && span) ? 0 : 1;       // 1: a chain starts here
+        for (int o = 1; o < 64; o <<= 1) {
+            const Run u = run_shfl_up(sv, o);
+            const int fu = __shfl_up(sf, o, 64);
+            if (lane >= o && !sf) {
+                sv = run_merge(u, sv);
+                sf = fu;
+            }
+            if (__ballot(!sf && lane >= 2 * o) == 0ull) break;
+        }
+        if (lane == 63) {
+            wrec[wave].s = sv;
+            wrec[wave].tail = has_tail ? 1u : 0u;
+            wrec[wave].open = sf ? 0u : 1u;
+        }
+        const Run prev = run_shfl_up(sv, 1);
+        const int prev_f = __shfl_up(sf, 1, 64);
+        __syncthreads();
+        if (tid == 0) {
+            // carries between waves; the chain entering wave 0 is the tile's
+            // first cube, which began in an earlier tile
+            Run c = run_empty();
+            uint32_t th = 1u;
+            for (int w = 0; w < kWaves; ++w) {
+                cin[w].s = c;
+                cin[w].open = th;
+                const WaveRec& r = wrec[w];
+                if (r.tail) {
+                    if (r.open) {
+                        c = run_merge(c, r.s);
+                    } else {
+                        c = r.s;
+                        th = 0u;
                     }
-                    const uint8_t fm = FL[m];
-                    if (fm & kSpan) {
-                        cur = merge(cur, TP[m]);
-                        ++m;
-                        continue;
-                    }
-                    cur = merge(cur, HP[m]);
-                    break;
+                } else {
+                    c = run_empty();
+                    th = 0u;
                 }
-                tside[0] = cur;
-                atomicOr(tflags, f2);
+            }
+        }
+        __syncthreads();
+        if (has_head && !span) {
+            Run pre;
+            uint32_t th;
+            if (lane == 0 || !prev_f) {
+                pre = lane == 0 ? cin[wave].s : run_merge(cin[wave].s, prev);
+                th = cin[wave].open;
             } else {
-                tside[0] = HP[0];
+                pre = prev;
+                th = 0u;
+            }
+            const Run fin = run_merge(pre, hrun);
+            if (th) {
+                tside[0] = to_partial(fin, h_lo);
                 atomicOr(tflags, kHasHead);
+            } else {
+                double v, vn;
+                run_finish(fin, v, vn);
+                a.v_out[h_first] = v;
+                accI += fin.mean;
+                accV += vn;
+                vmax = v > vmax ? v : vmax;
+            }
+        }
+        if (tid == n_active - 1 && has_tail) {
+            Run t = sv;
+            uint32_t th = 0u;
+            if (!sf) {
+                t = run_merge(cin[wave].s, sv);
+                th = cin[wave].open;
+            }
+            if (th) {
+                tside[0] = to_partial(t, h_lo);
+                atomicOr(tflags, kHasHead | kHasTail | kSpan);
+            } else {
+                tside[1] = to_partial(t, h_last);
+                atomicOr(tflags, kHasTail);
             }
         }
         __syncthreads();
         if (tid == 0) {
-            TileSide ts;
-            ts.flags = *tflags;
-            ts.head = tside[0];
-            ts.tail = (ts.flags & kSpan) ? tside[0] : tside[1];
-            ts.pad = 0;
-            a.side[tile] = ts;
+            const uint32_t fl = *tflags;
+            TileSide* ts = a.side + tile;
+            ts->flags = fl;
+            ts->head = tside[0];
+            ts->tail = (fl & kSpan) ? tside[0] : tside[1];
         }
         if (a.lds_hist && ++since_flush >= a.flush_every) {
-            flush();
+            // weights and u16 counts of this workgroup into its slot
+            for (int wi = tid; wi < nwords; wi += kFillThreads) {
+                const uint32_t cw = cl[wi];
+                cl[wi] = 0u;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int i = 2 * wi + q;
+                    if (i < nbins) {
+                        const double hv = hl[i];
+                        hl[i] = 0.0;
+                        const uint32_t cv = (cw >> (16 * q)) & 0xFFFFu;
+                        if (first_flush) {
+                            slotH[i] = hv;
+                            slotC[i] = cv;
+                        } else {
+                            slotH[i] += hv;
+                            slotC[i] += cv;
+                        }
+                    }
+                }
+            }
+            first_flush = false;
             since_flush = 0;
         }
         __syncthreads();
     }
-    if (a.lds_hist) {
-        flush();
+    if (a.lds_hist && (since_flush > 0 || first_flush)) {
+        for (int wi = tid; wi < nwords; wi += kFillThreads) {
+            const uint32_t cw = cl[wi];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int i = 2 * wi + q;
+                if (i < nbins) {
+                    const double hv = hl[i];
+                    const uint32_t cv = (cw >> (16 * q)) & 0xFFFFu;
+                    if (first_flush) {
+                        slotH[i] = hv;
+                        slotC[i] = cv;
+                    } else {
+                        slotH[i] += hv;
+                        slotC[i] += cv;
+                    }
+                }
+            }
+        }
     }
 
     // ---- fixed-order workgroup reduction of the lane partials -------------
-    __syncthreads();
-    double* red = reinterpret_cast<double*>(smem + lp.hp_off);
-    red[tid] = accI;
-    red[kFillThreads + tid] = accV;
-    red[2 * kFillThreads + tid] = vmax;
-    __syncthreads();
-    for (int w = kFillThreads / 2; w > 0; w >>= 1) {
-        if (tid < w) {
-            red[tid] += red[tid + w];
-            red[kFillThreads + tid] += red[kFillThreads + tid + w];
-            const double o = red[2 * kFillThreads + tid + w];
-            if (o > red[2 * kFillThreads + tid]) red[2 * kFillThreads + tid] = o;
-        }
-        __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) {
+        accI += __shfl_down(accI, o, 64);
+        accV += __shfl_down(accV, o, 64);
+        const double m = __shfl_down(vmax, o, 64);
+        vmax = m > vmax ? m : vmax;
     }
+    if (lane == 0) {
+        red[3 * wave] = accI;
+        red[3 * wave + 1] = accV;
+        red[3 * wave + 2] = vmax;
+    }
+    __syncthreads();
     if (tid == 0) {
-        a.wg_part[2 * blockIdx.x] = red[0];
-        a.wg_part[2 * blockIdx.x + 1] = red[kFillThreads];
-        atomicMax(a.vmax, (unsigned long long)__double_as_longlong(red[2 * kFillThreads]));
+        double sI = 0.0, sV = 0.0, mx = 0.0;
+        for (int w = 0; w < kWaves; ++w) {
+            sI += red[3 * w];
+            sV += red[3 * w + 1];
+            mx = red[3 * w + 2] > mx ? red[3 * w + 2] : mx;
+        }
+        a.wg_part[2 * blockIdx.x] = sI;
+        a.wg_part[2 * blockIdx.x + 1] = sV;
+        atomicMax(a.vmax, (unsigned long long)__double_as_longlong(mx));
     }
     if (bad) atomicAdd(a.nonfinite, bad);
 }
@@ -644,7 +770,7 @@ hipError_t launch_final(const FinalArgs& a, hipStream_t st)
 
 size_t fill_lds_bytes(int D, int ng, bool fp64, int lds_hist, int tile)
 {
-    return lds_plan(D, ng, fp64 ? 8 : 4, lds_hist, tile, 2).total;
+    return lds_plan(D, ng, fp64 ? 8 : 4, lds_hist, tile).total;
 }
 
 }  // namespace vg
