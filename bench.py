@@ -66,6 +66,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-evals", type=float, default=1.5e7)
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the VEGAS+ path here "
@@ -126,6 +128,13 @@ def main():
                      "kernel": "k_fill", "kernel_ms": fill_ms},
         "result": {"integral": r.integral, "sigma": math.sqrt(r.sigma2), "chi2_dof": r.chi2_dof},
     }
+    if args.copy_calibration:
+        src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")   # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, int(args.cpu_evals), args.cpu_iters)
     print(json.dumps(out), flush=True)

@@ -350,7 +350,6 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
     a.per_lane = c->g.per_lane;
     a.n_tiles = c->g.n_tiles;
     a.lds_hist = lds_hist;
-    a.flush_every = std::max(1, 65535 / c->g.tile);
     a.accum = c->cfg.accum;
     a.grid = fp64 ? (const void*)c->at<double>(c->p.grid64) : (const void*)c->at<float>(c->p.grid32);
     a.start = c->at<uint32_t>(c->p.start[c->cur]);
@@ -363,7 +362,6 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
     a.hist_C = c->at<uint32_t>(c->p.histC);
     a.vmax = c->vmax(t);
     a.nonfinite = c->nonfinite();
-    a.prev_iter = c->have_prev ? c->at<double>(c->p.iter) + 2 * (t - 1) : nullptr;
     const size_t lds = fill_lds_bytes(c->g.D, c->g.ng, fp64, lds_hist, c->g.tile);
     HIPCHK(c->mark());
     HIPCHK(launch_fill(a, fp64, c->n_wg, lds, c->stream));

@@ -55,8 +55,9 @@ __device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
     for (int r = 0; r < 10; ++r) {
         const uint64_t a = (uint64_t)c0 * 0xD2511F53u;
         const uint64_t b = (uint64_t)c2 * 0xCD9E8D57u;
-        const uint32_t y0 = (uint32_t)(b >> 32) ^ c1 ^ K.k0[r];
-        const uint32_t y2 = (uint32_t)(a >> 32) ^ c3 ^ K.k1[r];
+        // three-input xor in one v_bitop3_b32 (truth table 0x96)
+        const uint32_t y0 = __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), c1, K.k0[r], 0x96);
+        const uint32_t y2 = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), c3, K.k1[r], 0x96);
         c1 = (uint32_t)b;
         c3 = (uint32_t)a;
         c0 = y0;
@@ -102,9 +103,10 @@ __device__ __forceinline__ BinSplit bin_split(uint32_t s, uint32_t r, uint32_t n
     o.p_lo = (uint32_t)P;
     o.p_hi = (uint32_t)(P >> 32);
     const uint32_t a = o.p_hi >> 1;                 // floor(P / 2^33)
-    const uint32_t q = ng * s + a;
+    // N_g, N_st < 2^24 and N_g s < 2^31: 24-bit multiplies are exact
+    const uint32_t q = __umul24(ng, s) + a;
     o.bin = div_magic(q, nst_magic, nst_shift);
-    o.c = q - o.bin * nst;
+    o.c = q - __umul24(o.bin, nst);
     return o;
 }
 

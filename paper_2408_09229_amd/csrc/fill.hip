@@ -14,8 +14,8 @@
 // LDS; its stratum digits; Philox4x32-10 words keyed by (k, t, instance);
 // the fixed-point point and bin index (getPoint, Eq. 3); x and the Jacobian
 // J = prod N_g dx from the map held in LDS (getJac, Eq. 2-4); f(x); w = J f.
-// Then w^2 and a count go to the per-axis histograms (LDS-privatised,
-// flushed per workgroup) and w to the running shifted sums of its cube.
+// Then w^2 and a count go to the per-axis histograms (privatised in LDS,
+// written once per workgroup) and w to the running shifted sums of its cube.
 //
 // Per cube (Eq. 5-6): runs of a cube that cross lanes merge with Chan's
 // pairwise formula in a segmented scan over wavefront shuffles, with one
@@ -249,8 +249,8 @@ struct LdsPlan {
 
 // LDS: map [D][N_g+1] in the sample path's precision; histogram weights
 // [D][N_g] in FP64 (the FP32 LDS atomic add is an order of magnitude slower
-// than the FP64 one on gfx950); counts as packed u16 pairs; the tile's cube
-// starts; per-wave carry records; the tile's side record; a reduction area.
+// than the FP64 one on gfx950) and u32 counts; the tile's cube starts;
+// per-wave carry records; the tile's side record; a reduction area.
 __host__ __device__ inline LdsPlan lds_plan(int D, int ng, int real_bytes, int lds_hist, int tile)
 {
     LdsPlan p;
@@ -260,7 +260,7 @@ __host__ __device__ inline LdsPlan lds_plan(int D, int ng, int real_bytes, int l
     p.h_off = o;
     if (lds_hist) o = al(o + (uint32_t)(D * ng * 8));
     p.c_off = o;
-    if (lds_hist) o = al(o + (uint32_t)(((D * ng + 1) / 2) * 4));
+    if (lds_hist) o = al(o + (uint32_t)(D * ng * 4));
     p.st_off = o; o = al(o + (uint32_t)((tile / 2 + 4) * 4));
     p.wave_off = o; o = al(o + (uint32_t)(kWaves * sizeof(WaveRec)));
     p.cin_off = o; o = al(o + (uint32_t)(kWaves * sizeof(WaveRec)));
@@ -293,21 +293,18 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs a)
     double* red = reinterpret_cast<double*>(smem + lp.red_off);
 
     const int nbins = D * (int)ng;
-    const int nwords = (nbins + 1) / 2;
     const R* gsrc = reinterpret_cast<const R*>(a.grid);
     for (int i = tid; i < D * (int)(ng + 1); i += kFillThreads) gl[i] = gsrc[i];
     if (a.lds_hist) {
-        for (int i = tid; i < nbins; i += kFillThreads) hl[i] = 0.0;
-        for (int i = tid; i < nwords; i += kFillThreads) cl[i] = 0u;
+        for (int i = tid; i < nbins; i += kFillThreads) {
+            hl[i] = 0.0;
+            cl[i] = 0u;
+        }
     }
 
     SamplePath<R, FAM, MAXD> sp(sc);
     double accI = 0.0, accV = 0.0, vmax = 0.0;
     unsigned long long bad = 0;
-    double* slotH = a.lds_hist ? a.hist_H + (size_t)blockIdx.x * nbins : a.hist_H;
-    uint32_t* slotC = a.lds_hist ? a.hist_C + (size_t)blockIdx.x * nbins : a.hist_C;
-    bool first_flush = true;
-    int since_flush = 0;
 
     __syncthreads();
 
@@ -387,7 +384,7 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs a)
                         if (d < D) {
                             const uint32_t bi = (uint32_t)d * ng + bins[d];
                             atomicAdd(hl + bi, w2);
-                            atomicAdd(cl + (bi >> 1), 1u << ((bi & 1u) << 4));
+                            atomicAdd(cl + bi, 1u);
                         }
                     }
                 } else {
@@ -517,51 +514,16 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs a)
             ts->head = tside[0];
             ts->tail = (fl & kSpan) ? tside[0] : tside[1];
         }
-        if (a.lds_hist && ++since_flush >= a.flush_every) {
-            // weights and u16 counts of this workgroup into its slot
-            for (int wi = tid; wi < nwords; wi += kFillThreads) {
-                const uint32_t cw = cl[wi];
-                cl[wi] = 0u;
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const int i = 2 * wi + q;
-                    if (i < nbins) {
-                        const double hv = hl[i];
-                        hl[i] = 0.0;
-                        const uint32_t cv = (cw >> (16 * q)) & 0xFFFFu;
-                        if (first_flush) {
-                            slotH[i] = hv;
-                            slotC[i] = cv;
-                        } else {
-                            slotH[i] += hv;
-                            slotC[i] += cv;
-                        }
-                    }
-                }
-            }
-            first_flush = false;
-            since_flush = 0;
-        }
         __syncthreads();
     }
-    if (a.lds_hist && (since_flush > 0 || first_flush)) {
-        for (int wi = tid; wi < nwords; wi += kFillThreads) {
-            const uint32_t cw = cl[wi];
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int i = 2 * wi + q;
-                if (i < nbins) {
-                    const double hv = hl[i];
-                    const uint32_t cv = (cw >> (16 * q)) & 0xFFFFu;
-                    if (first_flush) {
-                        slotH[i] = hv;
-                        slotC[i] = cv;
-                    } else {
-                        slotH[i] += hv;
-                        slotC[i] += cv;
-                    }
-                }
-            }
+    if (a.lds_hist) {
+        // this workgroup's histograms into its slot (reduced in slot order by
+        // the map kernel)
+        double* slotH = a.hist_H + (size_t)blockIdx.x * nbins;
+        uint32_t* slotC = a.hist_C + (size_t)blockIdx.x * nbins;
+        for (int i = tid; i < nbins; i += kFillThreads) {
+            slotH[i] = hl[i];
+            slotC[i] = cl[i];
         }
     }
 

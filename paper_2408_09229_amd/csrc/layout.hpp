@@ -53,7 +53,6 @@ struct FillArgs {
     int32_t per_lane;
     int32_t n_tiles;
     int32_t lds_hist;           // 1: LDS histograms, 0: global FP64 atomics
-    int32_t flush_every;        // tiles between LDS count flushes (u16 packing)
     int32_t accum;              // VEGAS_ACC_*
     const void* grid;           // [D][N_g+1], FP64 or FP32 per precision
     const uint32_t* start;      // [N_c+1] first sample of each cube
@@ -66,7 +65,6 @@ struct FillArgs {
     uint32_t* hist_C;           // same layout
     unsigned long long* vmax;   // max v_h as FP64 bits (v >= 0)
     unsigned long long* nonfinite;
-    const double* prev_iter;    // (I, s2) of the previous iteration or null
 };
 
 struct FixupArgs {
