@@ -28,21 +28,39 @@ sys.path.insert(0, ROOT)
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 
 
-def valu_ops_per_eval(dim: int, n_terms: int) -> int:
-    """Algorithmic VALU lane-operations of one sample of the GAUSS_DIAG FP32
-    path: the operations the method itself needs, counted once each.
+def valu_ops_per_eval(dim: int, family: int, n_terms: int = 0) -> int:
+    """Algorithmic VALU issue slots of one sample of the FP32 path: the
+    operations the method itself needs, each counted once at its issue cost
+    on gfx950 (full-rate ops 1 slot; the transcendental exp2 2 slots, since
+    it issues at half rate).
 
     Philox4x32-10, per block of 4 axes: 10 rounds x (2 32x32->64 products +
     2 three-input xors) = 40.  Per axis: fixed-point bin (product, two
     shifts/masks, stratum multiply-add, divide-by-constant high product and
     shift, remainder) 7, offset (2 converts, fma, multiply) 4, map (address,
     difference, fma, two Jacobian products) 5, integrand accumulators 3, two
-    histogram addresses 2 -> 21.  Integrand finish: mean and spread 5, per
-    Gaussian term 3 + 1 transcendental, prefactor 3 + 1 transcendental.
-    Weight, square and FP64 cube moments: 8.
+    histogram addresses 2 -> 21.  Integrand finish: GAUSS_DIAG mean and
+    spread 5, per Gaussian term 3 + exp2 (2), prefactor 3 + exp2 (2);
+    GAUSS_CORR spread, quadratic form 8 + exp2 (2).  Weight, square and FP64
+    cube moments: 8.
     """
+    import vegas_inputs as vi
     blocks = (dim + 3) // 4
-    return 40 * blocks + 21 * dim + 5 + 4 * n_terms + 4 + 8
+    if family == vi.GAUSS_DIAG:
+        finish = 5 + 5 * n_terms + 5
+    elif family == vi.GAUSS_CORR:
+        finish = 10
+    else:
+        finish = 4
+    return 40 * blocks + 21 * dim + finish + 8
+
+
+WORKLOADS = {
+    "gauss3_8d": "d=8 mixture of 3 Gaussians s=0.05, 1024 intervals, FP32 sample path + FP64 accumulators",
+    "ridge_4d": "d=4 ridge of 1000 Gaussians s=0.01 on the diagonal, 1024 intervals, FP32 + FP64 accumulators",
+    "gauss_prod_4d": "d=4 Gaussian product s=0.1, 128 intervals, FP64 throughout",
+    "corr_gauss_16d": "d=16 correlated Gaussian rho=0.9 s=0.03, 1024 intervals, FP32 + FP64 accumulators",
+}
 
 
 def cpu_baseline(w, budget_evals: int, iters: int):
@@ -62,7 +80,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n-eval", type=float, default=1e8)
+    ap.add_argument("--workload", default="gauss3_8d", choices=sorted(WORKLOADS))
+    ap.add_argument("--n-eval", type=float, default=0, help="override evals/iteration (0: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-evals", type=float, default=1.5e7)
     ap.add_argument("--cpu-iters", type=int, default=3)
@@ -79,9 +98,11 @@ def main():
     import vegas_inputs as vi
     from paper_2408_09229_amd import Vegas, make_config
 
-    w = vi.gauss3_8d().with_(n_eval=int(args.n_eval))
+    w = getattr(vi, args.workload)()
+    if args.n_eval:
+        w = w.with_(n_eval=int(args.n_eval))
     torch.cuda.set_device(0)
-    cfg = make_config(w.dim, w.n_g, w.n_eval, alpha=w.alpha, beta=w.beta, seed=w.seed, precision="f32",
+    cfg = make_config(w.dim, w.n_g, w.n_eval, alpha=w.alpha, beta=w.beta, seed=w.seed, precision=w.precision,
                       max_iter=args.warmup + args.steps + 1)
     v = Vegas(cfg, w.family, w.params)
     print(f"[bench] {w.name}: n_eval={w.n_eval} tiles={v.info.n_tiles} wg={v.info.n_workgroups}",
@@ -102,7 +123,10 @@ def main():
     ms_step = ms / args.steps
     value = w.n_eval * args.steps / (ms / 1e3)
     fill_ms = phases[0] / max(n_timed, 1)
-    ops = valu_ops_per_eval(w.dim, int(w.params[2])) * w.n_eval
+    from tests import closed_forms
+    exact = closed_forms.exact(w)
+    n_terms = int(w.params[2]) if w.family == vi.GAUSS_DIAG else 0
+    ops = valu_ops_per_eval(w.dim, w.family, n_terms) * w.n_eval
     ach = ops / (fill_ms / 1e3)
     print(f"[bench] integral={r.integral:.12f} +- {math.sqrt(r.sigma2):.3e} chi2/dof={r.chi2_dof:.2f} "
           f"phases ms/it: fill {fill_ms:.3f} fixup+est {phases[1] / n_timed:.3f} alloc "
@@ -118,15 +142,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": w.precision,
         "data": "synthetic",
-        "config": {"workload": "gauss3_8d: d=8 mixture of 3 Gaussians s=0.05, 1024 intervals, "
-                               f"{w.n_eval:.0e} evals/iteration, FP32 sample path + FP64 accumulators",
+        "config": {"workload": f"{w.name}: {WORKLOADS[w.name]}, {w.n_eval:.0e} evals/iteration",
                    "n_eval": w.n_eval, "dim": w.dim, "n_intervals": w.n_g, "parallelism": "single-gpu"},
         "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
-                     "unit": "Tops/s (VALU lane-ops)", "frac": ach / VALU_LANE_OPS_PEAK, "traffic": None,
+                     "unit": "T VALU issue-slots/s", "frac": ach / VALU_LANE_OPS_PEAK, "traffic": None,
                      "kernel": "k_fill", "kernel_ms": fill_ms},
-        "result": {"integral": r.integral, "sigma": math.sqrt(r.sigma2), "chi2_dof": r.chi2_dof},
+        "result": {"integral": r.integral, "sigma": math.sqrt(r.sigma2), "chi2_dof": r.chi2_dof,
+                   "exact": exact, "z": (r.integral - exact) / math.sqrt(r.sigma2) if r.sigma2 > 0 else None},
     }
     if args.copy_calibration:
         src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")   # 256 MiB

@@ -78,7 +78,9 @@ int family_params(int fam, int D, const vegas_integrand* f)
 {
     switch (fam) {
     case VEGAS_GAUSS_DIAG:
-        if (f->n_params < 3 || !f->params) return -1;
+        if (f->n_params < 3 || !f->params || !(f->params[2] >= 1.0 && f->params[2] <= 4096.0) ||
+            f->params[2] != std::floor(f->params[2]))
+            return -1;
         return 3 + (int)f->params[2];
     case VEGAS_GENZ_PPEAK:
     case VEGAS_GENZ_GAUSS: return 1 + 2 * D;
@@ -107,7 +109,7 @@ vegas_status geometry(const vegas_config* c, const vegas_integrand* f, Geometry*
     if (c->instance >= (1u << 24)) return fail(VEGAS_EINVAL, "instance must be < 2^24");
     if (c->max_iter < 0) return fail(VEGAS_EINVAL, "max_iter must be >= 0");
     const int np = family_params(f->family, c->dim, f);
-    if (np < 0) return fail(VEGAS_EINVAL, "unknown integrand family %d or bad parameters", f->family);
+    if (np < 0) return fail(VEGAS_EINVAL, "unknown integrand family %d or bad parameters (GAUSS_DIAG: 1..4096 terms)", f->family);
     if (f->n_params != np || (np > 0 && !f->params))
         return fail(VEGAS_EINVAL, "family %d expects %d parameters, got %d", f->family, np, f->n_params);
     for (int i = 0; i < np; ++i)
@@ -165,11 +167,11 @@ vegas_status geometry(const vegas_config* c, const vegas_integrand* f, Geometry*
     g->tile = kLanesPerTile * g->per_lane;
     g->n_tiles = (int)((ne + g->tile - 1) / g->tile);
     const bool fp64 = c->precision == VEGAS_PREC_FP64;
-    g->lds_hist_ok = fill_lds_bytes(g->D, g->ng, fp64, 1, g->tile) <= kLdsLimit;
-    if (!g->lds_hist_ok && fill_lds_bytes(g->D, g->ng, fp64, 0, g->tile) > kLdsLimit)
+    g->n_aux = std::max(f->family == VEGAS_GAUSS_DIAG ? (int)f->params[2] : 2 * g->D, 1);
+    g->lds_hist_ok = fill_lds_bytes(g->D, g->ng, fp64, 1, g->tile, g->n_aux) <= kLdsLimit;
+    if (!g->lds_hist_ok && fill_lds_bytes(g->D, g->ng, fp64, 0, g->tile, g->n_aux) > kLdsLimit)
         return fail(VEGAS_EUNSUPPORTED, "map of %d x %d intervals does not fit in LDS", g->D, g->ng);
     if ((size_t)3 * (g->ng + 1) * 8 > kLdsLimit) return fail(VEGAS_EUNSUPPORTED, "n_intervals too large for the map update");
-    g->n_aux = std::max(f->family == VEGAS_GAUSS_DIAG ? (int)f->params[2] : 2 * g->D, 1);
     return VEGAS_OK;
 }
 
@@ -280,6 +282,7 @@ SampleConst sample_const(const vegas_ctx* c)
     s.prm = c->at<double>(c->p.prm);
     s.aux_d = c->at<double>(c->p.aux_d);
     s.aux_f = c->at<float>(c->p.aux_f);
+    s.n_aux = c->g.n_aux;
     return s;
 }
 
@@ -362,7 +365,7 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
     a.hist_C = c->at<uint32_t>(c->p.histC);
     a.vmax = c->vmax(t);
     a.nonfinite = c->nonfinite();
-    const size_t lds = fill_lds_bytes(c->g.D, c->g.ng, fp64, lds_hist, c->g.tile);
+    const size_t lds = fill_lds_bytes(c->g.D, c->g.ng, fp64, lds_hist, c->g.tile, c->g.n_aux);
     HIPCHK(c->mark());
     HIPCHK(launch_fill(a, fp64, c->n_wg, lds, c->stream));
     HIPCHK(c->mark());

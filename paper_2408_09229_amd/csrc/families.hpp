@@ -1,7 +1,9 @@
 // Built-in integrand families (vegas.h VEGAS_* ids; Tab. 3 and the benchmark
 // workloads).  Each is a functor fed one coordinate at a time, so the sample
 // path never stores a coordinate vector:
-//   setup(sc)    per-thread constants from the raw / derived parameters
+//   setup(sc, aux)  per-thread constants from the raw parameters and the
+//                   derived per-term / per-axis table aux (in the sample
+//                   path's precision; the fill kernel passes a copy in LDS)
 //   begin()      reset the per-sample accumulators
 //   axis(d, x)   fold in coordinate d
 //   finish()     f(x)
@@ -34,16 +36,14 @@ template <typename R>
 struct Fn<R, F_GAUSS_DIAG> {
     R A, h, Dr, invD, x0, a1, a2;
     int M;
-    const double* cd;
-    const float* kc;     // FP32: K c_j with K = sqrt(D / (2 s^2 ln 2))
+    const R* cj;         // FP64: c_j; FP32: K c_j with K = sqrt(D / (2 s^2 ln 2))
     R K;
-    __device__ __forceinline__ void setup(const SampleConst& sc)
+    __device__ __forceinline__ void setup(const SampleConst& sc, const R* aux)
     {
         const double s = sc.prm[1];
         A = (R)sc.prm[0];
         M = (int)sc.prm[2];
-        cd = sc.prm + 3;
-        kc = sc.aux_f;
+        cj = aux;
         Dr = (R)sc.D;
         invD = (R)(1.0 / (double)sc.D);
         if constexpr (std::is_same<R, double>::value) {
@@ -75,25 +75,30 @@ struct Fn<R, F_GAUSS_DIAG> {
             double acc = 0.0;
             const double dh = Dr * h;
             for (int j = 0; j < M; ++j) {
-                const double u = m - cd[j];
+                const double u = m - cj[j];
                 acc += exp(-(dh * u) * u);
             }
             return A * exp(-S * h) * acc;
         } else {
+            // per term: difference, square, exp2, add (4 independent sums)
             const float Km = K * m;
-            float acc0 = 0.f, acc1 = 0.f;
+            float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
             int j = 0;
-            for (; j + 1 < M; j += 2) {
-                const float g0 = Km - kc[j];
-                const float g1 = Km - kc[j + 1];
+            for (; j + 3 < M; j += 4) {
+                const float g0 = Km - cj[j];
+                const float g1 = Km - cj[j + 1];
+                const float g2 = Km - cj[j + 2];
+                const float g3 = Km - cj[j + 3];
                 acc0 += exp2_fast(-(g0 * g0));
                 acc1 += exp2_fast(-(g1 * g1));
+                acc2 += exp2_fast(-(g2 * g2));
+                acc3 += exp2_fast(-(g3 * g3));
             }
-            if (j < M) {
-                const float g0 = Km - kc[j];
+            for (; j < M; ++j) {
+                const float g0 = Km - cj[j];
                 acc0 += exp2_fast(-(g0 * g0));
             }
-            return A * exp2_fast(-S * h) * (acc0 + acc1);
+            return A * exp2_fast(-S * h) * ((acc0 + acc1) + (acc2 + acc3));
         }
     }
 };
@@ -102,22 +107,18 @@ struct Fn<R, F_GAUSS_DIAG> {
 template <typename R>
 struct Fn<R, F_GENZ_PPEAK> {
     R A, p;
-    const double* ad;    // [1/a^2 .. , u ..]
-    const float* af;
+    const R* ax;         // [1/a^2 .., u ..]
     int D;
-    __device__ __forceinline__ void setup(const SampleConst& sc)
+    __device__ __forceinline__ void setup(const SampleConst& sc, const R* aux)
     {
         A = (R)sc.prm[0];
-        ad = sc.aux_d;
-        af = sc.aux_f;
+        ax = aux;
         D = sc.D;
     }
     __device__ __forceinline__ void begin() { p = 1; }
     __device__ __forceinline__ void axis(int d, R x)
     {
-        R ia2, u0;
-        if constexpr (std::is_same<R, double>::value) { ia2 = ad[d]; u0 = ad[D + d]; }
-        else { ia2 = af[d]; u0 = af[D + d]; }
+        const R ia2 = ax[d], u0 = ax[D + d];
         const R u = x - u0;
         p = p * fma(u, u, ia2);
     }
@@ -128,22 +129,18 @@ struct Fn<R, F_GENZ_PPEAK> {
 template <typename R>
 struct Fn<R, F_GENZ_GAUSS> {
     R A, q;
-    const double* ad;    // [a^2 .., u ..]
-    const float* af;     // [a^2 / ln 2 .., u ..]
+    const R* ax;         // FP64: [a^2 .., u ..]; FP32: [a^2 / ln 2 .., u ..]
     int D;
-    __device__ __forceinline__ void setup(const SampleConst& sc)
+    __device__ __forceinline__ void setup(const SampleConst& sc, const R* aux)
     {
         A = (R)sc.prm[0];
-        ad = sc.aux_d;
-        af = sc.aux_f;
+        ax = aux;
         D = sc.D;
     }
     __device__ __forceinline__ void begin() { q = 0; }
     __device__ __forceinline__ void axis(int d, R x)
     {
-        R a2, u0;
-        if constexpr (std::is_same<R, double>::value) { a2 = ad[d]; u0 = ad[D + d]; }
-        else { a2 = af[d]; u0 = af[D + d]; }
+        const R a2 = ax[d], u0 = ax[D + d];
         const R u = x - u0;
         q = fma(a2 * u, u, q);
     }
@@ -161,7 +158,7 @@ struct Fn<R, F_GENZ_GAUSS> {
 template <typename R>
 struct Fn<R, F_GAUSS_CORR> {
     R mu, c1, c2, z, x0, a1, a2, invD;
-    __device__ __forceinline__ void setup(const SampleConst& sc)
+    __device__ __forceinline__ void setup(const SampleConst& sc, const R*)
     {
         const double m = sc.prm[0], s = sc.prm[1], rho = sc.prm[2];
         const int D = sc.D;
@@ -202,7 +199,7 @@ struct Fn<R, F_GAUSS_CORR> {
 template <typename R>
 struct Fn<R, F_LINEAR> {
     R A, s;
-    __device__ __forceinline__ void setup(const SampleConst& sc) { A = (R)sc.prm[0]; }
+    __device__ __forceinline__ void setup(const SampleConst& sc, const R*) { A = (R)sc.prm[0]; }
     __device__ __forceinline__ void begin() { s = 0; }
     __device__ __forceinline__ void axis(int, R x) { s = s + x; }
     __device__ __forceinline__ R finish() const { return A * s; }
@@ -211,7 +208,7 @@ struct Fn<R, F_LINEAR> {
 template <typename R>
 struct Fn<R, F_ROOS> {
     R A, p;
-    __device__ __forceinline__ void setup(const SampleConst& sc) { A = (R)sc.prm[0]; }
+    __device__ __forceinline__ void setup(const SampleConst& sc, const R*) { A = (R)sc.prm[0]; }
     __device__ __forceinline__ void begin() { p = 1; }
     __device__ __forceinline__ void axis(int, R x) { p = p * fabs((R)4 * x - (R)2); }
     __device__ __forceinline__ R finish() const { return A * p; }
@@ -220,7 +217,7 @@ struct Fn<R, F_ROOS> {
 template <typename R>
 struct Fn<R, F_CONST> {
     R A;
-    __device__ __forceinline__ void setup(const SampleConst& sc) { A = (R)sc.prm[0]; }
+    __device__ __forceinline__ void setup(const SampleConst& sc, const R*) { A = (R)sc.prm[0]; }
     __device__ __forceinline__ void begin() {}
     __device__ __forceinline__ void axis(int, R) {}
     __device__ __forceinline__ R finish() const { return A; }
@@ -229,7 +226,7 @@ struct Fn<R, F_CONST> {
 template <typename R>
 struct Fn<R, F_COSINE> {
     R A, p;
-    __device__ __forceinline__ void setup(const SampleConst& sc) { A = (R)sc.prm[0]; }
+    __device__ __forceinline__ void setup(const SampleConst& sc, const R*) { A = (R)sc.prm[0]; }
     __device__ __forceinline__ void begin() { p = 1; }
     __device__ __forceinline__ void axis(int, R x) { p = p * cos(x); }
     __device__ __forceinline__ R finish() const { return A * p; }

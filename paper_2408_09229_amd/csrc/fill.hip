@@ -67,9 +67,11 @@ struct SamplePath {
     double nst_d;
     float inv_nst_f;
 
-    __device__ __forceinline__ explicit SamplePath(const SampleConst& c) : sc(c)
+    // aux: the family's derived table in the path's precision (LDS in the
+    // fill, global memory in the probe)
+    __device__ __forceinline__ SamplePath(const SampleConst& c, const R* aux) : sc(c)
     {
-        fn.setup(c);
+        fn.setup(c, aux);
         keys = philox_keys<std::is_same<R, float>::value && MAXD <= 8>(c.key0, c.key1);
         ngR = (R)c.ng;
         nst_d = (double)c.nst;
@@ -244,19 +246,20 @@ struct WaveRec {
 };
 
 struct LdsPlan {
-    uint32_t grid_off, h_off, c_off, st_off, wave_off, cin_off, side_off, red_off, total;
+    uint32_t grid_off, aux_off, h_off, c_off, st_off, wave_off, cin_off, side_off, red_off, total;
 };
 
 // LDS: map [D][N_g+1] in the sample path's precision; histogram weights
 // [D][N_g] in FP64 (the FP32 LDS atomic add is an order of magnitude slower
 // than the FP64 one on gfx950) and u32 counts; the tile's cube starts;
 // per-wave carry records; the tile's side record; a reduction area.
-__host__ __device__ inline LdsPlan lds_plan(int D, int ng, int real_bytes, int lds_hist, int tile)
+__host__ __device__ inline LdsPlan lds_plan(int D, int ng, int real_bytes, int lds_hist, int tile, int n_aux)
 {
     LdsPlan p;
     uint32_t o = 0;
     auto al = [](uint32_t v) { return (v + 15u) & ~15u; };
     p.grid_off = o; o = al(o + (uint32_t)(D * (ng + 1) * real_bytes));
+    p.aux_off = o; o = al(o + (uint32_t)(n_aux * real_bytes));
     p.h_off = o;
     if (lds_hist) o = al(o + (uint32_t)(D * ng * 8));
     p.c_off = o;
@@ -281,8 +284,9 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs a)
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int S = a.per_lane;
-    const LdsPlan lp = lds_plan(D, (int)ng, (int)sizeof(R), a.lds_hist, a.tile);
+    const LdsPlan lp = lds_plan(D, (int)ng, (int)sizeof(R), a.lds_hist, a.tile, sc.n_aux);
     R* gl = reinterpret_cast<R*>(smem + lp.grid_off);
+    R* auxl = reinterpret_cast<R*>(smem + lp.aux_off);
     double* hl = reinterpret_cast<double*>(smem + lp.h_off);
     uint32_t* cl = reinterpret_cast<uint32_t*>(smem + lp.c_off);
     uint32_t* st = reinterpret_cast<uint32_t*>(smem + lp.st_off);
@@ -295,6 +299,11 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs a)
     const int nbins = D * (int)ng;
     const R* gsrc = reinterpret_cast<const R*>(a.grid);
     for (int i = tid; i < D * (int)(ng + 1); i += kFillThreads) gl[i] = gsrc[i];
+    {
+        const R* asrc = std::is_same<R, double>::value ? reinterpret_cast<const R*>(sc.aux_d)
+                                                       : reinterpret_cast<const R*>(sc.aux_f);
+        for (int i = tid; i < sc.n_aux; i += kFillThreads) auxl[i] = asrc[i];
+    }
     if (a.lds_hist) {
         for (int i = tid; i < nbins; i += kFillThreads) {
             hl[i] = 0.0;
@@ -302,7 +311,7 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs a)
         }
     }
 
-    SamplePath<R, FAM, MAXD> sp(sc);
+    SamplePath<R, FAM, MAXD> sp(sc, auxl);
     double accI = 0.0, accV = 0.0, vmax = 0.0;
     unsigned long long bad = 0;
 
@@ -629,7 +638,9 @@ __global__ void k_probe(ProbeArgs a)
         const uint32_t mid = (lo + hi) >> 1;
         if (a.start[mid] <= k) lo = mid; else hi = mid;
     }
-    SamplePath<R, FAM, MAXD> sp(a.sc);
+    const R* aux = std::is_same<R, double>::value ? reinterpret_cast<const R*>(a.sc.aux_d)
+                                                  : reinterpret_cast<const R*>(a.sc.aux_f);
+    SamplePath<R, FAM, MAXD> sp(a.sc, aux);
     uint32_t s[MAXD], bins[MAXD];
     R delta[MAXD], x[MAXD], J, f;
     sp.digits(lo, s);
@@ -730,9 +741,9 @@ hipError_t launch_final(const FinalArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
-size_t fill_lds_bytes(int D, int ng, bool fp64, int lds_hist, int tile)
+size_t fill_lds_bytes(int D, int ng, bool fp64, int lds_hist, int tile, int n_aux)
 {
-    return lds_plan(D, ng, fp64 ? 8 : 4, lds_hist, tile).total;
+    return lds_plan(D, ng, fp64 ? 8 : 4, lds_hist, tile, n_aux).total;
 }
 
 }  // namespace vg

@@ -42,7 +42,7 @@ hipError_t launch_fill(const FillArgs& a, bool fp64, int n_wg, size_t lds, hipSt
 hipError_t launch_fixup(const FixupArgs& a, hipStream_t st);
 hipError_t launch_final(const FinalArgs& a, hipStream_t st);
 hipError_t launch_probe(const ProbeArgs& a, bool fp64, hipStream_t st);
-size_t fill_lds_bytes(int D, int ng, bool fp64, int lds_hist, int tile);
+size_t fill_lds_bytes(int D, int ng, bool fp64, int lds_hist, int tile, int n_aux);
 
 hipError_t launch_prep(const PrepArgs& a, hipStream_t st);
 hipError_t launch_alloc(const AllocArgs& a, unsigned long long* qmax_bits, hipStream_t st);

@@ -44,6 +44,7 @@ struct SampleConst {
     const double* prm;         // raw parameters (device)
     const double* aux_d;       // derived constants, FP64 (device)
     const float* aux_f;        // derived constants, FP32 (device)
+    int32_t n_aux;             // entries of aux_d / aux_f
 };
 
 struct FillArgs {
