@@ -105,7 +105,13 @@ vegas_status geometry(const vegas_config* c, const vegas_integrand* f, Geometry*
     if (!(c->beta >= 0.0) || !std::isfinite(c->beta)) return fail(VEGAS_EINVAL, "beta must be finite and >= 0");
     if (c->precision != VEGAS_PREC_FP64 && c->precision != VEGAS_PREC_FP32)
         return fail(VEGAS_EINVAL, "unknown precision %d", c->precision);
-    if (c->accum != VEGAS_ACC_FP64) return fail(VEGAS_EUNSUPPORTED, "accumulation mode %d not available", c->accum);
+    if (c->accum != VEGAS_ACC_FP64 && c->accum != VEGAS_ACC_ORDERED)
+        return fail(VEGAS_EUNSUPPORTED, "accumulation mode %d not available", c->accum);
+    if (c->accum == VEGAS_ACC_ORDERED) {
+        if (c->precision != VEGAS_PREC_FP64) return fail(VEGAS_EINVAL, "ORDERED accumulation runs in FP64");
+        if ((double)c->n_eval * c->dim * c->n_intervals > (double)(1ull << 28) || c->n_eval > (1 << 24))
+            return fail(VEGAS_EUNSUPPORTED, "ORDERED accumulation is for n_eval*dim*n_intervals <= 2^28");
+    }
     if (c->instance >= (1u << 24)) return fail(VEGAS_EINVAL, "instance must be < 2^24");
     if (c->max_iter < 0) return fail(VEGAS_EINVAL, "max_iter must be >= 0");
     const int np = family_params(f->family, c->dim, f);
@@ -178,10 +184,10 @@ vegas_status geometry(const vegas_config* c, const vegas_integrand* f, Geometry*
 // Workspace carving: offsets of every device array (256-byte aligned).
 struct Plan {
     size_t prm, lo, hi, aux_d, aux_f, grid64, grid32, start[2], tfirst[2], v, wg_part, wg_comp, side, fix_part,
-        histH, histC, Hsum, Csum, counters, bsum, boff, iter, total;
+        histH, histC, partH, partC, Hsum, Csum, counters, bsum, boff, iter, ord_w, ord_bins, ord_m, total;
 };
 
-Plan plan(const Geometry& g, int max_iter)
+Plan plan(const Geometry& g, int max_iter, bool ordered)
 {
     Plan p;
     size_t o = 0;
@@ -212,12 +218,20 @@ Plan plan(const Geometry& g, int max_iter)
     const size_t slots = g.lds_hist_ok ? kMaxWG : 1;
     p.histH = take(sizeof(double) * nb * slots);
     p.histC = take(sizeof(uint32_t) * nb * slots);
+    p.partH = take(sizeof(double) * nb * kHistParts);
+    p.partC = take(sizeof(uint32_t) * nb * kHistParts);
     p.Hsum = take(sizeof(double) * nb);
     p.Csum = take(sizeof(double) * nb);
     p.counters = take(sizeof(unsigned long long) * 8);   // vmax[2], qmax[2], nonfinite
     p.bsum = take(sizeof(unsigned long long) * nblk);
     p.boff = take(sizeof(unsigned long long) * (nblk + 1));
     p.iter = take(sizeof(double) * 2 * (size_t)max_iter);
+    p.ord_w = p.ord_bins = p.ord_m = 0;
+    if (ordered) {
+        p.ord_w = take(sizeof(double) * g.n_eval);
+        p.ord_bins = take(sizeof(uint32_t) * (size_t)g.n_eval * g.D);
+        p.ord_m = take(sizeof(double) * g.n_cubes);
+    }
     p.total = o;
     return p;
 }
@@ -296,6 +310,8 @@ AllocArgs alloc_args(vegas_ctx* c, int t, int uniform)
     a.beta = c->cfg.beta;
     a.uniform = uniform;
     a.tile = c->g.tile;
+    a.tile_shift = 0;
+    while ((1 << a.tile_shift) < c->g.tile) ++a.tile_shift;
     a.n_tiles = c->g.n_tiles;
     a.per_block = kAllocPerBlock;
     a.v = c->at<double>(c->p.v);
@@ -323,6 +339,22 @@ vegas_status run_update(vegas_ctx* c, int t, int n_slots, bool timed)
     m.alpha = c->cfg.adapt_map ? c->cfg.alpha : 0.0;
     m.hist_H = c->at<double>(c->p.histH);
     m.hist_C = c->at<uint32_t>(c->p.histC);
+    if (n_slots > kHistParts) {
+        // many workgroup slots: a wide first-level reduce, then the map
+        // kernel adds kHistParts partials in order
+        HistReduceArgs hr;
+        hr.nbins = c->g.D * c->g.ng;
+        hr.n_slots = n_slots;
+        hr.parts = kHistParts;
+        hr.hist_H = m.hist_H;
+        hr.hist_C = m.hist_C;
+        hr.part_H = c->at<double>(c->p.partH);
+        hr.part_C = c->at<uint32_t>(c->p.partC);
+        HIPCHK(launch_hist_reduce(hr, c->stream));
+        m.n_slots = kHistParts;
+        m.hist_H = hr.part_H;
+        m.hist_C = hr.part_C;
+    }
     m.grid64 = c->at<double>(c->p.grid64);
     m.grid32 = c->at<float>(c->p.grid32);
     m.Hsum = c->at<double>(c->p.Hsum);
@@ -342,6 +374,32 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
     const int nb = c->g.D * c->g.ng;
     HIPCHK(launch_reset(c->vmax(t), 1, c->stream));
     HIPCHK(launch_reset(c->qmax(t), 1, c->stream));
+    if (c->cfg.accum == VEGAS_ACC_ORDERED) {
+        OrderedArgs o;
+        o.sc = sample_const(c);
+        o.t = (uint32_t)t;
+        o.grid = c->at<double>(c->p.grid64);
+        o.start = c->at<uint32_t>(c->p.start[c->cur]);
+        o.w = c->at<double>(c->p.ord_w);
+        o.bins = c->at<uint32_t>(c->p.ord_bins);
+        o.m = c->at<double>(c->p.ord_m);
+        o.v = c->at<double>(c->p.v);
+        o.hist_H = c->at<double>(c->p.histH);
+        o.hist_C = c->at<uint32_t>(c->p.histC);
+        o.iter_out = c->at<double>(c->p.iter) + 2 * t;
+        o.vmax = c->vmax(t);
+        o.nonfinite = c->nonfinite();
+        HIPCHK(c->mark());
+        HIPCHK(launch_ordered(o, c->stream));
+        HIPCHK(c->mark());
+        HIPCHK(c->mark());
+        const vegas_status s = run_update(c, t, 1, true);
+        if (s != VEGAS_OK) return s;
+        c->n_run = t + 1;
+        c->combined.push_back(integrate ? 1 : 0);
+        c->have_prev = true;
+        return VEGAS_OK;
+    }
     if (!lds_hist) {
         HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histH), nb, c->stream));
         HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histC), (nb + 1) / 2, c->stream));
@@ -488,7 +546,7 @@ vegas_status vegas_workspace_size(const vegas_config* cfg, const vegas_integrand
     const vegas_status s = geometry(cfg, f, &g);
     if (s != VEGAS_OK) return s;
     if (!bytes) return fail(VEGAS_EINVAL, "null bytes");
-    *bytes = plan(g, cfg->max_iter > 0 ? cfg->max_iter : 4096).total;
+    *bytes = plan(g, cfg->max_iter > 0 ? cfg->max_iter : 4096, cfg->accum == VEGAS_ACC_ORDERED).total;
     return VEGAS_OK;
 }
 
@@ -501,7 +559,7 @@ vegas_status vegas_create(const vegas_config* cfg, const vegas_integrand* f, voi
     vegas_status s = geometry(cfg, f, &g);
     if (s != VEGAS_OK) return s;
     const int max_iter = cfg->max_iter > 0 ? cfg->max_iter : 4096;
-    const Plan p = plan(g, max_iter);
+    const Plan p = plan(g, max_iter, cfg->accum == VEGAS_ACC_ORDERED);
     if (!d_workspace) return fail(VEGAS_EINVAL, "null workspace");
     if (((uintptr_t)d_workspace & 255u) != 0) return fail(VEGAS_EINVAL, "workspace must be 256-byte aligned");
     if (bytes < p.total) return fail(VEGAS_ENOMEM, "workspace has %zu bytes, needs %zu", bytes, p.total);

@@ -24,6 +24,22 @@ struct ProbeArgs {
     double* f;
 };
 
+struct OrderedArgs {
+    SampleConst sc;
+    uint32_t t;
+    const double* grid;         // FP64 [D][N_g+1]
+    const uint32_t* start;      // [N_c+1]
+    double* w;                  // [N_ev] sample weights
+    uint32_t* bins;             // [N_ev][D]
+    double* m;                  // [N_c] cube means
+    double* v;                  // [N_c] cube unbiased variances
+    double* hist_H;             // [D*N_g] (slot 0)
+    uint32_t* hist_C;
+    double* iter_out;           // (I_t, sigma_t^2)
+    unsigned long long* vmax;
+    unsigned long long* nonfinite;
+};
+
 struct PrepArgs {
     int32_t family;
     int32_t D;
@@ -45,8 +61,10 @@ hipError_t launch_probe(const ProbeArgs& a, bool fp64, hipStream_t st);
 size_t fill_lds_bytes(int D, int ng, bool fp64, int lds_hist, int tile, int n_aux);
 
 hipError_t launch_prep(const PrepArgs& a, hipStream_t st);
+hipError_t launch_ordered(const OrderedArgs& a, hipStream_t st);
 hipError_t launch_alloc(const AllocArgs& a, unsigned long long* qmax_bits, hipStream_t st);
 hipError_t launch_map_update(const MapArgs& a, hipStream_t st);
+hipError_t launch_hist_reduce(const HistReduceArgs& a, hipStream_t st);
 hipError_t launch_reset(unsigned long long* p, int n, hipStream_t st);
 hipError_t launch_grid32(const double* g64, float* g32, int n, hipStream_t st);
 

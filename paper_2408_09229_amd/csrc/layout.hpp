@@ -95,6 +95,7 @@ struct AllocArgs {
     double beta;
     int32_t uniform;            // 1: Q_h = 1
     int32_t tile;
+    int32_t tile_shift;         // tile = 2^tile_shift
     int32_t n_tiles;
     int32_t per_block;          // cubes per block
     const double* v;
@@ -106,12 +107,24 @@ struct AllocArgs {
     uint32_t* tile_first;       // [n_tiles+1] out
 };
 
+constexpr int kHistParts = 8;          // first-level slot groups of the histogram reduce
+
+struct HistReduceArgs {
+    int32_t nbins;              // D * N_g
+    int32_t n_slots;
+    int32_t parts;              // 1 .. kHistParts
+    const double* hist_H;       // [n_slots][nbins]
+    const uint32_t* hist_C;
+    double* part_H;             // [parts][nbins]
+    uint32_t* part_C;
+};
+
 struct MapArgs {
     int32_t D;
     int32_t ng;
-    int32_t n_slots;            // histogram slots to reduce (n_wg, or 1)
+    int32_t n_slots;            // partial histograms to add, in order
     double alpha;
-    const double* hist_H;
+    const double* hist_H;       // [n_slots][D*N_g]
     const uint32_t* hist_C;
     double* grid64;             // [D][N_g+1] in/out
     float* grid32;              // [D][N_g+1] out (FP32 copy)

@@ -1,0 +1,115 @@
+// The per-sample path of Alg. 2 shared by the fill, the ordered mode and
+// the probe: stratum digits of a cube, Philox words, fixed-point point and
+// bin, map and Jacobian, integrand.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <type_traits>
+
+#include "common.hpp"
+#include "families.hpp"
+#include "layout.hpp"
+
+namespace vg {
+
+// ---------------------------------------------------------------------------
+// the per-sample path shared by the fill and the probe
+// ---------------------------------------------------------------------------
+template <typename R, int FAM, int MAXD>
+struct SamplePath {
+    const SampleConst& sc;
+    Fn<R, FAM> fn;
+    PhiloxKeys keys;
+    R ngR;
+    double nst_d;
+    float inv_nst_f;
+
+    // aux: the family's derived table in the path's precision (LDS in the
+    // fill, global memory in the probe)
+    __device__ __forceinline__ SamplePath(const SampleConst& c, const R* aux) : sc(c)
+    {
+        fn.setup(c, aux);
+        keys = philox_keys<std::is_same<R, float>::value && MAXD <= 8>(c.key0, c.key1);
+        ngR = (R)c.ng;
+        nst_d = (double)c.nst;
+        inv_nst_f = (float)(1.0 / (double)c.nst);
+    }
+
+    // digits of cube h in base N_st, axis 0 fastest
+    __device__ __forceinline__ void digits(uint32_t h, uint32_t (&s)[MAXD]) const
+    {
+#pragma unroll
+        for (int d = 0; d < MAXD; ++d) {
+            const uint32_t q = div_magic(h, sc.nst_magic, sc.nst_shift);
+            s[d] = h - q * sc.nst;
+            h = q;
+        }
+    }
+
+    // digits of h+1 from those of h; the carry reaches axis d once every
+    // N_st^d cubes, so the nested branches are rarely taken past axis 0
+    __device__ __forceinline__ void next_digits(uint32_t (&s)[MAXD]) const
+    {
+        next_digit_from<0>(s);
+    }
+    template <int d>
+    __device__ __forceinline__ void next_digit_from(uint32_t (&s)[MAXD]) const
+    {
+        if constexpr (d < MAXD) {
+            const uint32_t v = s[d] + 1u;
+            if (v == sc.nst) {
+                s[d] = 0u;
+                next_digit_from<d + 1>(s);
+            } else {
+                s[d] = v;
+            }
+        }
+    }
+
+    // Evaluate sample k (iteration t) of the cube with digits s against the
+    // grid g (row stride N_g+1).  Returns w = J f; bins and (optionally)
+    // delta / x / J / f are reported through the out-parameters.
+    template <bool PROBE>
+    __device__ __forceinline__ R eval(uint32_t k, uint32_t t, const uint32_t (&s)[MAXD],
+                                      const R* __restrict__ g, uint32_t (&bins)[MAXD],
+                                      R* delta_out, R* x_out, R& J, R& f)
+    {
+        uint32_t wd[MAXD];
+#pragma unroll
+        for (int b = 0; b < (MAXD + 3) / 4; ++b) {
+            if (4 * b < sc.D) {
+                const W4 o = philox10(k, 0u, t, sc.ctr3 | (uint32_t)b, keys);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (4 * b + q < MAXD) wd[4 * b + q] = o.v[q];
+            }
+        }
+        J = (R)1;
+        fn.begin();
+        const uint32_t row = sc.ng + 1u;
+#pragma unroll
+        for (int d = 0; d < MAXD; ++d) {
+            if (d < sc.D) {
+                const BinSplit p = bin_split(s[d], wd[d], sc.ng, sc.nst, sc.nst_magic, sc.nst_shift);
+                bins[d] = p.bin;
+                R delta;
+                if constexpr (std::is_same<R, double>::value) delta = delta_f64(p, nst_d);
+                else delta = delta_f32(p, inv_nst_f);
+                const R* gd = g + d * row;
+                const R xl = gd[p.bin];
+                const R dx = gd[p.bin + 1] - xl;
+                const R x = fma(dx, delta, xl);
+                J = J * (ngR * dx);
+                fn.axis(d, x);
+                if constexpr (PROBE) {
+                    delta_out[d] = delta;
+                    x_out[d] = x;
+                }
+            }
+        }
+        f = fn.finish();
+        return J * f;
+    }
+};
+
+}  // namespace vg

@@ -237,8 +237,8 @@ __global__ __launch_bounds__(kAllocThreads) void k_alloc_write(AllocArgs a, cons
         const uint32_t nh = a.n_min + (uint32_t)(hi - lo);
         a.start[h] = start;
         // tiles whose first sample lies in this cube
-        const uint64_t t = (uint64_t)a.tile;
-        for (uint64_t j = ((uint64_t)start + t - 1u) / t; j * t < (uint64_t)start + nh; ++j)
+        const uint64_t end = (uint64_t)start + nh;
+        for (uint64_t j = ((uint64_t)start + (uint64_t)a.tile - 1u) >> a.tile_shift; (j << a.tile_shift) < end; ++j)
             a.tile_first[j] = h;
         if (h == a.n_cubes - 1u) {
             a.start[a.n_cubes] = a.n_eval;
@@ -257,6 +257,47 @@ hipError_t launch_alloc(const AllocArgs& a, unsigned long long* qmax_bits, hipSt
     hipLaunchKernelGGL(k_alloc_sum, dim3(nb), dim3(kAllocThreads), 0, st, a, qmax_bits);
     hipLaunchKernelGGL(k_alloc_scan, dim3(1), dim3(kAllocThreads), 0, st, a, nb);
     hipLaunchKernelGGL(k_alloc_write, dim3(nb), dim3(kAllocThreads), 0, st, a, qmax_bits, nb);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// histogram slots -> a few partials: thread (bin, part) adds its part's
+// slots in slot order; the map kernel then adds the parts in part order, so
+// the sum is the same on every run
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_hist_reduce(HistReduceArgs a)
+{
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= a.nbins * a.parts) return;
+    const int part = idx / a.nbins;
+    const int bin = idx - part * a.nbins;
+    const int per = (a.n_slots + a.parts - 1) / a.parts;
+    const int w0 = part * per;
+    const int w1 = min(w0 + per, a.n_slots);
+    double h = 0.0;
+    uint32_t c = 0;
+    int w = w0;
+    for (; w + 4 <= w1; w += 4) {
+        const double h0 = a.hist_H[(size_t)w * a.nbins + bin];
+        const double h1 = a.hist_H[(size_t)(w + 1) * a.nbins + bin];
+        const double h2 = a.hist_H[(size_t)(w + 2) * a.nbins + bin];
+        const double h3 = a.hist_H[(size_t)(w + 3) * a.nbins + bin];
+        c += a.hist_C[(size_t)w * a.nbins + bin] + a.hist_C[(size_t)(w + 1) * a.nbins + bin] +
+             a.hist_C[(size_t)(w + 2) * a.nbins + bin] + a.hist_C[(size_t)(w + 3) * a.nbins + bin];
+        h = (((h + h0) + h1) + h2) + h3;
+    }
+    for (; w < w1; ++w) {
+        h += a.hist_H[(size_t)w * a.nbins + bin];
+        c += a.hist_C[(size_t)w * a.nbins + bin];
+    }
+    a.part_H[(size_t)part * a.nbins + bin] = h;
+    a.part_C[(size_t)part * a.nbins + bin] = c;
+}
+
+hipError_t launch_hist_reduce(const HistReduceArgs& a, hipStream_t st)
+{
+    const int n = a.nbins * a.parts;
+    hipLaunchKernelGGL(k_hist_reduce, dim3((n + 255) / 256), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -88,3 +88,14 @@ def test_budget_too_small_for_strata(abi):
 def test_status_strings(abi):
     for s in range(-6, 1):
         assert abi.vegas_status_string(s)
+
+
+def test_ordered_limits(abi):
+    it = abi._Integrand(vi.CONST, np.array([1.0]))
+    n = C.c_size_t()
+    ok = abi.make_config(2, 8, 2000, accum="ordered")
+    assert abi.vegas_workspace_size(C.byref(ok), C.byref(it.s), C.byref(n)) == 0
+    f32 = abi.make_config(2, 8, 2000, accum="ordered", precision="f32")
+    assert abi.vegas_workspace_size(C.byref(f32), C.byref(it.s), C.byref(n)) == -1
+    big = abi.make_config(2, 1024, 10 ** 7, accum="ordered")
+    assert abi.vegas_workspace_size(C.byref(big), C.byref(it.s), C.byref(n)) == -6

@@ -200,3 +200,48 @@ def test_gauss_prod_4d_config(orc, V):
     o = orc.run(w.dim, w.n_g, w.n_eval, w.family, w.params, n_iter=1, seed=w.seed)
     assert abs(I[0] - o.I_t[0]) <= 1e-12 * abs(o.I_t[0])
     v.close()
+
+
+ORDERED_CASES = [
+    vi.Workload("ppeak3_ord", 3, vi.GENZ_PPEAK, np.array([1.0, 6.0, 9.0, 12.0, 0.3, 0.6, 0.45]), n_g=16,
+                n_eval=6_007, n_iter=5),
+    vi.Workload("roos2_ord", 2, vi.ROOS, np.array([1.0]), n_g=8, n_eval=2_003, n_iter=5, alpha=0.7, beta=0.3),
+    vi.Workload("linear4_ord", 4, vi.LINEAR, np.array([2.0]), n_g=32, n_eval=10_000, n_iter=5, alpha=1.5),
+]
+
+
+@pytest.mark.parametrize("w", ORDERED_CASES, ids=lambda w: w.name)
+def test_ordered_trajectory_bitexact(orc, V, w):
+    """ORDERED accumulation: a whole trajectory (estimates, map, allocation)
+    equals the oracle's bit for bit, for integrands built from correctly
+    rounded operations."""
+    say(f"[ordered] {w.name}")
+    v = V(w, accum="ordered")
+    v.integrate(w.n_iter)
+    I, s2 = v.get_iterations()
+    g = v.get_map()
+    nh = v.get_nh()
+    o = orc.run(w.dim, w.n_g, w.n_eval, w.family, w.params, n_iter=w.n_iter, seed=w.seed, alpha=w.alpha,
+                beta=w.beta)
+    assert np.array_equal(I, o.I_t), (I - o.I_t)
+    assert np.array_equal(s2, o.s2_t)
+    assert np.array_equal(g, o.grid)
+    assert np.array_equal(nh, o.nh)
+    r = v.result()
+    assert r.integral == o.integral and r.sigma2 == o.sigma2
+    v.close()
+
+
+def test_ordered_reproducible(V):
+    w = vi.gauss_prod_4d().with_(n_eval=8_000, n_g=16)
+    say("[ordered] reproducible")
+    runs = []
+    for _ in range(2):
+        v = V(w, accum="ordered")
+        v.integrate(4)
+        runs.append((v.get_iterations(), v.get_map(), v.get_nh()))
+        v.close()
+    (Ia, sa), ga, na = runs[0]
+    (Ib, sb), gb, nb = runs[1]
+    assert np.array_equal(Ia, Ib) and np.array_equal(sa, sb)
+    assert np.array_equal(ga, gb) and np.array_equal(na, nb)
