@@ -63,6 +63,34 @@ WORKLOADS = {
 }
 
 
+FILL_SOURCES = ["fill.hip", "sample.hpp", "common.hpp", "families.hpp", "layout.hpp"]
+
+
+def fill_source_hash() -> str:
+    """Hash of the fill kernel's sources: a profiled HBM figure is reported
+    only while it still describes the kernel being timed."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in FILL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2408_09229_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload: str):
+    """HBM bytes per fill launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary in profiles/ (scaled by a device copy of known size), or None
+    when there is none or the kernel changed since it was taken."""
+    import re
+    path = os.path.join(ROOT, "profiles", f"k_fill_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    return rec["traffic_bytes"] if rec.get("source_hash") == fill_source_hash() else None
+
+
 def cpu_baseline(w, budget_evals: int, iters: int):
     import oracle
     ww = w.with_(n_eval=budget_evals, n_iter=iters)
@@ -85,6 +113,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-evals", type=float, default=1.5e7)
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--issue-rates", action="store_true",
+                    help="only measure VALU issue rates of the instruction kinds the path uses")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for scaling HBM counters)")
     args = ap.parse_args()
@@ -94,6 +124,16 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.issue_rates:
+        import ctypes
+        lib = ctypes.CDLL(os.path.join(ROOT, "paper_2408_09229_amd", "libvegas_issue_rates.so"))
+        out = (ctypes.c_double * 6)()
+        torch.cuda.set_device(0)
+        assert lib.vegas_issue_rates(out, 6, ctypes.c_double(2.4), 1024) == 0
+        names = ["fma_f32", "mul+exp2_f32", "mad_u64_u32+xor", "fma_f64", "bitop3", "add_f64+rcp_f64"]
+        print(json.dumps({n: round(v, 3) for n, v in zip(names, out)}))
+        return
 
     import vegas_inputs as vi
     from paper_2408_09229_amd import Vegas, make_config
@@ -147,7 +187,7 @@ def main():
         "config": {"workload": f"{w.name}: {WORKLOADS[w.name]}, {w.n_eval:.0e} evals/iteration",
                    "n_eval": w.n_eval, "dim": w.dim, "n_intervals": w.n_g, "parallelism": "single-gpu"},
         "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
-                     "unit": "T VALU issue-slots/s", "frac": ach / VALU_LANE_OPS_PEAK, "traffic": None,
+                     "unit": "T VALU issue-slots/s", "frac": ach / VALU_LANE_OPS_PEAK, "traffic": profiled_traffic(w.name),
                      "kernel": "k_fill", "kernel_ms": fill_ms},
         "result": {"integral": r.integral, "sigma": math.sqrt(r.sigma2), "chi2_dof": r.chi2_dof,
                    "exact": exact, "z": (r.integral - exact) / math.sqrt(r.sigma2) if r.sigma2 > 0 else None},

@@ -14,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libvegas_hip.so")
+UBENCH_OUT = os.path.join(HERE, "libvegas_issue_rates.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("VEGAS_OFFLOAD_ARCH", "gfx950")
 
@@ -49,6 +50,10 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(OUT + ".tmp", OUT)
+    # instruction issue-rate probe used by bench.py --issue-rates (not the path)
+    ub = _compile("issue_rates.hip", verbose)
+    subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", UBENCH_OUT + ".tmp", ub], check=True)
+    os.replace(UBENCH_OUT + ".tmp", UBENCH_OUT)
     return OUT
 
 
