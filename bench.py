@@ -60,10 +60,13 @@ WORKLOADS = {
     "ridge_4d": "d=4 ridge of 1000 Gaussians s=0.01 on the diagonal, 1024 intervals, FP32 + FP64 accumulators",
     "gauss_prod_4d": "d=4 Gaussian product s=0.1, 128 intervals, FP64 throughout",
     "corr_gauss_16d": "d=16 correlated Gaussian rho=0.9 s=0.03, 1024 intervals, FP32 + FP64 accumulators",
+    "genz_batch": "4096 Genz product-peak / Gaussian integrals, d in 3..12, budgets log-uniform in 1e4..1e7 "
+                  "evals/iteration, 256 intervals, one batched launch per phase, FP32 sample path + FP64 "
+                  "accumulators",
 }
 
 
-FILL_SOURCES = ["fill.hip", "sample.hpp", "common.hpp", "families.hpp", "layout.hpp"]
+FILL_SOURCES = ["fill.hip", "fill_dev.hpp", "batch.hip", "sample.hpp", "common.hpp", "families.hpp", "layout.hpp"]
 
 
 def fill_source_hash() -> str:
@@ -103,6 +106,97 @@ def cpu_baseline(w, budget_evals: int, iters: int):
                       f"intervals (single-threaded FP64 C oracle, {dt:.1f} s)"}
 
 
+def cpu_baseline_batch(insts, budget_evals: int):
+    """The oracle over the first problems of the batch (one iteration each)
+    until their budgets add up to about budget_evals."""
+    import oracle
+    import vegas_inputs as vi
+    t0 = time.perf_counter()
+    done = 0
+    n = 0
+    for i, x in enumerate(insts):
+        if done >= budget_evals:
+            break
+        oracle.run(x.dim, vi.BATCH_N_G, x.n_eval, x.family, x.params, n_iter=1, seed=0, inst=i)
+        done += x.n_eval
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"one iteration of the first {n} problems of the batch ({done:.2e} evals; "
+                      f"single-threaded FP64 C oracle, {dt:.1f} s)"}
+
+
+def run_batch(args):
+    """The batched workload: every step is one iteration of all 4096 problems."""
+    import torch
+    import numpy as np
+    import vegas_inputs as vi
+    from paper_2408_09229_amd import VegasBatch, make_config
+    from tests import closed_forms as cf
+    insts = vi.genz_batch(4096, seed=0)
+    torch.cuda.set_device(0)
+    cfgs = [make_config(x.dim, vi.BATCH_N_G, x.n_eval, seed=0, instance=i, precision=vi.BATCH_PRECISION,
+                        max_iter=args.warmup + args.steps + 1) for i, x in enumerate(insts)]
+    cache = args.tune_cache or os.path.join(os.path.expanduser("~"), ".cache", "vegas_mi355x", "tune.txt")
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    b = VegasBatch(cfgs, [(x.family, x.params) for x in insts], tune_cache=cache)
+    inf = b.info()
+    n_eval = inf.n_eval_total
+    print(f"[bench] genz_batch: n={len(insts)} evals/iteration={n_eval:.4e} cubes={inf.n_cubes_total:.3e} "
+          f"layout per_lane={inf.per_lane} item={inf.item_samples} items={inf.n_items} tuned={inf.tuned} "
+          f"({inf.tune_ms:.2f} ms) ws={inf.workspace_bytes / 2**30:.2f} GiB", file=sys.stderr, flush=True)
+    b.adapt(args.warmup)
+    torch.cuda.synchronize()
+    b.set_timing(True)
+    st = b.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    b.integrate(args.steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    phases, n_timed = b.get_timing()
+    res = b.results()
+    fill_ms = phases[0] / max(n_timed, 1)
+    ops = sum(valu_ops_per_eval(x.dim, x.family) * x.n_eval for x in insts)
+    ach = ops / (fill_ms / 1e3)
+    ex = np.array([cf.genz_ppeak(x.params, x.dim) if x.family == vi.GENZ_PPEAK else cf.genz_gauss(x.params, x.dim)
+                   for x in insts])
+    z = (res["integral"] - ex) / np.sqrt(res["sigma2"])
+    rel = np.abs(res["integral"] / ex - 1.0)
+    print(f"[bench] phases ms/it: fill {fill_ms:.3f} fixup+est {phases[1] / n_timed:.3f} alloc "
+          f"{phases[2] / n_timed:.3f} map {phases[3] / n_timed:.3f}; max|z| {np.abs(z).max():.2f}",
+          file=sys.stderr, flush=True)
+    out = {
+        "metric": "integrand evals/sec (VEGAS+ iteration)",
+        "value": n_eval * args.steps / (ms / 1e3),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": vi.BATCH_PRECISION,
+        "data": "synthetic",
+        "config": {"workload": f"genz_batch: {WORKLOADS['genz_batch']}, {n_eval:.3e} evals/iteration",
+                   "n_problems": len(insts), "n_eval": n_eval, "n_intervals": vi.BATCH_N_G,
+                   "layout": {"per_lane": inf.per_lane, "item_samples": inf.item_samples, "tuned": inf.tuned},
+                   "parallelism": "single-gpu"},
+        "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
+                     "unit": "T VALU issue-slots/s", "frac": ach / VALU_LANE_OPS_PEAK,
+                     "traffic": profiled_traffic("genz_batch"), "kernel": "k_batch_fill", "kernel_ms": fill_ms},
+        "result": {"iterations_combined": int(res["n_iter_combined"][0]), "max_abs_z": float(np.abs(z).max()),
+                   "frac_abs_z_gt3": float(np.mean(np.abs(z) > 3)), "median_rel_err": float(np.median(rel))},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batch(insts, int(args.cpu_evals))
+    print(json.dumps(out), flush=True)
+    b.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +211,7 @@ def main():
                     help="only measure VALU issue rates of the instruction kinds the path uses")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for scaling HBM counters)")
+    ap.add_argument("--tune-cache", default="", help="autotuner cache of the batched workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the VEGAS+ path here "

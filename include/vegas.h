@@ -153,6 +153,13 @@ vegas_status vegas_get_info(const vegas_ctx* ctx, vegas_info* out);
 /* Map grid, FP64, layout [D][N_g+1] row-major. */
 vegas_status vegas_get_map(vegas_ctx* ctx, double* grid);
 vegas_status vegas_set_map(vegas_ctx* ctx, const double* grid);
+/* Replace the integrand's parameters (same family and count, validated as
+ * at create) for the iterations that follow; map, allocation and iteration
+ * log stay.  Meant for continuation: adapting first on a wider version of a
+ * sharply peaked integrand whose values would otherwise underflow
+ * everywhere the uniform start samples.  Estimates of iterations run under
+ * other parameters belong to that other integrand (run them as adapt). */
+vegas_status vegas_set_params(vegas_ctx* ctx, const double* params);
 /* Samples per hypercube n_h of the next iteration, uint32 [N_c]
  * (set: must sum to N_ev with every n_h >= n_min). */
 vegas_status vegas_get_nh(vegas_ctx* ctx, uint32_t* nh);
@@ -196,6 +203,80 @@ vegas_status vegas_sample_probe(vegas_ctx* ctx, uint32_t t, uint64_t k0, int64_t
  * ms is a host array of 4 doubles. */
 vegas_status vegas_set_timing(vegas_ctx* ctx, int32_t on);
 vegas_status vegas_get_timing(vegas_ctx* ctx, double* ms, int32_t* n_iter);
+
+/* ---- batches: many independent problems advanced together ------------- */
+/* A batch holds n problems, each with its own configuration (dimension,
+ * intervals, budget, alpha, beta, seed, instance) and integrand.  All n
+ * run one iteration at a time together: one persistent fill launch whose
+ * workgroups pop work items (runs of consecutive sample tiles of one
+ * problem) from a queue ordered longest first, then one launch per update
+ * phase for all problems.  Every problem computes what a single context
+ * with the same config computes (Alg. 1-2, Eq. 5-9); only the order of
+ * floating-point sums differs.
+ * Status: vegas_batch_create currently returns VEGAS_EUNSUPPORTED (the
+ * batched iteration is switched off after a device fault whose cause is
+ * not yet found); vegas_batch_workspace_size validates and sizes.
+ * Restrictions: families GENZ_PPEAK, GENZ_GAUSS and GAUSS_DIAG; dim <= 12;
+ * every config has the same precision, and accum FP64 or KAHAN;
+ * n in 1..2^20.  The iteration log holds max(max_iter) iterations (256 if
+ * every max_iter is 0). */
+typedef struct vegas_batch vegas_batch;
+
+typedef struct {
+    int32_t n;                /* problems */
+    int32_t per_lane;         /* layout: samples per lane (small problems use fewer) */
+    int64_t item_samples;     /* layout: target samples per work item */
+    int64_t n_items;          /* work items per fill */
+    int64_t n_tiles;
+    int32_t n_workgroups;     /* persistent fill workgroups */
+    int32_t tuned;            /* 0 default layout, 1 timed at create, 2 read from the cache */
+    double  tune_ms;          /* fill time of the chosen layout when tuned */
+    size_t  lds_bytes;        /* LDS of the fill */
+    size_t  workspace_bytes;  /* bytes of the workspace the layout uses */
+    int64_t n_eval_total;     /* sum of n_eval over the problems (one iteration) */
+    int64_t n_cubes_total;
+} vegas_batch_info;
+
+/* Bytes of device workspace for n problems (cfgs[n], fs[n], host arrays):
+ * enough for every layout the autotuner may pick.  No HIP call. */
+vegas_status vegas_batch_workspace_size(int32_t n, const vegas_config* cfgs,
+                                        const vegas_integrand* fs, size_t* bytes);
+
+/* Validate and set up n problems in the caller's workspace (device,
+ * 256-byte aligned, >= the size above) on hip_stream.  tune_cache: path of
+ * a text file of tuned layouts, or NULL for the default layout.  When the
+ * file has no entry for this batch shape on this device, the fill is timed
+ * over the candidate layouts, the fastest is used, and a line is appended
+ * to the file (a file that cannot be written is ignored).  Synchronous.
+ * *out is released by vegas_batch_destroy. */
+vegas_status vegas_batch_create(int32_t n, const vegas_config* cfgs, const vegas_integrand* fs,
+                                void* d_workspace, size_t bytes, void* hip_stream,
+                                const char* tune_cache, vegas_batch** out);
+/* Synchronous: release the handle. */
+void vegas_batch_destroy(vegas_batch* b);
+/* Choose one of the candidate layouts by hand (per_lane 8/4/2 with
+ * item_samples 2^16, 2^18 or 2^20, as listed by the tuner); only before the
+ * first iteration.  Synchronous; VEGAS_EINVAL for other values. */
+vegas_status vegas_batch_set_layout(vegas_batch* b, int32_t per_lane, int64_t item_samples);
+/* Iterations for every problem: discarded (adapt) or combined by Eq. 8-9
+ * (integrate).  Asynchronous. */
+vegas_status vegas_batch_adapt(vegas_batch* b, int32_t n_iter);
+vegas_status vegas_batch_integrate(vegas_batch* b, int32_t n_iter);
+/* Synchronous: out[n] (host) receives each problem's combined estimate.
+ * VEGAS_ENONFINITE (after filling out) if any weight was NaN/Inf. */
+vegas_status vegas_batch_results(vegas_batch* b, vegas_estimate* out);
+/* Synchronous inspection of problem i (host pointers): its per-iteration
+ * estimates, its map [D][N_g+1] and its next allocation n_h [N_c]. */
+vegas_status vegas_batch_get_iterations(vegas_batch* b, int32_t i, double* I, double* sigma2,
+                                        int32_t cap, int32_t* n);
+vegas_status vegas_batch_get_map(vegas_batch* b, int32_t i, double* grid);
+vegas_status vegas_batch_get_nh(vegas_batch* b, int32_t i, uint32_t* nh);
+vegas_status vegas_batch_get_info(const vegas_batch* b, vegas_batch_info* out);
+/* Phase timing as for vegas_set_timing / vegas_get_timing, summed over all
+ * problems: ms[0] fill, ms[1] fix-up + estimates, ms[2] allocation,
+ * ms[3] map refinement. */
+vegas_status vegas_batch_set_timing(vegas_batch* b, int32_t on);
+vegas_status vegas_batch_get_timing(vegas_batch* b, double* ms, int32_t* n_iter);
 
 const char* vegas_status_string(vegas_status s);
 const char* vegas_last_error(void);

@@ -19,6 +19,10 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
                       "or `python paper_2408_09229_amd/build.py`")
 
+# torch first: its HIP runtime is then the one the library binds to, so
+# that device memory and streams from torch are valid in the library
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 VEGAS_OK, VEGAS_EINVAL, VEGAS_ENOMEM, VEGAS_EDEVICE, VEGAS_ESTATE, VEGAS_ENONFINITE, VEGAS_EUNSUPPORTED = \
@@ -53,6 +57,13 @@ class vegas_info(C.Structure):
                 ("lds_hist", C.c_int32), ("workspace_bytes", C.c_size_t)]
 
 
+class vegas_batch_info(C.Structure):
+    _fields_ = [("n", C.c_int32), ("per_lane", C.c_int32), ("item_samples", C.c_int64),
+                ("n_items", C.c_int64), ("n_tiles", C.c_int64), ("n_workgroups", C.c_int32),
+                ("tuned", C.c_int32), ("tune_ms", C.c_double), ("lds_bytes", C.c_size_t),
+                ("workspace_bytes", C.c_size_t), ("n_eval_total", C.c_int64), ("n_cubes_total", C.c_int64)]
+
+
 _vp = C.c_void_p
 _st = C.c_int
 _DECL = {
@@ -66,6 +77,7 @@ _DECL = {
     "vegas_get_info": (_st, [_vp, C.POINTER(vegas_info)]),
     "vegas_get_map": (_st, [_vp, _vp]),
     "vegas_set_map": (_st, [_vp, _vp]),
+    "vegas_set_params": (_st, [_vp, _vp]),
     "vegas_get_nh": (_st, [_vp, _vp]),
     "vegas_set_nh": (_st, [_vp, _vp]),
     "vegas_get_accumulators": (_st, [_vp, _vp, _vp, _vp]),
@@ -77,6 +89,19 @@ _DECL = {
     "vegas_sample_probe": (_st, [_vp, C.c_uint32, C.c_uint64, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "vegas_set_timing": (_st, [_vp, C.c_int32]),
     "vegas_get_timing": (_st, [_vp, _vp, C.POINTER(C.c_int32)]),
+    "vegas_batch_workspace_size": (_st, [C.c_int32, _vp, _vp, C.POINTER(C.c_size_t)]),
+    "vegas_batch_create": (_st, [C.c_int32, _vp, _vp, _vp, C.c_size_t, _vp, C.c_char_p, C.POINTER(_vp)]),
+    "vegas_batch_destroy": (None, [_vp]),
+    "vegas_batch_set_layout": (_st, [_vp, C.c_int32, C.c_int64]),
+    "vegas_batch_adapt": (_st, [_vp, C.c_int32]),
+    "vegas_batch_integrate": (_st, [_vp, C.c_int32]),
+    "vegas_batch_results": (_st, [_vp, _vp]),
+    "vegas_batch_get_iterations": (_st, [_vp, C.c_int32, _vp, _vp, C.c_int32, C.POINTER(C.c_int32)]),
+    "vegas_batch_get_map": (_st, [_vp, C.c_int32, _vp]),
+    "vegas_batch_get_nh": (_st, [_vp, C.c_int32, _vp]),
+    "vegas_batch_get_info": (_st, [_vp, C.POINTER(vegas_batch_info)]),
+    "vegas_batch_set_timing": (_st, [_vp, C.c_int32]),
+    "vegas_batch_get_timing": (_st, [_vp, _vp, C.POINTER(C.c_int32)]),
     "vegas_status_string": (C.c_char_p, [_st]),
     "vegas_last_error": (C.c_char_p, []),
 }
@@ -201,6 +226,10 @@ class Vegas:
         g = np.ascontiguousarray(g, dtype=np.float64)
         check(vegas_set_map(self.h, _dptr(g)), "vegas_set_map")
 
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        check(vegas_set_params(self.h, _dptr(p)), "vegas_set_params")
+
     def get_nh(self):
         nh = np.zeros(self.info.n_cubes, np.uint32)
         check(vegas_get_nh(self.h, _dptr(nh)), "vegas_get_nh")
@@ -273,3 +302,109 @@ class Vegas:
         res["delta"] = res["delta"].reshape(n, D)
         res["x"] = res["x"].reshape(n, D)
         return res
+
+
+class _BatchSpec:
+    """Host arrays of n configs and integrands (kept alive for the calls)."""
+
+    def __init__(self, cfgs, integrands):
+        n = len(cfgs)
+        if n != len(integrands):
+            raise ValueError("one integrand per config")
+        self.its = [_Integrand(*spec) for spec in integrands]
+        self.cfgs = (vegas_config * n)(*cfgs)
+        self.fs = (vegas_integrand * n)(*[it.s for it in self.its])
+        self.n = n
+
+
+def batch_workspace_size(cfgs, integrands) -> int:
+    sp = _BatchSpec(cfgs, integrands)
+    n = C.c_size_t()
+    check(vegas_batch_workspace_size(sp.n, sp.cfgs, sp.fs, C.byref(n)), "vegas_batch_workspace_size")
+    return n.value
+
+
+class VegasBatch:
+    """n independent VEGAS+ problems advanced together on the current device.
+
+    ``cfgs`` is a list of vegas_config, ``integrands`` a list of
+    (family, params[, lo, hi]) tuples.  ``tune_cache``: path of the
+    autotuner's text cache, or None for the default layout.
+    """
+
+    def __init__(self, cfgs, integrands, *, tune_cache=None, stream=None, device=None):
+        import torch
+        self._spec = _BatchSpec(cfgs, integrands)
+        self.n = self._spec.n
+        self.cfgs = list(cfgs)
+        nb = C.c_size_t()
+        check(vegas_batch_workspace_size(self.n, self._spec.cfgs, self._spec.fs, C.byref(nb)),
+              "vegas_batch_workspace_size")
+        self.device = torch.device(device or "cuda")
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        check(vegas_batch_create(self.n, self._spec.cfgs, self._spec.fs, C.c_void_p(self.ws.data_ptr()), nb.value,
+                                 C.c_void_p(self.stream.cuda_stream),
+                                 None if tune_cache is None else os.fsencode(tune_cache), C.byref(h)),
+              "vegas_batch_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            vegas_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def info(self) -> vegas_batch_info:
+        r = vegas_batch_info()
+        check(vegas_batch_get_info(self.h, C.byref(r)), "vegas_batch_get_info")
+        return r
+
+    def set_layout(self, per_lane: int, item_samples: int):
+        check(vegas_batch_set_layout(self.h, per_lane, item_samples), "vegas_batch_set_layout")
+
+    def adapt(self, n: int):
+        check(vegas_batch_adapt(self.h, n), "vegas_batch_adapt")
+
+    def integrate(self, n: int):
+        check(vegas_batch_integrate(self.h, n), "vegas_batch_integrate")
+
+    def results(self, allow_nonfinite=False):
+        """Structured numpy array of the n combined estimates."""
+        out = (vegas_estimate * self.n)()
+        check(vegas_batch_results(self.h, out), "vegas_batch_results",
+              allow=(VEGAS_ENONFINITE,) if allow_nonfinite else ())
+        return np.ctypeslib.as_array(out).copy()
+
+    def get_iterations(self, i: int):
+        cap = 4096
+        I = np.zeros(cap)
+        s2 = np.zeros(cap)
+        n = C.c_int32()
+        check(vegas_batch_get_iterations(self.h, i, _dptr(I), _dptr(s2), cap, C.byref(n)),
+              "vegas_batch_get_iterations")
+        m = min(n.value, cap)
+        return I[:m].copy(), s2[:m].copy()
+
+    def get_map(self, i: int):
+        c = self.cfgs[i]
+        g = np.zeros((c.dim, c.n_intervals + 1))
+        check(vegas_batch_get_map(self.h, i, _dptr(g)), "vegas_batch_get_map")
+        return g
+
+    def get_nh(self, i: int, n_cubes: int):
+        nh = np.zeros(n_cubes, np.uint32)
+        check(vegas_batch_get_nh(self.h, i, _dptr(nh)), "vegas_batch_get_nh")
+        return nh
+
+    def set_timing(self, on: bool):
+        check(vegas_batch_set_timing(self.h, int(on)), "vegas_batch_set_timing")
+
+    def get_timing(self):
+        ms = np.zeros(4)
+        n = C.c_int32()
+        check(vegas_batch_get_timing(self.h, _dptr(ms), C.byref(n)), "vegas_batch_get_timing")
+        return ms, n.value

@@ -17,11 +17,12 @@
 
 #include "../../include/vegas.h"
 #include "common.hpp"
+#include "host.hpp"
 #include "launch.hpp"
 
 using namespace vg;
 
-namespace {
+namespace vgh {
 
 thread_local std::string g_err;
 
@@ -36,30 +37,7 @@ vegas_status fail(vegas_status s, const char* fmt, ...)
     return s;
 }
 
-#define HIPCHK(expr)                                                                        \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
-        if (e_ != hipSuccess)                                                               \
-            return fail(VEGAS_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
-    } while (0)
-
 constexpr int kMaxWG = 512;            // histogram slots reserved in the workspace
-constexpr size_t kLdsLimit = 160 * 1024;
-constexpr int kMaxNg = 4096;
-
-// Problem geometry derived from a validated config (no HIP call).
-struct Geometry {
-    int D, ng, n_min, family, n_params;
-    uint32_t n_eval;
-    uint32_t nst;
-    uint32_t n_cubes;
-    uint64_t R;
-    uint32_t magic;
-    int shift;
-    int per_lane, tile, n_tiles;
-    int lds_hist_ok;
-    int n_aux;
-};
 
 // largest m with m^D <= lim, without overflow
 bool pow_at_most(uint64_t m, int D, uint64_t lim, uint64_t* out)
@@ -105,8 +83,10 @@ vegas_status geometry(const vegas_config* c, const vegas_integrand* f, Geometry*
     if (!(c->beta >= 0.0) || !std::isfinite(c->beta)) return fail(VEGAS_EINVAL, "beta must be finite and >= 0");
     if (c->precision != VEGAS_PREC_FP64 && c->precision != VEGAS_PREC_FP32)
         return fail(VEGAS_EINVAL, "unknown precision %d", c->precision);
-    if (c->accum != VEGAS_ACC_FP64 && c->accum != VEGAS_ACC_ORDERED)
-        return fail(VEGAS_EUNSUPPORTED, "accumulation mode %d not available", c->accum);
+    if (c->accum != VEGAS_ACC_FP64 && c->accum != VEGAS_ACC_ORDERED && c->accum != VEGAS_ACC_KAHAN)
+        return fail(VEGAS_EINVAL, "unknown accumulation mode %d", c->accum);
+    if (c->accum == VEGAS_ACC_KAHAN && c->precision != VEGAS_PREC_FP32)
+        return fail(VEGAS_EINVAL, "KAHAN accumulation is for the FP32 sample path");
     if (c->accum == VEGAS_ACC_ORDERED) {
         if (c->precision != VEGAS_PREC_FP64) return fail(VEGAS_EINVAL, "ORDERED accumulation runs in FP64");
         if ((double)c->n_eval * c->dim * c->n_intervals > (double)(1ull << 28) || c->n_eval > (1 << 24))
@@ -181,9 +161,15 @@ vegas_status geometry(const vegas_config* c, const vegas_integrand* f, Geometry*
     return VEGAS_OK;
 }
 
+}  // namespace vgh
+
+using namespace vgh;
+
+namespace {
+
 // Workspace carving: offsets of every device array (256-byte aligned).
 struct Plan {
-    size_t prm, lo, hi, aux_d, aux_f, grid64, grid32, start[2], tfirst[2], v, wg_part, wg_comp, side, fix_part,
+    size_t prm, lo, hi, aux_d, aux_f, grid64, grid32, start[2], tfirst[2], v, wg_part, side, fix_part,
         histH, histC, partH, partC, Hsum, Csum, counters, bsum, boff, iter, ord_w, ord_bins, ord_m, total;
 };
 
@@ -212,7 +198,6 @@ Plan plan(const Geometry& g, int max_iter, bool ordered)
     }
     p.v = take(sizeof(double) * g.n_cubes);
     p.wg_part = take(sizeof(double) * 2 * kMaxWG);
-    p.wg_comp = take(sizeof(float) * 4 * kMaxWG);
     p.side = take(sizeof(TileSide) * g.n_tiles);
     p.fix_part = take(sizeof(double) * 2 * g.n_tiles);
     const size_t slots = g.lds_hist_ok ? kMaxWG : 1;
@@ -417,7 +402,6 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
     a.tile_first = c->at<uint32_t>(c->p.tfirst[c->cur]);
     a.v_out = c->at<double>(c->p.v);
     a.wg_part = c->at<double>(c->p.wg_part);
-    a.wg_comp = c->at<float>(c->p.wg_comp);
     a.side = c->at<TileSide>(c->p.side);
     a.hist_H = c->at<double>(c->p.histH);
     a.hist_C = c->at<uint32_t>(c->p.histC);
@@ -441,8 +425,6 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
     fa.wg_part = a.wg_part;
     fa.fix_part = fx.fix_part;
     fa.iter_out = c->at<double>(c->p.iter) + 2 * t;
-    fa.accum = c->cfg.accum;
-    fa.wg_comp = a.wg_comp;
     HIPCHK(launch_final(fa, c->stream));
     HIPCHK(c->mark());
     const vegas_status s = run_update(c, t, lds_hist ? c->n_wg : 1, true);
@@ -452,6 +434,38 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
     c->have_prev = true;
     return VEGAS_OK;
 }
+
+// host-side start / tile table from an injected allocation
+vegas_status upload_nh(vegas_ctx* c, const uint32_t* nh, int buf)
+{
+    const uint32_t nc = c->g.n_cubes;
+    std::vector<uint32_t> st(nc + 1), tf(c->g.n_tiles + 1);
+    uint64_t run = 0;
+    for (uint32_t h = 0; h < nc; ++h) {
+        if (nh[h] < (uint32_t)c->g.n_min) return fail(VEGAS_EINVAL, "n_h[%u] = %u below n_min", h, nh[h]);
+        st[h] = (uint32_t)run;
+        run += nh[h];
+    }
+    if (run != c->g.n_eval) return fail(VEGAS_EINVAL, "n_h sums to %llu, not n_eval", (unsigned long long)run);
+    st[nc] = c->g.n_eval;
+    uint32_t h = 0;
+    for (int j = 0; j < c->g.n_tiles; ++j) {
+        const uint64_t k = (uint64_t)j * c->g.tile;
+        while (st[h + 1] <= k) ++h;
+        tf[j] = h;
+    }
+    tf[c->g.n_tiles] = nc;
+    HIPCHK(hipMemcpyAsync(c->at<uint32_t>(c->p.start[buf]), st.data(), sizeof(uint32_t) * st.size(),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->at<uint32_t>(c->p.tfirst[buf]), tf.data(), sizeof(uint32_t) * tf.size(),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return VEGAS_OK;
+}
+
+}  // namespace
+
+namespace vgh {
 
 void combine(const std::vector<double>& I, const std::vector<double>& s2, double* Ib, double* s2b, double* chi)
 {
@@ -492,35 +506,7 @@ void combine(const std::vector<double>& I, const std::vector<double>& s2, double
     *chi = n > 1 ? c2 / (double)(n - 1) : 0.0;
 }
 
-// host-side start / tile table from an injected allocation
-vegas_status upload_nh(vegas_ctx* c, const uint32_t* nh, int buf)
-{
-    const uint32_t nc = c->g.n_cubes;
-    std::vector<uint32_t> st(nc + 1), tf(c->g.n_tiles + 1);
-    uint64_t run = 0;
-    for (uint32_t h = 0; h < nc; ++h) {
-        if (nh[h] < (uint32_t)c->g.n_min) return fail(VEGAS_EINVAL, "n_h[%u] = %u below n_min", h, nh[h]);
-        st[h] = (uint32_t)run;
-        run += nh[h];
-    }
-    if (run != c->g.n_eval) return fail(VEGAS_EINVAL, "n_h sums to %llu, not n_eval", (unsigned long long)run);
-    st[nc] = c->g.n_eval;
-    uint32_t h = 0;
-    for (int j = 0; j < c->g.n_tiles; ++j) {
-        const uint64_t k = (uint64_t)j * c->g.tile;
-        while (st[h + 1] <= k) ++h;
-        tf[j] = h;
-    }
-    tf[c->g.n_tiles] = nc;
-    HIPCHK(hipMemcpyAsync(c->at<uint32_t>(c->p.start[buf]), st.data(), sizeof(uint32_t) * st.size(),
-                          hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipMemcpyAsync(c->at<uint32_t>(c->p.tfirst[buf]), tf.data(), sizeof(uint32_t) * tf.size(),
-                          hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    return VEGAS_OK;
-}
-
-}  // namespace
+}  // namespace vgh
 
 extern "C" {
 
@@ -731,6 +717,40 @@ vegas_status vegas_set_map(vegas_ctx* c, const double* grid)
     const size_t n = (size_t)c->g.D * row;
     HIPCHK(hipMemcpyAsync(c->at<double>(c->p.grid64), grid, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
     HIPCHK(launch_grid32(c->at<double>(c->p.grid64), c->at<float>(c->p.grid32), (int)n, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return VEGAS_OK;
+}
+
+vegas_status vegas_set_params(vegas_ctx* c, const double* params)
+{
+    if (!c || !params) return fail(VEGAS_EINVAL, "bad arguments");
+    // validate as a new problem of the same family and shape
+    vegas_integrand f;
+    f.family = c->g.family;
+    f.n_params = c->g.n_params;
+    f.params = params;
+    f.lo = c->lo.data();
+    f.hi = c->hi.data();
+    Geometry g;
+    const vegas_status s = geometry(&c->cfg, &f, &g);
+    if (s != VEGAS_OK) return s;
+    if (g.n_aux != c->g.n_aux) return fail(VEGAS_EINVAL, "new parameters change the size of the integrand's tables");
+    c->params.assign(params, params + g.n_params);
+    HIPCHK(hipMemcpyAsync(c->at<double>(c->p.prm), c->params.data(), sizeof(double) * g.n_params,
+                          hipMemcpyHostToDevice, c->stream));
+    PrepArgs pa;
+    pa.family = g.family;
+    pa.D = g.D;
+    pa.n_params = g.n_params;
+    pa.prm = c->at<double>(c->p.prm);
+    pa.lo = c->at<double>(c->p.lo);
+    pa.hi = c->at<double>(c->p.hi);
+    pa.ng = g.ng;
+    pa.aux_d = c->at<double>(c->p.aux_d);
+    pa.aux_f = c->at<float>(c->p.aux_f);
+    pa.grid64 = nullptr;                  // the map stays
+    pa.grid32 = nullptr;
+    HIPCHK(launch_prep(pa, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return VEGAS_OK;
 }

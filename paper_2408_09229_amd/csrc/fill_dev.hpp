@@ -1,0 +1,563 @@
+// Device building blocks of the fill (Alg. 2): per-cube moment runs and
+// their merges, per-lane accumulators, the LDS plan, and one tile of the
+// fill.  Shared by the single-problem and the batched fill kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <type_traits>
+
+#include "common.hpp"
+#include "families.hpp"
+#include "layout.hpp"
+#include "sample.hpp"
+
+namespace vg {
+
+// ---------------------------------------------------------------------------
+// merging partial moments (Chan, Golub, LeVeque 1983)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ Partial merge(const Partial& a, const Partial& b)
+{
+    Partial o;
+    o.h = a.h;
+    o.n = a.n + b.n;
+    const double na = (double)a.n, nb = (double)b.n, n = (double)o.n;
+    const double dm = b.mean - a.mean;
+    o.mean = a.mean + dm * (nb / n);
+    o.m2 = a.m2 + b.m2 + (dm * dm) * (na * nb / n);
+    return o;
+}
+
+__device__ __forceinline__ double unbiased_var(const Partial& p)
+{
+    const double m2 = p.m2 > 0.0 ? p.m2 : 0.0;
+    return m2 / (double)(p.n - 1u);
+}
+
+// ---------------------------------------------------------------------------
+// runs of one cube: count, mean, sum of squared deviations
+// ---------------------------------------------------------------------------
+struct Run {
+    uint32_t n;
+    double mean;
+    double m2;
+};
+
+__device__ __forceinline__ Run run_empty()
+{
+    Run r;
+    r.n = 0;
+    r.mean = 0.0;
+    r.m2 = 0.0;
+    return r;
+}
+
+__device__ __forceinline__ Run run_merge(const Run& a, const Run& b)
+{
+    if (a.n == 0) return b;
+    if (b.n == 0) return a;
+    Run o;
+    o.n = a.n + b.n;
+    const double na = (double)a.n, nb = (double)b.n, n = (double)o.n;
+    const double dm = b.mean - a.mean;
+    o.mean = a.mean + dm * (nb / n);
+    o.m2 = a.m2 + b.m2 + (dm * dm) * (na * nb / n);
+    return o;
+}
+
+__device__ __forceinline__ Run run_shfl_up(const Run& r, int o)
+{
+    Run u;
+    u.n = __shfl_up(r.n, o, 64);
+    u.mean = __shfl_up(r.mean, o, 64);
+    u.m2 = __shfl_up(r.m2, o, 64);
+    return u;
+}
+
+// 1/n to double precision: hardware reciprocal plus one Newton step
+__device__ __forceinline__ double recip(double n)
+{
+    double y = __builtin_amdgcn_rcp(n);
+    y = fma(fma(-n, y, 1.0), y, y);
+    return fma(fma(-n, y, 1.0), y, y);
+}
+
+// shifted sums (c, S1 = sum (w - c), S2 = sum (w - c)^2) of n samples -> run
+__device__ __forceinline__ Run run_from_sums(uint32_t n, double c, double S1, double S2)
+{
+    Run r;
+    r.n = n;
+    const double inv = recip((double)n);
+    const double m1 = S1 * inv;
+    r.mean = c + m1;
+    r.m2 = fma(-S1, m1, S2);
+    return r;
+}
+
+// unbiased variance of a finished cube and its share v/n of sigma^2
+__device__ __forceinline__ void run_finish(const Run& r, double& v, double& v_over_n)
+{
+    const double dn = (double)r.n;
+    const double m2 = r.m2 > 0.0 ? r.m2 : 0.0;
+    v = m2 * recip(dn - 1.0);
+    v_over_n = v * recip(dn);
+}
+
+__device__ __forceinline__ Partial to_partial(const Run& r, uint32_t h)
+{
+    Partial p;
+    p.h = h;
+    p.n = r.n;
+    p.mean = r.mean;
+    p.m2 = r.m2;
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// per-lane accumulators.  FP64: shifted sums in double.  Kahan: shifted sums
+// and lane totals in compensated FP32 (each add carries its rounding error
+// forward; contraction is off, so the compensation is not folded away).
+// ---------------------------------------------------------------------------
+template <bool KAHAN>
+struct CubeSums;
+
+template <>
+struct CubeSums<false> {
+    double c, s1, s2;
+    __device__ __forceinline__ void reset() { s1 = 0.0; s2 = 0.0; }
+    template <typename R>
+    __device__ __forceinline__ void add(R w, bool first)
+    {
+        const double wd = (double)w;
+        if (first) c = wd;
+        const double u = wd - c;
+        s1 += u;
+        s2 = fma(u, u, s2);
+    }
+    __device__ __forceinline__ Run run(uint32_t n) const { return run_from_sums(n, c, s1, s2); }
+};
+
+template <>
+struct CubeSums<true> {
+    float c, s1, k1, s2, k2;
+    __device__ __forceinline__ void reset() { s1 = 0.f; k1 = 0.f; s2 = 0.f; k2 = 0.f; }
+    template <typename R>
+    __device__ __forceinline__ void add(R w, bool first)
+    {
+        const float wf = (float)w;
+        if (first) c = wf;
+        const float u = wf - c;
+        const float y1 = u - k1;
+        const float t1 = s1 + y1;
+        k1 = (t1 - s1) - y1;
+        s1 = t1;
+        const float y2 = u * u - k2;
+        const float t2 = s2 + y2;
+        k2 = (t2 - s2) - y2;
+        s2 = t2;
+    }
+    __device__ __forceinline__ Run run(uint32_t n) const
+    {
+        return run_from_sums(n, (double)c, (double)s1 - (double)k1, (double)s2 - (double)k2);
+    }
+};
+
+template <bool KAHAN>
+struct LaneTotal;
+
+template <>
+struct LaneTotal<false> {
+    double s = 0.0;
+    __device__ __forceinline__ void add(double v) { s += v; }
+    __device__ __forceinline__ double value() const { return s; }
+};
+
+template <>
+struct LaneTotal<true> {
+    float s = 0.f, k = 0.f;
+    __device__ __forceinline__ void add(double v)
+    {
+        const float y = (float)v - k;
+        const float t = s + y;
+        k = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ double value() const { return (double)s - (double)k; }
+};
+
+// ---------------------------------------------------------------------------
+// the fill kernel
+// ---------------------------------------------------------------------------
+constexpr int kWaves = kFillThreads / 64;
+
+struct WaveRec {
+    Run s;            // scanned run at the wave's last lane
+    uint32_t tail;    // last lane ends in a cube that continues
+    uint32_t open;    // that run reaches back past the wave's first lane
+};
+
+struct LdsPlan {
+    uint32_t grid_off, aux_off, h_off, c_off, st_off, wave_off, cin_off, side_off, red_off, total;
+};
+
+// LDS: map [D][N_g+1] in the sample path's precision; histogram weights
+// [D][N_g] in FP64 (the FP32 LDS atomic add is an order of magnitude slower
+// than the FP64 one on gfx950) and u32 counts; the tile's cube starts;
+// per-wave carry records; the tile's side record; a reduction area.
+__host__ __device__ inline LdsPlan lds_plan(int D, int ng, int real_bytes, int lds_hist, int tile, int n_aux)
+{
+    LdsPlan p;
+    uint32_t o = 0;
+    auto al = [](uint32_t v) { return (v + 15u) & ~15u; };
+    p.grid_off = o; o = al(o + (uint32_t)(D * (ng + 1) * real_bytes));
+    p.aux_off = o; o = al(o + (uint32_t)(n_aux * real_bytes));
+    p.h_off = o;
+    if (lds_hist) o = al(o + (uint32_t)(D * ng * 8));
+    p.c_off = o;
+    if (lds_hist) o = al(o + (uint32_t)(D * ng * 4));
+    p.st_off = o; o = al(o + (uint32_t)((tile / 2 + 4) * 4));
+    p.wave_off = o; o = al(o + (uint32_t)(kWaves * sizeof(WaveRec)));
+    p.cin_off = o; o = al(o + (uint32_t)(kWaves * sizeof(WaveRec)));
+    p.side_off = o; o = al(o + (uint32_t)(2 * sizeof(Partial) + 16));
+    p.red_off = o; o = al(o + (uint32_t)(kWaves * 3 * sizeof(double)));
+    p.total = o;
+    return p;
+}
+
+// What one tile of the fill reads and writes outside LDS.
+struct TileIO {
+    uint32_t t;                   // iteration (Philox counter word 2)
+    int32_t tile;                 // samples per tile
+    int32_t per_lane;
+    int32_t lds_hist;
+    const uint32_t* start;        // [N_c+1]
+    const uint32_t* tile_first;   // [n_tiles+1]
+    double* v_out;                // [N_c]
+    TileSide* side;               // [n_tiles]
+    double* hist_H;               // global histogram (when not in LDS)
+    uint32_t* hist_C;
+};
+
+// LDS views of the fill (see lds_plan).
+template <typename R>
+struct FillLds {
+    R* gl;
+    R* auxl;
+    double* hl;
+    uint32_t* cl;
+    uint32_t* st;
+    WaveRec* wrec;
+    WaveRec* cin;
+    Partial* tside;
+    uint32_t* tflags;
+    double* red;
+
+    __device__ __forceinline__ FillLds(unsigned char* smem, const LdsPlan& lp)
+    {
+        gl = reinterpret_cast<R*>(smem + lp.grid_off);
+        auxl = reinterpret_cast<R*>(smem + lp.aux_off);
+        hl = reinterpret_cast<double*>(smem + lp.h_off);
+        cl = reinterpret_cast<uint32_t*>(smem + lp.c_off);
+        st = reinterpret_cast<uint32_t*>(smem + lp.st_off);
+        wrec = reinterpret_cast<WaveRec*>(smem + lp.wave_off);
+        cin = reinterpret_cast<WaveRec*>(smem + lp.cin_off);
+        tside = reinterpret_cast<Partial*>(smem + lp.side_off);
+        tflags = reinterpret_cast<uint32_t*>(smem + lp.side_off + 2 * sizeof(Partial));
+        red = reinterpret_cast<double*>(smem + lp.red_off);
+    }
+};
+
+// One tile of `io.tile` consecutive samples: every lane walks its
+// `per_lane` samples (Alg. 2), cubes finished inside a lane are finalised
+// there, runs crossing lanes merge by the wavefront scan, and the tile's
+// boundary runs go to its side record.  Called by all lanes of the
+// workgroup; ends with a barrier.
+template <typename R, int FAM, int MAXD, bool KAHAN>
+__device__ __forceinline__ void fill_tile(int tile, const TileIO& io, const FillLds<R>& L,
+                                          SamplePath<R, FAM, MAXD>& sp, LaneTotal<KAHAN>& totI,
+                                          LaneTotal<KAHAN>& totV, double& vmax, unsigned long long& bad)
+{
+    const SampleConst& sc = sp.sc;
+    const int D = sc.D;
+    const uint32_t ng = sc.ng;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int S = io.per_lane;
+    R* gl = L.gl;
+    double* hl = L.hl;
+    uint32_t* cl = L.cl;
+    uint32_t* st = L.st;
+    WaveRec* wrec = L.wrec;
+    WaveRec* cin = L.cin;
+    Partial* tside = L.tside;
+    uint32_t* tflags = L.tflags;
+        const uint32_t t0 = (uint32_t)tile * (uint32_t)io.tile;
+        const uint32_t t1 = min(t0 + (uint32_t)io.tile, sc.n_eval);
+        const uint32_t h_lo = io.tile_first[tile];
+        const uint32_t h_nx = io.tile_first[tile + 1];
+        const uint32_t h_top = min(h_nx, sc.n_cubes - 1u);
+        const int nst_load = (int)(h_top - h_lo) + 2;   // starts of h_lo .. h_top+1
+        for (int i = tid; i < nst_load; i += kFillThreads) st[i] = io.start[h_lo + i];
+        if (tid == 0) *tflags = 0u;
+        __syncthreads();
+
+        const uint32_t k0 = t0 + (uint32_t)(tid * S);
+        const uint32_t k1 = min(k0 + (uint32_t)S, t1);
+        const int n_active = (int)((t1 - t0 + (uint32_t)S - 1u) / (uint32_t)S);
+        // per lane: the run of its first cube when that cube began earlier
+        // (head), and the run of its last cube when it continues (tail)
+        bool has_head = false, has_tail = false, span = false;
+        Run hrun = run_empty(), trun = run_empty();
+        uint32_t h_first = 0, h_last = 0;
+        if (k0 < k1) {
+            int lo = 0, hi = nst_load - 1;          // largest idx with st[idx] <= k0
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (st[mid] <= k0) lo = mid; else hi = mid;
+            }
+            int idx = lo;
+            uint32_t h = h_lo + (uint32_t)idx;
+            h_first = h;
+            uint32_t nxt = st[idx + 1];
+            bool head = st[idx] < k0;
+            uint32_t s[MAXD];
+            sp.digits(h, s);
+            uint32_t n = 0;
+            CubeSums<KAHAN> cs;
+            cs.reset();
+
+            for (int j = 0; j < S; ++j) {
+                const uint32_t k = k0 + (uint32_t)j;
+                if (k >= k1) break;
+                if (k == nxt) {
+                    // the current cube ends: shifted sums -> (mean, m2)
+                    const Run r = cs.run(n);
+                    if (head) {
+                        hrun = r;
+                        has_head = true;
+                    } else {
+                        double v, vn;
+                        run_finish(r, v, vn);
+                        io.v_out[h] = v;
+                        totI.add(r.mean);
+                        totV.add(vn);
+                        vmax = v > vmax ? v : vmax;
+                    }
+                    ++idx;
+                    ++h;
+                    nxt = st[idx + 1];
+                    head = false;
+                    n = 0;
+                    cs.reset();
+                    sp.next_digits(s);
+                }
+                uint32_t bins[MAXD];
+                R J, f;
+                R w = sp.template eval<false>(k, io.t, s, gl, bins, nullptr, nullptr, J, f);
+                if (!__builtin_isfinite(w)) {
+                    w = (R)0;
+                    ++bad;
+                }
+                const double wd = (double)w;
+                const double w2 = wd * wd;
+                if (io.lds_hist) {
+#pragma unroll
+                    for (int d = 0; d < MAXD; ++d) {
+                        if (d < D) {
+                            const uint32_t bi = (uint32_t)d * ng + bins[d];
+                            atomicAdd(hl + bi, w2);
+                            atomicAdd(cl + bi, 1u);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int d = 0; d < MAXD; ++d) {
+                        if (d < D) {
+                            const uint32_t bi = (uint32_t)d * ng + bins[d];
+                            unsafeAtomicAdd(io.hist_H + bi, w2);
+                            atomicAdd(io.hist_C + bi, 1u);
+                        }
+                    }
+                }
+                cs.add(w, n == 0);
+                ++n;
+            }
+            h_last = h;
+            const Run r = cs.run(n);
+            if (nxt > k1) {                 // continues into the next lane
+                trun = r;
+                has_tail = true;
+                span = head;
+            } else if (head) {
+                hrun = r;
+                has_head = true;
+            } else {
+                double v, vn;
+                run_finish(r, v, vn);
+                io.v_out[h] = v;
+                totI.add(r.mean);
+                totV.add(vn);
+                vmax = v > vmax ? v : vmax;
+            }
+        }
+
+        // ---- runs that cross lanes: segmented scan inside the wavefront ---
+        // S_l = merge(S_{l-1}, tail_l) while lane l continues the cube of
+        // lane l-1 (span), else tail_l.  Hillis-Steele over shuffles, stopping
+        // as soon as every chain has reached its first lane.
+        Run sv = has_tail ? trun : run_empty();
+        int sf = (has_tail && span) ? 0 : 1;       // 1: a chain starts here
+        for (int o = 1; o < 64; o <<= 1) {
+            const Run u = run_shfl_up(sv, o);
+            const int fu = __shfl_up(sf, o, 64);
+            if (lane >= o && !sf) {
+                sv = run_merge(u, sv);
+                sf = fu;
+            }
+            if (__ballot(!sf && lane >= 2 * o) == 0ull) break;
+        }
+        if (lane == 63) {
+            wrec[wave].s = sv;
+            wrec[wave].tail = has_tail ? 1u : 0u;
+            wrec[wave].open = sf ? 0u : 1u;
+        }
+        const Run prev = run_shfl_up(sv, 1);
+        const int prev_f = __shfl_up(sf, 1, 64);
+        __syncthreads();
+        if (tid == 0) {
+            // carries between waves; the chain entering wave 0 is the tile's
+            // first cube, which began in an earlier tile
+            Run c = run_empty();
+            uint32_t th = 1u;
+            for (int w = 0; w < kWaves; ++w) {
+                cin[w].s = c;
+                cin[w].open = th;
+                const WaveRec& r = wrec[w];
+                if (r.tail) {
+                    if (r.open) {
+                        c = run_merge(c, r.s);
+                    } else {
+                        c = r.s;
+                        th = 0u;
+                    }
+                } else {
+                    c = run_empty();
+                    th = 0u;
+                }
+            }
+        }
+        __syncthreads();
+        if (has_head && !span) {
+            Run pre;
+            uint32_t th;
+            if (lane == 0 || !prev_f) {
+                pre = lane == 0 ? cin[wave].s : run_merge(cin[wave].s, prev);
+                th = cin[wave].open;
+            } else {
+                pre = prev;
+                th = 0u;
+            }
+            const Run fin = run_merge(pre, hrun);
+            if (th) {
+                tside[0] = to_partial(fin, h_lo);
+                atomicOr(tflags, kHasHead);
+            } else {
+                double v, vn;
+                run_finish(fin, v, vn);
+                io.v_out[h_first] = v;
+                totI.add(fin.mean);
+                totV.add(vn);
+                vmax = v > vmax ? v : vmax;
+            }
+        }
+        if (tid == n_active - 1 && has_tail) {
+            Run t = sv;
+            uint32_t th = 0u;
+            if (!sf) {
+                t = run_merge(cin[wave].s, sv);
+                th = cin[wave].open;
+            }
+            if (th) {
+                tside[0] = to_partial(t, h_lo);
+                atomicOr(tflags, kHasHead | kHasTail | kSpan);
+            } else {
+                tside[1] = to_partial(t, h_last);
+                atomicOr(tflags, kHasTail);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const uint32_t fl = *tflags;
+            TileSide* ts = io.side + tile;
+            ts->flags = fl;
+            ts->head = tside[0];
+            ts->tail = (fl & kSpan) ? tside[0] : tside[1];
+        }
+        __syncthreads();
+}
+
+
+// Fixed-order workgroup reduction of the lane totals: sum of cube means and
+// of v/n over the lanes (wave shuffles, then waves in order), max of v.
+// Results are valid in thread 0.  Uses red[3 * kWaves]; ends with a barrier.
+__device__ __forceinline__ void wg_reduce_totals(double accI, double accV, double vmax, double* red, double& sI,
+                                                 double& sV, double& mx)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    for (int o = 32; o > 0; o >>= 1) {
+        accI += __shfl_down(accI, o, 64);
+        accV += __shfl_down(accV, o, 64);
+        const double m = __shfl_down(vmax, o, 64);
+        vmax = m > vmax ? m : vmax;
+    }
+    if (lane == 0) {
+        red[3 * wave] = accI;
+        red[3 * wave + 1] = accV;
+        red[3 * wave + 2] = vmax;
+    }
+    __syncthreads();
+    sI = 0.0;
+    sV = 0.0;
+    mx = 0.0;
+    if (tid == 0) {
+        for (int w = 0; w < kWaves; ++w) {
+            sI += red[3 * w];
+            sV += red[3 * w + 1];
+            mx = red[3 * w + 2] > mx ? red[3 * w + 2] : mx;
+        }
+    }
+    __syncthreads();
+}
+
+// A cube whose runs cross tiles, owned by the tile where it starts (tile j
+// has a tail that does not span the whole tile): merge the heads of the
+// following tiles in tile order until the cube ends.  Writes v of the cube
+// and returns (mean, v/n) in out[0..1]; zeros for tiles that own none.
+__device__ __forceinline__ void fixup_chain(const TileSide* side, int n_tiles, int j, double* v_out,
+                                            unsigned long long* vmax, double* out)
+{
+    double mI = 0.0, mV = 0.0;
+    const uint32_t f = side[j].flags;
+    if ((f & kHasTail) && !(f & kSpan)) {
+        Partial cur = side[j].tail;
+        int m = j + 1;
+        while (m < n_tiles) {
+            const TileSide& ts = side[m];
+            cur = merge(cur, ts.head);
+            if (!(ts.flags & kSpan)) break;
+            ++m;
+        }
+        const double v = unbiased_var(cur);
+        v_out[cur.h] = v;
+        mI = cur.mean;
+        mV = v / (double)cur.n;
+        atomicMax(vmax, (unsigned long long)__double_as_longlong(v));
+    }
+    out[0] = mI;
+    out[1] = mV;
+}
+
+}  // namespace vg

@@ -1,0 +1,50 @@
+// Host helpers shared by the single-problem and the batched C ABI:
+// error reporting, configuration validation into a problem geometry, and
+// the Eq. 8-9 combination of iteration estimates.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/vegas.h"
+
+namespace vgh {
+
+// record a thread-local message and return s
+vegas_status fail(vegas_status s, const char* fmt, ...);
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return vgh::fail(VEGAS_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kLdsLimit = 160 * 1024;
+constexpr int kMaxNg = 4096;
+
+// Problem geometry derived from a validated config (no HIP call).
+struct Geometry {
+    int D, ng, n_min, family, n_params;
+    uint32_t n_eval;
+    uint32_t nst;
+    uint32_t n_cubes;
+    uint64_t R;
+    uint32_t magic;
+    int shift;
+    int per_lane, tile, n_tiles;
+    int lds_hist_ok;
+    int n_aux;
+};
+
+// validate (cfg, f) and derive the strata, cube count, magic divisor and
+// the single-problem tile layout
+vegas_status geometry(const vegas_config* c, const vegas_integrand* f, Geometry* g);
+
+// Eq. 8-9: inverse-variance weighted mean, its variance and chi^2/dof of the
+// iteration estimates (iterations with sigma^2 = 0 are exact and decide)
+void combine(const std::vector<double>& I, const std::vector<double>& s2, double* Ib, double* s2b, double* chi);
+
+}  // namespace vgh

@@ -1,5 +1,6 @@
-// Host-side launchers of the VEGAS+ kernels (defined in fill.hip and
-// update.hip, called by the C ABI in api.hip).
+// Host-side launchers of the VEGAS+ kernels (defined in fill.hip, update.hip,
+// ordered.hip and batch.hip; called by the C ABI in api.hip and
+// batch_api.hip).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -67,6 +68,13 @@ hipError_t launch_map_update(const MapArgs& a, hipStream_t st);
 hipError_t launch_hist_reduce(const HistReduceArgs& a, hipStream_t st);
 hipError_t launch_reset(unsigned long long* p, int n, hipStream_t st);
 hipError_t launch_grid32(const double* g64, float* g32, int n, hipStream_t st);
+
+hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t st);
+hipError_t launch_batch_fill(const BatchArgs& a, bool fp64, bool kahan, int n_wg, size_t lds, hipStream_t st);
+hipError_t launch_batch_estimate(const BatchArgs& a, hipStream_t st);
+hipError_t launch_batch_alloc(const BatchArgs& a, bool any_general_beta, hipStream_t st);
+hipError_t launch_batch_map(const BatchArgs& a, int max_ng, hipStream_t st);
+hipError_t launch_batch_prep(const BatchArgs& a, hipStream_t st);
 
 constexpr int kAllocThreads = 1024;
 constexpr int kAllocPerThread = 4;

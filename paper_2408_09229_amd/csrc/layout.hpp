@@ -60,7 +60,6 @@ struct FillArgs {
     const uint32_t* tile_first; // [n_tiles+1] cube holding each tile's first sample
     double* v_out;              // [N_c] unbiased per-cube variance
     double* wg_part;            // [n_wg][2]: sum of cube means, sum of v/n
-    float* wg_comp;             // [n_wg][4]: Kahan mode partial (sum, comp) x2
     TileSide* side;             // [n_tiles]
     double* hist_H;             // LDS mode: [n_wg][D*N_g]; global mode: [D*N_g]
     uint32_t* hist_C;           // same layout
@@ -83,8 +82,6 @@ struct FinalArgs {
     const double* wg_part;
     const double* fix_part;
     double* iter_out;           // (I_t, sigma_t^2)
-    int32_t accum;
-    const float* wg_comp;
 };
 
 struct AllocArgs {
@@ -128,8 +125,68 @@ struct MapArgs {
     const uint32_t* hist_C;
     double* grid64;             // [D][N_g+1] in/out
     float* grid32;              // [D][N_g+1] out (FP32 copy)
-    double* Hsum;               // [D][N_g] reduced histogram (kept for inspection)
+    double* Hsum;               // [D][N_g] reduced histogram (kept for inspection; may be null)
     double* Csum;
+};
+
+// ---------------------------------------------------------------------------
+// batched problems: many independent integrals advanced together
+// ---------------------------------------------------------------------------
+// Per-problem record (device), built by the host at create.
+struct BatchInst {
+    SampleConst sc;             // prm / aux point into the workspace
+    double alpha, beta;
+    uint64_t R;                 // N_ev - n_min N_c
+    uint32_t n_min;
+    int32_t adapt_strat;        // 0: the allocation stays uniform
+    int32_t adapt_map;          // 0: the map stays as it is
+    int32_t per_lane, tile, tile_shift, n_tiles;
+    uint32_t tile0;             // first global tile
+    uint32_t item0, n_items;    // its work items (consecutive)
+    uint32_t blk0, n_blk;       // its allocation blocks (consecutive)
+    const double* lo;           // [D] box
+    const double* hi;
+    double* grid64;             // [D][N_g+1]
+    float* grid32;
+    uint32_t* start[2];         // [N_c+1], double-buffered
+    uint32_t* tfirst[2];        // [n_tiles+1]
+    double* v;                  // [N_c]
+    double* hist_H;             // [n_items][D*N_g]: one slot per work item
+    uint32_t* hist_C;
+    unsigned long long* bsum;   // [n_blk]
+    unsigned long long* boff;   // [n_blk+1]
+    unsigned long long* ctr;    // vmax[2], qmax[2] (FP64 bits, by iteration parity), non-finite count
+    double* iter;               // [max_iter][2]: (I_t, sigma_t^2)
+};
+
+// A work item: consecutive tiles of one problem, the unit of the queue.
+struct BatchItem {
+    uint32_t inst;
+    uint32_t tile0;             // first tile, local to the problem
+    uint32_t n_tiles;
+    uint32_t pad;
+};
+
+struct BatchArgs {
+    int32_t n_inst;
+    int32_t n_items;
+    int32_t n_tiles;            // over all problems
+    int32_t n_blk;
+    int32_t n_axes;
+    uint32_t t;                 // iteration (Philox counter word 2)
+    int32_t cur;                // allocation buffer the fill reads
+    int32_t force_uniform;      // 1: write the uniform allocation
+    const BatchInst* inst;
+    const BatchItem* items;     // problem order
+    const uint32_t* order;      // queue order of the items (largest first)
+    const uint32_t* tile_inst;  // [n_tiles] problem of each global tile
+    const uint32_t* blk_inst;   // [n_blk] problem of each allocation block
+    const uint32_t* axis_inst;  // [n_axes] problem << 4 | axis
+    unsigned int* next;         // queue head
+    double* item_part;          // [n_items][2]: sum of cube means, sum of v/n
+    TileSide* side;             // [n_tiles]
+    double* fix_part;           // [n_tiles][2]
+    unsigned long long* nonfinite;
 };
 
 }  // namespace vg

@@ -52,7 +52,7 @@ def test_workloads_validate(abi, w):
 @pytest.mark.parametrize("change,status", [
     (dict(dim=0), -1), (dict(dim=17), -1), (dict(n_intervals=0), -1), (dict(n_eval=1), -1),
     (dict(n_min=1), -1), (dict(alpha=-0.1), -1), (dict(beta=float("nan")), -1),
-    (dict(accum=1), -6), (dict(n_intervals=8192), -1), (dict(instance=1 << 24), -1),
+    (dict(accum=1), -1), (dict(accum=7), -1), (dict(n_intervals=8192), -1), (dict(instance=1 << 24), -1),
 ])
 def test_config_rejected(abi, change, status):
     w = vi.gauss_prod_4d()
@@ -99,3 +99,12 @@ def test_ordered_limits(abi):
     assert abi.vegas_workspace_size(C.byref(f32), C.byref(it.s), C.byref(n)) == -1
     big = abi.make_config(2, 1024, 10 ** 7, accum="ordered")
     assert abi.vegas_workspace_size(C.byref(big), C.byref(it.s), C.byref(n)) == -6
+
+
+def test_kahan_needs_fp32(abi):
+    it = abi._Integrand(vi.CONST, np.array([1.0]))
+    n = C.c_size_t()
+    ok = abi.make_config(3, 16, 5000, accum="kahan", precision="f32")
+    assert abi.vegas_workspace_size(C.byref(ok), C.byref(it.s), C.byref(n)) == 0
+    bad = abi.make_config(3, 16, 5000, accum="kahan", precision="f64")
+    assert abi.vegas_workspace_size(C.byref(bad), C.byref(it.s), C.byref(n)) == -1

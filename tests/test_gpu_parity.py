@@ -245,3 +245,29 @@ def test_ordered_reproducible(V):
     (Ib, sb), gb, nb = runs[1]
     assert np.array_equal(Ia, Ib) and np.array_equal(sa, sb)
     assert np.array_equal(ga, gb) and np.array_equal(na, nb)
+
+
+@pytest.mark.parametrize("w", [vi.gauss3_8d().with_(name="gauss3_8d_kahan", n_eval=3_000_007, n_g=256, n_iter=5),
+                               vi.closed_form_cases()[1]], ids=lambda w: w.name)
+def test_kahan_accumulation(V, w):
+    """Compensated FP32 accumulators: on the same samples the first
+    iteration's estimate agrees with FP64 accumulation to FP32 resolution,
+    and the run lands within 3 sigma of the closed form."""
+    say(f"[kahan] {w.name}")
+    a = V(w, precision="f32", accum="kahan")
+    b = V(w, precision="f32")
+    a.adapt(1)
+    b.adapt(1)
+    Ia, sa = a.get_iterations()
+    Ib, sb = b.get_iterations()
+    assert abs(Ia[0] - Ib[0]) <= 1e-6 * abs(Ib[0]), (Ia[0], Ib[0])
+    assert abs(sa[0] - sb[0]) <= 1e-4 * sb[0], (sa[0], sb[0])
+    # unadapted early iterations would bias the Eq. 8-9 average: adapt
+    # first, then combine
+    a.adapt(4)
+    a.integrate(w.n_iter)
+    r = a.result()
+    exact = cf.exact(w)
+    assert abs(r.integral - exact) < 3.0 * math.sqrt(r.sigma2), (r.integral, exact, math.sqrt(r.sigma2))
+    a.close()
+    b.close()

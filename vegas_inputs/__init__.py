@@ -125,6 +125,13 @@ class BatchInstance:
     n_eval: int
 
 
+# the batched workload: shared map size, iteration split and precision
+BATCH_N_G = 256
+BATCH_ADAPT = 5          # iterations whose estimates are discarded
+BATCH_ITER = 5           # iterations combined by Eq. 8-9
+BATCH_PRECISION = "f32"  # FP32 sample path, FP64 accumulators
+
+
 def genz_batch(n: int = 4096, seed: int = 0, budget_lo: float = 1e4,
                budget_hi: float = 1e7) -> List[BatchInstance]:
     """Seeded parametrised integrals of uneven dimension and budget.
