@@ -1,0 +1,151 @@
+"""Pins of the coupling-flow warp oracle (oracle/flow.py), CPU only.
+
+* identity at initialisation (zero last layer -> uniform bins)
+* F^-1(F(y)) = y and both passes give the same log J_F
+* log J_F equals log|det| of a central-difference Jacobian of F
+* the analytic loss gradient equals central differences of the loss
+* BF16 rounding equals torch's float32 -> bfloat16 conversion
+* a few Adam steps on the variance loss lower the variance of the weights of
+  a correlated target (the gradient points the right way)
+"""
+import numpy as np
+import pytest
+
+from oracle import flow as fl
+
+D = 16
+
+
+def random_theta(dim, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    th = fl.init_params(dim, seed)
+    for L in fl.unpack(th, dim):
+        L["W3"][...] = rng.normal(0, scale, L["W3"].shape)
+        L["b1"][...] = rng.normal(0, 0.1, L["b1"].shape)
+        L["b2"][...] = rng.normal(0, 0.1, L["b2"].shape)
+        L["b3"][...] = rng.normal(0, 0.5, L["b3"].shape)
+    return th
+
+
+def test_shapes_and_count():
+    assert fl.n_params(16) == 4 * (64 * 8 + 64 + 64 * 64 + 64 + 128 * 64 + 128)
+    for A, B in fl.masks(16):
+        assert len(A) == len(B) == 8 and len(np.intersect1d(A, B)) == 0
+
+
+def test_identity_at_init():
+    th = fl.init_params(D, 3)
+    y = np.random.default_rng(0).random((200, D))
+    w, lj = fl.forward(th, y)
+    assert np.max(np.abs(w - y)) < 1e-14
+    assert np.max(np.abs(lj)) < 1e-13
+
+
+def test_round_trip():
+    th = random_theta(D, 1)
+    y = np.random.default_rng(2).random((500, D))
+    w, lj = fl.forward(th, y)
+    assert np.all((w >= 0) & (w <= 1))
+    y2, lj2 = fl.inverse(th, w)
+    assert np.max(np.abs(y2 - y)) < 1e-12
+    assert np.max(np.abs(lj2 - lj)) < 1e-11
+
+
+def test_logdet_against_finite_differences():
+    dim = 6
+    th = random_theta(dim, 4)
+    rng = np.random.default_rng(5)
+    y = 0.05 + 0.9 * rng.random((40, dim))
+    w, lj = fl.forward(th, y)
+    h = 1e-7
+    checked = 0
+    for i in range(len(y)):
+        # skip points within h of a bin edge of any layer's transformed input
+        z, near = y[i:i + 1].copy(), False
+        for L, (A, B) in zip(fl.unpack(th, dim), fl.masks(dim)):
+            f = fl.K_BINS * z[0, B]
+            near |= np.any(np.abs(f - np.round(f)) < 1e-4)
+            z, _ = fl.layer_forward(L, z, A, B)
+        if near:
+            continue
+        J = np.zeros((dim, dim))
+        for j in range(dim):
+            e = np.zeros(dim)
+            e[j] = h
+            J[:, j] = (fl.forward(th, (y[i] + e)[None])[0][0] - fl.forward(th, (y[i] - e)[None])[0][0]) / (2 * h)
+        sign, ld = np.linalg.slogdet(J)
+        assert sign > 0
+        assert abs(ld - lj[i]) < 1e-6, (ld, lj[i])
+        checked += 1
+    assert checked >= 10
+
+
+def test_gradient_against_finite_differences():
+    dim = 4
+    th = random_theta(dim, 7, scale=0.5)
+    rng = np.random.default_rng(8)
+    w = 0.05 + 0.9 * rng.random((30, dim))
+    coef = rng.random(30)
+    _, g = fl.loss_grad(th, w, coef)
+    h = 1e-6
+    idx = rng.choice(th.size, 60, replace=False)
+    n_ok = 0
+    for i in idx:
+        tp = th.copy()
+        tm = th.copy()
+        tp[i] += h
+        tm[i] -= h
+        # (h is far below the distance of these points to any bin edge)
+        Lp, _ = fl.loss_grad(tp, w, coef)
+        Lm, _ = fl.loss_grad(tm, w, coef)
+        fd = (Lp - Lm) / (2 * h)
+        if abs(fd - g[i]) > 1e-5 * max(1.0, abs(g[i])):
+            pytest.fail(f"param {i}: analytic {g[i]} vs central difference {fd}")
+        n_ok += 1
+    assert n_ok == len(idx)
+    assert np.linalg.norm(g) > 0
+
+
+def test_bf16_matches_torch():
+    import torch
+    x = np.concatenate([[1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, -2.5, 1e-30, 3.3e38, 0.0],
+                        np.random.default_rng(3).normal(0, 10, 1000)])
+    want = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(fl.bf16(x), want)
+
+
+def test_training_lowers_variance():
+    """Target: a correlated Gaussian on [0,1]^4 (rho 0.8, s 0.12).  With
+    x = w, omega = g(F(y)) J_F(y); Adam on the variance loss lowers the
+    variance of omega below the identity warp's."""
+    dim = 4
+    rng = np.random.default_rng(11)
+    s, rho = 0.12, 0.8
+    cov = s * s * ((1 - rho) * np.eye(dim) + rho * np.ones((dim, dim)))
+    ic = np.linalg.inv(cov)
+    norm = 1.0 / np.sqrt((2 * np.pi) ** dim * np.linalg.det(cov))
+
+    def g(x):
+        u = x - 0.5
+        return norm * np.exp(-0.5 * np.einsum("ni,ij,nj->n", u, ic, u))
+
+    def var_of(th, n=200000, seed=0):
+        y = np.random.default_rng(seed).random((n, dim))
+        w, lj = fl.forward(th, y)
+        om = g(w) * np.exp(lj)
+        return om.var(), om.mean()
+
+    th = fl.init_params(dim, 0)
+    v0, m0 = var_of(th)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    for step in range(1, 101):
+        y = rng.random((10000, dim))
+        w, lj = fl.forward(th, y)
+        om = g(w) * np.exp(lj)
+        c = om ** 2 / np.sum(om ** 2)
+        _, gr = fl.loss_grad(th, w, c)
+        th, m, v = fl.adam(th, gr, m, v, step, 1e-4)
+    v1, m1 = var_of(th)
+    assert abs(m0 - 1) < 0.1 and abs(m1 - 1) < 0.1      # unbiased both ways
+    assert v1 < 0.8 * v0, (v0, v1)
