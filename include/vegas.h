@@ -204,6 +204,52 @@ vegas_status vegas_sample_probe(vegas_ctx* ctx, uint32_t t, uint64_t k0, int64_t
 vegas_status vegas_set_timing(vegas_ctx* ctx, int32_t on);
 vegas_status vegas_get_timing(vegas_ctx* ctx, double* ms, int32_t* n_iter);
 
+/* ---- learned warp: a coupling flow stacked on the VEGAS map ------------- */
+/* Not in the paper; an extension of the method.  With the warp enabled,
+ * every iteration draws the stratified points y as before, maps them by a
+ * normalising flow F to w = F(y), and w goes through the VEGAS map to x.
+ * A sample weighs f(x) J_map(w) J_F(y).  J_F is the exact Jacobian
+ * determinant, so every estimate stays unbiased.  The map and allocation
+ * adapt to the warped samples exactly as before.
+ * F: four coupling layers on [0,1]^16.  Layer l keeps the axes A_l
+ *   ({0..7}, {8..15}, the even axes, the odd axes) and moves the other 8.
+ *   A move is the piecewise-linear CDF of 16 bin probabilities
+ *   p = (1 - 1e-3) softmax(o) + 1e-3/16.  The logits o come from an MLP of
+ *   x = 2 z_A - 1: 8 -> 64 -> 64 -> 128 with ReLU.  The matrix products run on
+ *   BF16 MFMA with FP32 accumulation.
+ * Parameters: vegas_flow_n_params() floats, layer by layer
+ *   W1[64][8], b1[64], W2[64][64], b2[64], W3[128][64], b3[128] (row-major
+ *   [out][in]).  A zero W3 and b3 make F the identity.
+ * Restrictions: dim 16, FP32 precision, accum FP64 or KAHAN, families
+ *   GAUSS_DIAG, GENZ_PPEAK, GENZ_GAUSS, GAUSS_CORR. */
+typedef struct {
+    float   lr;               /* Adam step of the warp's training */
+    int32_t train;            /* 1: train after every warped iteration */
+} vegas_flow_config;
+
+int32_t vegas_flow_n_params(void);
+/* Bytes of the warp's own device workspace for this context. */
+vegas_status vegas_flow_workspace_size(const vegas_ctx* ctx, size_t* bytes);
+/* Attach a warp with initial parameters.  params: host pointer, n_params
+ * floats.  d_workspace: device memory of at least the size above,
+ * 256-byte aligned; it must outlive the context.  Synchronous.  The warp
+ * starts disabled. */
+vegas_status vegas_flow_attach(vegas_ctx* ctx, const vegas_flow_config* cfg, const float* params,
+                               void* d_workspace, size_t bytes);
+/* on = 1: the following iterations sample through the warp. */
+vegas_status vegas_flow_enable(vegas_ctx* ctx, int32_t on);
+/* Synchronous copies of the FP32 parameters (host pointers). */
+vegas_status vegas_flow_get_params(vegas_ctx* ctx, float* params);
+vegas_status vegas_flow_set_params(vegas_ctx* ctx, const float* params);
+/* Test hook, synchronous.  The last warped iteration's samples: w [N][16],
+ * log J_F [N] and weight omega [N] (FP32, host pointers; any may be NULL). */
+vegas_status vegas_flow_get_samples(vegas_ctx* ctx, float* w, float* lj, float* omega);
+/* Test hook, synchronous, on the current device.  One BF16 matrix product
+ * D = A B.  Device pointers: A [32][16], B [16][32], D [32][32], all FP32
+ * row-major.  A and B are rounded to BF16 first.  It checks the lane layout
+ * the warp's kernels assume. */
+vegas_status vegas_mfma_probe(const float* d_A, const float* d_B, float* d_D);
+
 /* ---- batches: many independent problems advanced together ------------- */
 /* A batch holds n problems, each with its own configuration (dimension,
  * intervals, budget, alpha, beta, seed, instance) and integrand.  All n

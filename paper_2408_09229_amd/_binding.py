@@ -57,6 +57,10 @@ class vegas_info(C.Structure):
                 ("lds_hist", C.c_int32), ("workspace_bytes", C.c_size_t)]
 
 
+class vegas_flow_config(C.Structure):
+    _fields_ = [("lr", C.c_float), ("train", C.c_int32)]
+
+
 class vegas_batch_info(C.Structure):
     _fields_ = [("n", C.c_int32), ("per_lane", C.c_int32), ("item_samples", C.c_int64),
                 ("n_items", C.c_int64), ("n_tiles", C.c_int64), ("n_workgroups", C.c_int32),
@@ -89,6 +93,14 @@ _DECL = {
     "vegas_sample_probe": (_st, [_vp, C.c_uint32, C.c_uint64, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "vegas_set_timing": (_st, [_vp, C.c_int32]),
     "vegas_get_timing": (_st, [_vp, _vp, C.POINTER(C.c_int32)]),
+    "vegas_flow_n_params": (C.c_int32, []),
+    "vegas_flow_workspace_size": (_st, [_vp, C.POINTER(C.c_size_t)]),
+    "vegas_flow_attach": (_st, [_vp, C.POINTER(vegas_flow_config), _vp, _vp, C.c_size_t]),
+    "vegas_flow_enable": (_st, [_vp, C.c_int32]),
+    "vegas_flow_get_params": (_st, [_vp, _vp]),
+    "vegas_flow_set_params": (_st, [_vp, _vp]),
+    "vegas_flow_get_samples": (_st, [_vp, _vp, _vp, _vp]),
+    "vegas_mfma_probe": (_st, [_vp, _vp, _vp]),
     "vegas_batch_workspace_size": (_st, [C.c_int32, _vp, _vp, C.POINTER(C.c_size_t)]),
     "vegas_batch_create": (_st, [C.c_int32, _vp, _vp, _vp, C.c_size_t, _vp, C.c_char_p, C.POINTER(_vp)]),
     "vegas_batch_destroy": (None, [_vp]),
@@ -281,6 +293,41 @@ class Vegas:
         check(vegas_get_timing(self.h, _dptr(ms), C.byref(n)), "vegas_get_timing")
         return ms, n.value
 
+    # -- learned warp -------------------------------------------------------
+    def attach_flow(self, params, lr: float = 1e-4, train: bool = False):
+        """Attach a coupling-flow warp (initial FP32 parameters ``params``)."""
+        import torch
+        n = C.c_size_t()
+        check(vegas_flow_workspace_size(self.h, C.byref(n)), "vegas_flow_workspace_size")
+        self.fws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != vegas_flow_n_params():
+            raise ValueError("wrong number of flow parameters")
+        self.fcfg = vegas_flow_config(lr, int(train))
+        check(vegas_flow_attach(self.h, C.byref(self.fcfg), _dptr(p), C.c_void_p(self.fws.data_ptr()), n.value),
+              "vegas_flow_attach")
+
+    def enable_flow(self, on: bool = True):
+        check(vegas_flow_enable(self.h, int(on)), "vegas_flow_enable")
+
+    def flow_params(self):
+        p = np.zeros(vegas_flow_n_params(), np.float32)
+        check(vegas_flow_get_params(self.h, _dptr(p)), "vegas_flow_get_params")
+        return p
+
+    def set_flow_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        check(vegas_flow_set_params(self.h, _dptr(p)), "vegas_flow_set_params")
+
+    def flow_samples(self):
+        """(w [N][16], log J_F [N], omega [N]) of the last warped iteration."""
+        n = self.cfg.n_eval
+        w = np.zeros((n, 16), np.float32)
+        lj = np.zeros(n, np.float32)
+        om = np.zeros(n, np.float32)
+        check(vegas_flow_get_samples(self.h, _dptr(w), _dptr(lj), _dptr(om)), "vegas_flow_get_samples")
+        return w, lj, om
+
     def probe(self, t: int, k0: int, n: int):
         """Per-sample path for samples k0..k0+n-1 of iteration t (torch tensors)."""
         import torch
@@ -408,3 +455,14 @@ class VegasBatch:
         n = C.c_int32()
         check(vegas_batch_get_timing(self.h, _dptr(ms), C.byref(n)), "vegas_batch_get_timing")
         return ms, n.value
+
+
+def mfma_probe(A, B):
+    """D = bf16(A) bf16(B) by one 32x32x16 BF16 MFMA on the current device."""
+    import torch
+    a = torch.tensor(np.ascontiguousarray(A, np.float32), device="cuda")
+    b = torch.tensor(np.ascontiguousarray(B, np.float32), device="cuda")
+    d = torch.zeros((32, 32), dtype=torch.float32, device="cuda")
+    check(vegas_mfma_probe(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), C.c_void_p(d.data_ptr())),
+          "vegas_mfma_probe")
+    return d.cpu().numpy()

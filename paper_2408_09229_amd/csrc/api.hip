@@ -240,6 +240,13 @@ struct vegas_ctx {
     bool timing;
     std::vector<hipEvent_t> events;    // 5 per timed iteration
 
+    // learned warp (vegas_flow_*): its own workspace, carved by flow_plan
+    bool flow_attached = false;
+    bool flow_on = false;
+    vegas_flow_config fcfg{};
+    unsigned char* fws = nullptr;
+    size_t f_theta = 0, f_packed = 0, f_w = 0, f_lj = 0, f_om = 0;
+
     ~vegas_ctx()
     {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -409,7 +416,21 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
     a.nonfinite = c->nonfinite();
     const size_t lds = fill_lds_bytes(c->g.D, c->g.ng, fp64, lds_hist, c->g.tile, c->g.n_aux);
     HIPCHK(c->mark());
-    HIPCHK(launch_fill(a, fp64, c->n_wg, lds, c->stream));
+    if (c->flow_on) {
+        // the warp: y -> w = F(y) for every sample, then the fill on w
+        FlowSampleArgs fa;
+        fa.sc = a.sc;
+        fa.t = a.t;
+        fa.start = a.start;
+        fa.theta = reinterpret_cast<const float*>(c->fws + c->f_theta);
+        fa.packed = c->fws + c->f_packed;
+        fa.w = reinterpret_cast<float*>(c->fws + c->f_w);
+        fa.lj = reinterpret_cast<float*>(c->fws + c->f_lj);
+        HIPCHK(launch_flow_sample(fa, 2 * c->n_wg, c->stream));
+        HIPCHK(launch_fill_flow(a, fa.w, fa.lj, reinterpret_cast<float*>(c->fws + c->f_om), c->n_wg, lds, c->stream));
+    } else {
+        HIPCHK(launch_fill(a, fp64, c->n_wg, lds, c->stream));
+    }
     HIPCHK(c->mark());
     FixupArgs fx;
     fx.n_tiles = c->g.n_tiles;
@@ -878,6 +899,136 @@ vegas_status vegas_sample_probe(vegas_ctx* c, uint32_t t, uint64_t k0, int64_t n
 }
 
 // state image: header, grid, n_h, iteration log, flags, counters
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// learned warp
+// ---------------------------------------------------------------------------
+namespace {
+
+struct FlowPlan {
+    size_t theta, packed, w, lj, om, total;
+};
+
+FlowPlan flow_plan(uint32_t n_eval)
+{
+    FlowPlan p;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = (o + bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    p.theta = take(sizeof(float) * kFParams);
+    p.packed = take((size_t)16 * kFlowLayers * kPLayer);
+    p.w = take(sizeof(float) * kFlowDim * (size_t)n_eval);
+    p.lj = take(sizeof(float) * (size_t)n_eval);
+    p.om = take(sizeof(float) * (size_t)n_eval);
+    p.total = o;
+    return p;
+}
+
+vegas_status flow_check(const vegas_ctx* c)
+{
+    if (c->g.D != kFlowDim) return fail(VEGAS_EUNSUPPORTED, "the learned warp is built for dim %d", kFlowDim);
+    if (c->cfg.precision != VEGAS_PREC_FP32) return fail(VEGAS_EUNSUPPORTED, "the learned warp runs the FP32 sample path");
+    if (c->cfg.accum == VEGAS_ACC_ORDERED) return fail(VEGAS_EUNSUPPORTED, "no learned warp in ORDERED accumulation");
+    const int f = c->g.family;
+    if (f != VEGAS_GAUSS_DIAG && f != VEGAS_GENZ_PPEAK && f != VEGAS_GENZ_GAUSS && f != VEGAS_GAUSS_CORR)
+        return fail(VEGAS_EUNSUPPORTED, "family %d has no warped fill", f);
+    return VEGAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t vegas_flow_n_params(void) { return kFParams; }
+
+vegas_status vegas_flow_workspace_size(const vegas_ctx* c, size_t* bytes)
+{
+    if (!c || !bytes) return fail(VEGAS_EINVAL, "bad arguments");
+    const vegas_status s = flow_check(c);
+    if (s != VEGAS_OK) return s;
+    *bytes = flow_plan(c->g.n_eval).total;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_flow_attach(vegas_ctx* c, const vegas_flow_config* cfg, const float* params, void* d_ws,
+                               size_t bytes)
+{
+    if (!c || !cfg || !params || !d_ws) return fail(VEGAS_EINVAL, "bad arguments");
+    vegas_status s = flow_check(c);
+    if (s != VEGAS_OK) return s;
+    if (((uintptr_t)d_ws & 255u) != 0) return fail(VEGAS_EINVAL, "flow workspace must be 256-byte aligned");
+    const FlowPlan p = flow_plan(c->g.n_eval);
+    if (bytes < p.total) return fail(VEGAS_ENOMEM, "flow workspace has %zu bytes, needs %zu", bytes, p.total);
+    if (!(cfg->lr >= 0.f) || !std::isfinite(cfg->lr)) return fail(VEGAS_EINVAL, "lr must be finite and >= 0");
+    for (int i = 0; i < kFParams; ++i)
+        if (!std::isfinite(params[i])) return fail(VEGAS_EINVAL, "flow parameter %d is not finite", i);
+    c->fcfg = *cfg;
+    c->fws = (unsigned char*)d_ws;
+    c->f_theta = p.theta;
+    c->f_packed = p.packed;
+    c->f_w = p.w;
+    c->f_lj = p.lj;
+    c->f_om = p.om;
+    c->flow_attached = true;
+    c->flow_on = false;
+    return vegas_flow_set_params(c, params);
+}
+
+vegas_status vegas_flow_enable(vegas_ctx* c, int32_t on)
+{
+    if (!c) return fail(VEGAS_EINVAL, "bad arguments");
+    if (on && !c->flow_attached) return fail(VEGAS_ESTATE, "no flow attached");
+    c->flow_on = on != 0;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_flow_set_params(vegas_ctx* c, const float* params)
+{
+    if (!c || !params) return fail(VEGAS_EINVAL, "bad arguments");
+    if (!c->flow_attached) return fail(VEGAS_ESTATE, "no flow attached");
+    HIPCHK(hipMemcpyAsync(c->fws + c->f_theta, params, sizeof(float) * kFParams, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(launch_flow_pack(reinterpret_cast<const float*>(c->fws + c->f_theta), c->fws + c->f_packed, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return VEGAS_OK;
+}
+
+vegas_status vegas_flow_get_params(vegas_ctx* c, float* params)
+{
+    if (!c || !params) return fail(VEGAS_EINVAL, "bad arguments");
+    if (!c->flow_attached) return fail(VEGAS_ESTATE, "no flow attached");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(params, c->fws + c->f_theta, sizeof(float) * kFParams, hipMemcpyDeviceToHost));
+    return VEGAS_OK;
+}
+
+vegas_status vegas_flow_get_samples(vegas_ctx* c, float* w, float* lj, float* om)
+{
+    if (!c) return fail(VEGAS_EINVAL, "bad arguments");
+    if (!c->flow_attached) return fail(VEGAS_ESTATE, "no flow attached");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const size_t n = c->g.n_eval;
+    if (w) HIPCHK(hipMemcpy(w, c->fws + c->f_w, sizeof(float) * kFlowDim * n, hipMemcpyDeviceToHost));
+    if (lj) HIPCHK(hipMemcpy(lj, c->fws + c->f_lj, sizeof(float) * n, hipMemcpyDeviceToHost));
+    if (om) HIPCHK(hipMemcpy(om, c->fws + c->f_om, sizeof(float) * n, hipMemcpyDeviceToHost));
+    return VEGAS_OK;
+}
+
+vegas_status vegas_mfma_probe(const float* d_A, const float* d_B, float* d_D)
+{
+    if (!d_A || !d_B || !d_D) return fail(VEGAS_EINVAL, "bad arguments");
+    HIPCHK(launch_mfma_probe(d_A, d_B, d_D, nullptr));
+    HIPCHK(hipDeviceSynchronize());
+    return VEGAS_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
 struct StateHeader {
     uint64_t magic;
     int32_t D, ng;

@@ -272,10 +272,12 @@ struct FillLds {
 // there, runs crossing lanes merge by the wavefront scan, and the tile's
 // boundary runs go to its side record.  Called by all lanes of the
 // workgroup; ends with a barrier.
-template <typename R, int FAM, int MAXD, bool KAHAN>
-__device__ __forceinline__ void fill_tile(int tile, const TileIO& io, const FillLds<R>& L,
-                                          SamplePath<R, FAM, MAXD>& sp, LaneTotal<KAHAN>& totI,
-                                          LaneTotal<KAHAN>& totV, double& vmax, unsigned long long& bad)
+// Path: the per-sample path (SamplePath, or the warped path of the learned
+// warp), with digits / next_digits / eval and the problem constants sc.
+template <typename R, int MAXD, bool KAHAN, typename Path>
+__device__ __forceinline__ void fill_tile(int tile, const TileIO& io, const FillLds<R>& L, Path& sp,
+                                          LaneTotal<KAHAN>& totI, LaneTotal<KAHAN>& totV, double& vmax,
+                                          unsigned long long& bad)
 {
     const SampleConst& sc = sp.sc;
     const int D = sc.D;

@@ -1,0 +1,443 @@
+// The learned warp on gfx950: packing of the BF16 MFMA operands, the
+// sampling pass (stratified y -> w = F(y), log J_F), and the fill of an
+// iteration through the warp (weight f(map(w)) J_map(w) J_F(y)).
+//
+// One wavefront evaluates the flow for 32 samples at a time.  Its matrix
+// products are v_mfma_f32_32x32x16_bf16 with the samples as rows; a layer's
+// hidden activations go through LDS to change from the product's output
+// layout to the next product's input layout, and the bin logits go through
+// LDS to the lanes that move each sample's axes.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+#include "families.hpp"
+#include "fill_dev.hpp"
+#include "flow.hpp"
+#include "launch.hpp"
+#include "layout.hpp"
+
+namespace vg {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// output layout of the 32x32 product: register r of lane l holds row
+// mrow(l, r), column l % 32
+__device__ __forceinline__ int mrow(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+// ---------------------------------------------------------------------------
+// operand packing (after every parameter change)
+// ---------------------------------------------------------------------------
+__global__ void k_flow_pack(const float* __restrict__ theta, bf16x8* __restrict__ packed)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kFlowLayers * kPLayer) return;
+    const int l = e / kPLayer;
+    int r = e - l * kPLayer;
+    const float* P = theta + (size_t)l * kFLayer;
+    const float* W1 = P + kFW1;
+    const float* W2 = P + kFW2;
+    const float* W3 = P + kFW3;
+    const int lane = r & 63;
+    const int kb = 8 * (lane >> 5);       // first k of this lane
+    const int n32 = lane & 31;
+    float v[8];
+    if (r < kPF2) {                       // F1[nt]: B[k = axis][n] = W1[n][pos(axis)] for axes in A
+        const int nt = r >> 6;
+        const int n = nt * 32 + n32;
+        for (int j = 0; j < 8; ++j) {
+            const int c = kb + j;
+            v[j] = flow_in_a(l, c) ? W1[n * kFlowHalf + flow_pos(l, c)] : 0.f;
+        }
+    } else if (r < kPF3) {                // F2[nt][ks]: B[k][n] = W2[n][k]
+        r -= kPF2;
+        const int nt = r >> 8, ks = (r >> 6) & 3;
+        const int n = nt * 32 + n32;
+        for (int j = 0; j < 8; ++j) v[j] = W2[n * kFlowHidden + ks * 16 + kb + j];
+    } else if (r < kPR3) {                // F3[nt][ks]: B[k][n] = W3[n][k]
+        r -= kPF3;
+        const int nt = r >> 8, ks = (r >> 6) & 3;
+        const int n = nt * 32 + n32;
+        for (int j = 0; j < 8; ++j) v[j] = W3[n * kFlowHidden + ks * 16 + kb + j];
+    } else if (r < kPR2) {                // R3[nt][ks]: B[k = o][n = h] = W3[o][h]
+        r -= kPR3;
+        const int nt = r >> 9, ks = (r >> 6) & 7;
+        const int n = nt * 32 + n32;
+        for (int j = 0; j < 8; ++j) v[j] = W3[(ks * 16 + kb + j) * kFlowHidden + n];
+    } else if (r < kPR1) {                // R2[nt][ks]: B[k = n2][n = n1] = W2[n2][n1]
+        r -= kPR2;
+        const int nt = r >> 8, ks = (r >> 6) & 3;
+        const int n = nt * 32 + n32;
+        for (int j = 0; j < 8; ++j) v[j] = W2[(ks * 16 + kb + j) * kFlowHidden + n];
+    } else {                              // R1[ks]: B[k = h][n = axis] = W1[h][pos(axis)] for axes in A
+        r -= kPR1;
+        const int ks = r >> 6;
+        const int c = n32;
+        for (int j = 0; j < 8; ++j)
+            v[j] = (c < kFlowDim && flow_in_a(l, c)) ? W1[(ks * 16 + kb + j) * kFlowHalf + flow_pos(l, c)] : 0.f;
+    }
+    bf16x8 o;
+    for (int j = 0; j < 8; ++j) o[j] = (__bf16)v[j];
+    packed[e] = o;
+}
+
+// ---------------------------------------------------------------------------
+// operand layout check: D = A B for one 32x32x16 product (A 32x16 and B
+// 16x32 row-major FP32, rounded to BF16; D 32x32 FP32).  One wavefront.
+// ---------------------------------------------------------------------------
+__global__ void k_mfma_probe(const float* A, const float* B, float* D)
+{
+    const int l = threadIdx.x;
+    bf16x8 a, b;
+    for (int j = 0; j < 8; ++j) {
+        a[j] = (__bf16)A[(l & 31) * 16 + 8 * (l >> 5) + j];
+        b[j] = (__bf16)B[(8 * (l >> 5) + j) * 32 + (l & 31)];
+    }
+    f32x16 c = {};
+    c = mfma(a, b, c);
+    for (int r = 0; r < 16; ++r) D[mrow(l, r) * 32 + (l & 31)] = c[r];
+}
+
+// ---------------------------------------------------------------------------
+// one coupling layer for the 32 samples of a wavefront (forward direction)
+// ---------------------------------------------------------------------------
+constexpr int kFlowWaves = 4;
+constexpr int kFlowThreads = 64 * kFlowWaves;
+struct __align__(16) FlowLds {
+    __bf16 h[kFlowWaves][32 * kFlowHidden];            // hidden activations [sample][unit]
+    float o[kFlowWaves][32 * kFlowHalf * kFlowBins];   // bin logits [sample][axis * 16 + bin]
+};
+
+// MLP of layer l for the wave's 32 samples: logits into o[sample][.]
+// z: the lane's 8 coordinates (axes 8 (lane/32) + j of sample lane % 32)
+__device__ __forceinline__ void flow_mlp(int l, const float (&z)[8], const float* __restrict__ P,
+                                         const bf16x8* __restrict__ pk, __bf16* hb, float* ob)
+{
+    const int lane = threadIdx.x & 63;
+    const int half = lane >> 5;
+    const int n32 = lane & 31;
+    bf16x8 xa;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) xa[j] = flow_in_a(l, 8 * half + j) ? (__bf16)(2.f * z[j] - 1.f) : (__bf16)0.f;
+    // h1 = relu(W1 x + b1)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        f32x16 acc = {};
+        acc = mfma(xa, pk[kPF1 + nt * 64 + lane], acc);
+        const float bias = P[kFB1 + nt * 32 + n32];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float v = acc[r] + bias;
+            hb[mrow(lane, r) * kFlowHidden + nt * 32 + n32] = (__bf16)(v > 0.f ? v : 0.f);
+        }
+    }
+    __syncthreads();
+    // h2 = relu(W2 h1 + b2)
+    bf16x8 ha[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) ha[ks] = *reinterpret_cast<const bf16x8*>(hb + n32 * kFlowHidden + ks * 16 + 8 * half);
+    f32x16 acc2[2];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        f32x16 acc = {};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) acc = mfma(ha[ks], pk[kPF2 + (nt * 4 + ks) * 64 + lane], acc);
+        acc2[nt] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const float bias = P[kFB2 + nt * 32 + n32];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float v = acc2[nt][r] + bias;
+            hb[mrow(lane, r) * kFlowHidden + nt * 32 + n32] = (__bf16)(v > 0.f ? v : 0.f);
+        }
+    }
+    __syncthreads();
+    // logits = W3 h2 + b3
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) ha[ks] = *reinterpret_cast<const bf16x8*>(hb + n32 * kFlowHidden + ks * 16 + 8 * half);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        f32x16 acc = {};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) acc = mfma(ha[ks], pk[kPF3 + (nt * 4 + ks) * 64 + lane], acc);
+        const float bias = P[kFB3 + nt * 32 + n32];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) ob[mrow(lane, r) * (kFlowHalf * kFlowBins) + nt * 32 + n32] = acc[r] + bias;
+    }
+    __syncthreads();
+}
+
+// bin probabilities of one moved axis from its 16 logits
+__device__ __forceinline__ void flow_probs(const float* lg, float (&p)[kFlowBins])
+{
+    float m = lg[0];
+#pragma unroll
+    for (int k = 1; k < kFlowBins; ++k) m = fmaxf(m, lg[k]);
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < kFlowBins; ++k) {
+        p[k] = expf(lg[k] - m);
+        s += p[k];
+    }
+    const float a = (1.f - kFlowEps) / s;
+#pragma unroll
+    for (int k = 0; k < kFlowBins; ++k) p[k] = fmaf(a, p[k], kFlowEps / kFlowBins);
+}
+
+// ---------------------------------------------------------------------------
+// sampling pass: y of every sample of iteration t, pushed through F
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kFlowThreads) void k_flow_sample(FlowSampleArgs a)
+{
+    __shared__ FlowLds S;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int half = lane >> 5;
+    const int n32 = lane & 31;
+    const SampleConst& sc = a.sc;
+    const PhiloxKeys keys = philox_keys<false>(sc.key0, sc.key1);
+    const uint32_t N = sc.n_eval;
+    const uint32_t chunks = (N + 31u) / 32u;
+    const uint32_t per_round = gridDim.x * kFlowWaves;
+    const uint32_t rounds = (chunks + per_round - 1u) / per_round;
+    const bf16x8* pk = reinterpret_cast<const bf16x8*>(a.packed);
+    const float inv_nst = 1.f / (float)sc.nst;
+    for (uint32_t rd = 0; rd < rounds; ++rd) {
+        // every wave runs every round (the layers synchronise the workgroup)
+        const uint32_t chunk = rd * per_round + blockIdx.x * kFlowWaves + wave;
+        const bool live = chunk < chunks;
+        const uint32_t k = live ? min(chunk * 32u + (uint32_t)n32, N - 1u) : 0u;
+        // cube of k and its stratum digits
+        uint32_t lo = 0, hi = sc.n_cubes;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (a.start[mid] <= k) lo = mid; else hi = mid;
+        }
+        uint32_t hc = lo, dig[kFlowDim];
+#pragma unroll
+        for (int d = 0; d < kFlowDim; ++d) {
+            const uint32_t q = div_magic(hc, sc.nst_magic, sc.nst_shift);
+            dig[d] = hc - q * sc.nst;
+            hc = q;
+        }
+        float z[8];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const W4 o = philox10(k, 0u, a.t, sc.ctr3 | (uint32_t)(2 * half + b), keys);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int j = 4 * b + q;
+                const float u = ((float)o.v[q] + 0.5f) * 0x1p-32f;
+                z[j] = ((float)dig[8 * half + j] + u) * inv_nst;
+            }
+        }
+        float lj = 0.f;
+        for (int l = 0; l < kFlowLayers; ++l) {
+            const float* P = a.theta + (size_t)l * kFLayer;
+            flow_mlp(l, z, P, pk + (size_t)l * kPLayer, S.h[wave], S.o[wave]);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int c = 8 * half + j;
+                if (flow_in_a(l, c)) continue;
+                float p[kFlowBins];
+                flow_probs(S.o[wave] + n32 * (kFlowHalf * kFlowBins) + flow_pos(l, c) * kFlowBins, p);
+                const float zk = z[j] * (float)kFlowBins;
+                const int bin = min((int)zk, kFlowBins - 1);
+                float cum = 0.f, pb = p[0];
+#pragma unroll
+                for (int q = 0; q < kFlowBins; ++q) {
+                    if (q < bin) cum += p[q];
+                    if (q == bin) pb = p[q];
+                }
+                z[j] = fminf(fmaxf(fmaf(zk - (float)bin, pb, cum), 0.f), 1.f);
+                lj += logf((float)kFlowBins * pb);
+            }
+            __syncthreads();
+        }
+        lj += __shfl_xor(lj, 32, 64);
+        if (live && chunk * 32u + (uint32_t)n32 < N) {
+            float4* wo = reinterpret_cast<float4*>(a.w + (size_t)k * kFlowDim + 8 * half);
+            wo[0] = make_float4(z[0], z[1], z[2], z[3]);
+            wo[1] = make_float4(z[4], z[5], z[6], z[7]);
+            if (half == 0) a.lj[k] = lj;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the fill through the warp
+// ---------------------------------------------------------------------------
+// Sample path of the warped fill: the point is w_k from the sampling pass
+// (FP32), its map bin floor(w N_g), and the weight carries J_F = exp(lj_k).
+// The stratum digits are not needed (the sampling pass used them).
+template <int FAM>
+struct WarpedPath {
+    const SampleConst& sc;
+    Fn<float, FAM> fn;
+    float ngR;
+    const float* w;
+    const float* lj;
+    float* om;
+
+    __device__ __forceinline__ WarpedPath(const SampleConst& c, const float* aux, const float* w_, const float* lj_,
+                                          float* om_)
+        : sc(c), w(w_), lj(lj_), om(om_)
+    {
+        fn.setup(c, aux);
+        ngR = (float)c.ng;
+    }
+    __device__ __forceinline__ void digits(uint32_t, uint32_t (&)[kFlowDim]) const {}
+    __device__ __forceinline__ void next_digits(uint32_t (&)[kFlowDim]) const {}
+
+    template <bool PROBE>
+    __device__ __forceinline__ float eval(uint32_t k, uint32_t, const uint32_t (&)[kFlowDim], const float* __restrict__ g,
+                                          uint32_t (&bins)[kFlowDim], float*, float*, float& J, float& f)
+    {
+        const float4* wk = reinterpret_cast<const float4*>(w + (size_t)k * kFlowDim);
+        float wv[kFlowDim];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 v = wk[q];
+            wv[4 * q] = v.x;
+            wv[4 * q + 1] = v.y;
+            wv[4 * q + 2] = v.z;
+            wv[4 * q + 3] = v.w;
+        }
+        J = 1.f;
+        fn.begin();
+        const uint32_t row = sc.ng + 1u;
+        const int top = (int)sc.ng - 1;
+#pragma unroll
+        for (int d = 0; d < kFlowDim; ++d) {
+            const float u = wv[d] * ngR;
+            const int bin = min((int)u, top);
+            const float delta = u - (float)bin;
+            bins[d] = (uint32_t)bin;
+            const float* gd = g + d * row;
+            const float xl = gd[bin];
+            const float dx = gd[bin + 1] - xl;
+            J = J * (ngR * dx);
+            fn.axis(d, fmaf(dx, delta, xl));
+        }
+        f = fn.finish();
+        J = J * expf(lj[k]);
+        const float wt = J * f;
+        om[k] = __builtin_isfinite(wt) ? wt : 0.f;
+        return wt;
+    }
+};
+
+template <int FAM, bool KAHAN>
+__global__ __launch_bounds__(kFillThreads) void k_fill_flow(FillArgs a, const float* w, const float* lj, float* om)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const SampleConst& sc = a.sc;
+    const int D = sc.D;
+    const uint32_t ng = sc.ng;
+    const int tid = threadIdx.x;
+    const LdsPlan lp = lds_plan(D, (int)ng, 4, a.lds_hist, a.tile, sc.n_aux);
+    const FillLds<float> L(smem, lp);
+    const int nbins = D * (int)ng;
+    const float* gsrc = reinterpret_cast<const float*>(a.grid);
+    for (int i = tid; i < D * (int)(ng + 1); i += kFillThreads) L.gl[i] = gsrc[i];
+    for (int i = tid; i < sc.n_aux; i += kFillThreads) L.auxl[i] = sc.aux_f[i];
+    if (a.lds_hist) {
+        for (int i = tid; i < nbins; i += kFillThreads) {
+            L.hl[i] = 0.0;
+            L.cl[i] = 0u;
+        }
+    }
+    WarpedPath<FAM> sp(sc, L.auxl, w, lj, om);
+    LaneTotal<KAHAN> totI, totV;
+    double vmax = 0.0;
+    unsigned long long bad = 0;
+    TileIO io;
+    io.t = a.t;
+    io.tile = a.tile;
+    io.per_lane = a.per_lane;
+    io.lds_hist = a.lds_hist;
+    io.start = a.start;
+    io.tile_first = a.tile_first;
+    io.v_out = a.v_out;
+    io.side = a.side;
+    io.hist_H = a.hist_H;
+    io.hist_C = a.hist_C;
+    __syncthreads();
+    for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x)
+        fill_tile<float, kFlowDim, KAHAN>(tile, io, L, sp, totI, totV, vmax, bad);
+    if (a.lds_hist) {
+        double* slotH = a.hist_H + (size_t)blockIdx.x * nbins;
+        uint32_t* slotC = a.hist_C + (size_t)blockIdx.x * nbins;
+        for (int i = tid; i < nbins; i += kFillThreads) {
+            slotH[i] = L.hl[i];
+            slotC[i] = L.cl[i];
+        }
+    }
+    double sI, sV, mx;
+    wg_reduce_totals(totI.value(), totV.value(), vmax, L.red, sI, sV, mx);
+    if (tid == 0) {
+        a.wg_part[2 * blockIdx.x] = sI;
+        a.wg_part[2 * blockIdx.x + 1] = sV;
+        atomicMax(a.vmax, (unsigned long long)__double_as_longlong(mx));
+    }
+    if (bad) atomicAdd(a.nonfinite, bad);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_flow_pack(const float* theta, void* packed, hipStream_t st)
+{
+    const int n = kFlowLayers * kPLayer;
+    hipLaunchKernelGGL(k_flow_pack, dim3((n + 255) / 256), dim3(256), 0, st, theta, (bf16x8*)packed);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma_probe(const float* A, const float* B, float* D, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, st, A, B, D);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_sample(const FlowSampleArgs& a, int n_wg, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_flow_sample, dim3(n_wg), dim3(kFlowThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int FAM>
+static hipError_t launch_fill_flow_fam(const FillArgs& a, const float* w, const float* lj, float* om, int n_wg,
+                                       size_t lds, hipStream_t st)
+{
+    if (a.accum == 1) {
+        hipFuncSetAttribute((const void*)k_fill_flow<FAM, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_fill_flow<FAM, true>), dim3(n_wg), dim3(kFillThreads), lds, st, a, w, lj, om);
+    } else {
+        hipFuncSetAttribute((const void*)k_fill_flow<FAM, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_fill_flow<FAM, false>), dim3(n_wg), dim3(kFillThreads), lds, st, a, w, lj, om);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_flow(const FillArgs& a, const float* w, const float* lj, float* om, int n_wg, size_t lds,
+                            hipStream_t st)
+{
+    switch (a.sc.family) {
+    case F_GAUSS_DIAG: return launch_fill_flow_fam<F_GAUSS_DIAG>(a, w, lj, om, n_wg, lds, st);
+    case F_GENZ_PPEAK: return launch_fill_flow_fam<F_GENZ_PPEAK>(a, w, lj, om, n_wg, lds, st);
+    case F_GENZ_GAUSS: return launch_fill_flow_fam<F_GENZ_GAUSS>(a, w, lj, om, n_wg, lds, st);
+    case F_GAUSS_CORR: return launch_fill_flow_fam<F_GAUSS_CORR>(a, w, lj, om, n_wg, lds, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace vg

@@ -1,0 +1,71 @@
+// The learned warp: a coupling flow F on [0,1]^16 stacked on the VEGAS map
+// (stratified y -> w = F(y) -> x = map(w)); shapes, parameter layout and the
+// launch records of its kernels.
+//
+// Four coupling layers.  Layer l keeps the axes A_l and moves the others
+// (B_l): A = {0..7}, {8..15}, even axes, odd axes.  The conditioner of a
+// layer is an MLP 8 -> 64 -> 64 -> 8 x 16 with ReLU, fed x = 2 z_A - 1; its
+// 16 outputs per moved axis are bin logits, p = (1 - eps) softmax + eps/16,
+// and the axis moves by the piecewise-linear CDF of p (derivative 16 p_b in
+// bin b), so log J_F is a sum of logs and exact.  Matrix products run on
+// BF16 MFMA with FP32 accumulation; everything else is FP32.
+#pragma once
+#include <stdint.h>
+
+#include "layout.hpp"
+
+namespace vg {
+
+constexpr int kFlowDim = 16;
+constexpr int kFlowHidden = 64;
+constexpr int kFlowBins = 16;
+constexpr int kFlowLayers = 4;
+constexpr int kFlowHalf = 8;                   // |A| = |B|
+constexpr float kFlowEps = 1e-3f;
+
+// per-layer parameter offsets (floats; row-major W[out][in])
+constexpr int kFW1 = 0;                                    // [64][8]
+constexpr int kFB1 = kFW1 + kFlowHidden * kFlowHalf;       // [64]
+constexpr int kFW2 = kFB1 + kFlowHidden;                   // [64][64]
+constexpr int kFB2 = kFW2 + kFlowHidden * kFlowHidden;     // [64]
+constexpr int kFW3 = kFB2 + kFlowHidden;                   // [128][64]
+constexpr int kFB3 = kFW3 + kFlowHalf * kFlowBins * kFlowHidden;   // [128]
+constexpr int kFLayer = kFB3 + kFlowHalf * kFlowBins;      // 13056
+constexpr int kFParams = kFlowLayers * kFLayer;
+
+// Packed BF16 operands of one layer, one 8-value entry per (tile, k-step,
+// lane), for v_mfma_f32_32x32x16_bf16 (B operand: lane l holds
+// B[8 (l/32) + j][l % 32], j < 8):
+//   F1: x (k = axis, 16 with the B axes zeroed) . W1^T      [2 n-tiles]
+//   F2: h1 . W2^T                                          [2 n-tiles][4 k]
+//   F3: h2 . W3^T                                          [4 n-tiles][4 k]
+//   R3: dO . W3     (backward)                             [2 n-tiles][8 k]
+//   R2: dA2 . W2                                           [2 n-tiles][4 k]
+//   R1: dA1 . W1 (n = axis, 16 of 32 used)                 [1 n-tile][4 k]
+constexpr int kPF1 = 0;
+constexpr int kPF2 = kPF1 + 2 * 64;
+constexpr int kPF3 = kPF2 + 2 * 4 * 64;
+constexpr int kPR3 = kPF3 + 4 * 4 * 64;
+constexpr int kPR2 = kPR3 + 2 * 8 * 64;
+constexpr int kPR1 = kPR2 + 2 * 4 * 64;
+constexpr int kPLayer = kPR1 + 4 * 64;           // 3456 entries of 16 bytes
+
+// axis c is conditioning (in A) in layer l
+__host__ __device__ inline bool flow_in_a(int l, int c)
+{
+    return l == 0 ? c < 8 : l == 1 ? c >= 8 : l == 2 ? (c & 1) == 0 : (c & 1) == 1;
+}
+// position of axis c inside its set (A or B) of layer l
+__host__ __device__ inline int flow_pos(int l, int c) { return l < 2 ? (c & 7) : (c >> 1); }
+
+struct FlowSampleArgs {
+    SampleConst sc;
+    uint32_t t;
+    const uint32_t* start;        // [N_c+1]
+    const float* theta;           // FP32 parameters (biases are read from here)
+    const void* packed;           // [4][kPLayer] x 16 bytes of BF16
+    float* w;                     // [N][16] out
+    float* lj;                    // [N] out: log J_F
+};
+
+}  // namespace vg

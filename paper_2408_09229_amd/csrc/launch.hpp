@@ -6,6 +6,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "flow.hpp"
 #include "layout.hpp"
 
 namespace vg {
@@ -75,6 +76,12 @@ hipError_t launch_batch_estimate(const BatchArgs& a, hipStream_t st);
 hipError_t launch_batch_alloc(const BatchArgs& a, bool any_general_beta, hipStream_t st);
 hipError_t launch_batch_map(const BatchArgs& a, int max_ng, hipStream_t st);
 hipError_t launch_batch_prep(const BatchArgs& a, hipStream_t st);
+
+hipError_t launch_flow_pack(const float* theta, void* packed, hipStream_t st);
+hipError_t launch_mfma_probe(const float* A, const float* B, float* D, hipStream_t st);
+hipError_t launch_flow_sample(const FlowSampleArgs& a, int n_wg, hipStream_t st);
+hipError_t launch_fill_flow(const FillArgs& a, const float* w, const float* lj, float* om, int n_wg, size_t lds,
+                            hipStream_t st);
 
 constexpr int kAllocThreads = 1024;
 constexpr int kAllocPerThread = 4;
