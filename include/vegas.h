@@ -224,7 +224,9 @@ vegas_status vegas_get_timing(vegas_ctx* ctx, double* ms, int32_t* n_iter);
  *   GAUSS_DIAG, GENZ_PPEAK, GENZ_GAUSS, GAUSS_CORR. */
 typedef struct {
     float   lr;               /* Adam step of the warp's training */
-    int32_t train;            /* 1: train after every warped iteration */
+    int32_t train;            /* 1: one Adam step after every warped iteration */
+    int32_t loss;             /* 0: variance, c_k ~ omega_k^2; 1: KL, c_k ~ |omega_k| */
+    int32_t judge;            /* 1: judge every warped iteration against plain VEGAS+ */
 } vegas_flow_config;
 
 int32_t vegas_flow_n_params(void);
@@ -236,14 +238,35 @@ vegas_status vegas_flow_workspace_size(const vegas_ctx* ctx, size_t* bytes);
  * starts disabled. */
 vegas_status vegas_flow_attach(vegas_ctx* ctx, const vegas_flow_config* cfg, const float* params,
                                void* d_workspace, size_t bytes);
-/* on = 1: the following iterations sample through the warp. */
+/* on = 1: the following iterations sample through the warp.  Enabling
+ * takes the judge's reference from the last (up to five) plain iterations:
+ * the median sigma_t^2 and the inverse-variance mean of I_t.
+ * With cfg.judge set, every warped iteration t is kept or rejected.  It is
+ * kept when sigma_t^2 <= 2 x the reference and |I_t - I_ref| <=
+ * 5 sqrt(sigma_t^2 + sigma_ref^2).  A kept iteration's parameters become the accepted ones,
+ * then one training step follows if cfg.train is set.  A rejected one
+ * restores the accepted parameters and restarts Adam.  Three rejections in
+ * a row switch the warp off, and plain VEGAS+ continues.  Warped and plain
+ * iterations are both unbiased and combine by Eq. 8-9 as usual.  The judge
+ * reads each warped iteration's estimate, so it synchronises the stream
+ * once per warped iteration. */
 vegas_status vegas_flow_enable(vegas_ctx* ctx, int32_t on);
+/* The warp's state: enabled now, warped iterations kept and rejected by the
+ * judge (host pointers, any may be NULL). */
+vegas_status vegas_flow_status(const vegas_ctx* ctx, int32_t* on, int32_t* accepted, int32_t* rejected);
 /* Synchronous copies of the FP32 parameters (host pointers). */
 vegas_status vegas_flow_get_params(vegas_ctx* ctx, float* params);
 vegas_status vegas_flow_set_params(vegas_ctx* ctx, const float* params);
 /* Test hook, synchronous.  The last warped iteration's samples: w [N][16],
  * log J_F [N] and weight omega [N] (FP32, host pointers; any may be NULL). */
 vegas_status vegas_flow_get_samples(vegas_ctx* ctx, float* w, float* lj, float* omega);
+/* Test hook, synchronous.  Gradient of the warp's training loss on the last
+ * warped iteration's samples (no parameter update), host pointer
+ * grad[n_params].  Loss: sum_k c_k log J_F(F^-1(w_k)) with c_k as set by
+ * vegas_flow_config.loss, normalised to sum 1.  With the variance loss its
+ * gradient is a positive multiple of the gradient of the estimator's
+ * variance. */
+vegas_status vegas_flow_grad(vegas_ctx* ctx, float* grad);
 /* Test hook, synchronous, on the current device.  One BF16 matrix product
  * D = A B.  Device pointers: A [32][16], B [16][32], D [32][32], all FP32
  * row-major.  A and B are rounded to BF16 first.  It checks the lane layout

@@ -58,7 +58,7 @@ class vegas_info(C.Structure):
 
 
 class vegas_flow_config(C.Structure):
-    _fields_ = [("lr", C.c_float), ("train", C.c_int32)]
+    _fields_ = [("lr", C.c_float), ("train", C.c_int32), ("loss", C.c_int32), ("judge", C.c_int32)]
 
 
 class vegas_batch_info(C.Structure):
@@ -97,9 +97,11 @@ _DECL = {
     "vegas_flow_workspace_size": (_st, [_vp, C.POINTER(C.c_size_t)]),
     "vegas_flow_attach": (_st, [_vp, C.POINTER(vegas_flow_config), _vp, _vp, C.c_size_t]),
     "vegas_flow_enable": (_st, [_vp, C.c_int32]),
+    "vegas_flow_status": (_st, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "vegas_flow_get_params": (_st, [_vp, _vp]),
     "vegas_flow_set_params": (_st, [_vp, _vp]),
     "vegas_flow_get_samples": (_st, [_vp, _vp, _vp, _vp]),
+    "vegas_flow_grad": (_st, [_vp, _vp]),
     "vegas_mfma_probe": (_st, [_vp, _vp, _vp]),
     "vegas_batch_workspace_size": (_st, [C.c_int32, _vp, _vp, C.POINTER(C.c_size_t)]),
     "vegas_batch_create": (_st, [C.c_int32, _vp, _vp, _vp, C.c_size_t, _vp, C.c_char_p, C.POINTER(_vp)]),
@@ -294,7 +296,8 @@ class Vegas:
         return ms, n.value
 
     # -- learned warp -------------------------------------------------------
-    def attach_flow(self, params, lr: float = 1e-4, train: bool = False):
+    def attach_flow(self, params, lr: float = 1e-4, train: bool = False, loss: str = "variance",
+                    judge: bool = False):
         """Attach a coupling-flow warp (initial FP32 parameters ``params``)."""
         import torch
         n = C.c_size_t()
@@ -303,12 +306,18 @@ class Vegas:
         p = np.ascontiguousarray(params, dtype=np.float32)
         if p.size != vegas_flow_n_params():
             raise ValueError("wrong number of flow parameters")
-        self.fcfg = vegas_flow_config(lr, int(train))
+        self.fcfg = vegas_flow_config(lr, int(train), {"variance": 0, "kl": 1}[loss], int(judge))
         check(vegas_flow_attach(self.h, C.byref(self.fcfg), _dptr(p), C.c_void_p(self.fws.data_ptr()), n.value),
               "vegas_flow_attach")
 
     def enable_flow(self, on: bool = True):
         check(vegas_flow_enable(self.h, int(on)), "vegas_flow_enable")
+
+    def flow_status(self):
+        """(enabled, warped iterations kept, rejected) as judged."""
+        on, a, r = C.c_int32(), C.c_int32(), C.c_int32()
+        check(vegas_flow_status(self.h, C.byref(on), C.byref(a), C.byref(r)), "vegas_flow_status")
+        return bool(on.value), a.value, r.value
 
     def flow_params(self):
         p = np.zeros(vegas_flow_n_params(), np.float32)
@@ -318,6 +327,12 @@ class Vegas:
     def set_flow_params(self, params):
         p = np.ascontiguousarray(params, dtype=np.float32)
         check(vegas_flow_set_params(self.h, _dptr(p)), "vegas_flow_set_params")
+
+    def flow_grad(self):
+        """Gradient of the warp's loss on the last warped iteration's samples."""
+        g = np.zeros(vegas_flow_n_params(), np.float32)
+        check(vegas_flow_grad(self.h, _dptr(g)), "vegas_flow_grad")
+        return g
 
     def flow_samples(self):
         """(w [N][16], log J_F [N], omega [N]) of the last warped iteration."""

@@ -18,7 +18,7 @@ UBENCH_OUT = os.path.join(HERE, "libvegas_issue_rates.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("VEGAS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["fill.hip", "update.hip", "ordered.hip", "batch.hip", "flow.hip", "api.hip", "batch_api.hip"]
+SOURCES = ["fill.hip", "update.hip", "ordered.hip", "batch.hip", "flow.hip", "flow_train.hip", "api.hip", "batch_api.hip"]
 
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

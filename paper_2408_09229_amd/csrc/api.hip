@@ -245,7 +245,15 @@ struct vegas_ctx {
     bool flow_on = false;
     vegas_flow_config fcfg{};
     unsigned char* fws = nullptr;
-    size_t f_theta = 0, f_packed = 0, f_w = 0, f_lj = 0, f_om = 0;
+    size_t f_theta = 0, f_packed = 0, f_w = 0, f_lj = 0, f_om = 0, f_U = 0, f_G0 = 0, f_G1 = 0, f_part = 0,
+           f_grad = 0, f_m = 0, f_v = 0, f_sumsq = 0;
+    int f_nwg = 0;                     // workgroups of the training passes
+    int f_step = 0;                    // Adam steps taken
+    size_t f_acc = 0;                  // last accepted parameters
+    std::vector<uint8_t> warped;       // per iteration: 1 = sampled through the warp
+    double ref_I = 0.0, ref_s2 = INFINITY;   // plain VEGAS+ reference of the judge
+    int rejects = 0;                   // consecutive rejected warped iterations
+    int n_accepted = 0, n_rejected = 0;
 
     ~vegas_ctx()
     {
@@ -356,6 +364,9 @@ vegas_status run_update(vegas_ctx* c, int t, int n_slots, bool timed)
     return VEGAS_OK;
 }
 
+vegas_status flow_train_step(vegas_ctx* c);
+bool flow_judge(vegas_ctx* c, int t);
+
 vegas_status run_iteration(vegas_ctx* c, bool integrate)
 {
     if (c->n_run >= c->max_iter) return fail(VEGAS_ESTATE, "iteration log full (max_iter = %d)", c->max_iter);
@@ -389,6 +400,7 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
         if (s != VEGAS_OK) return s;
         c->n_run = t + 1;
         c->combined.push_back(integrate ? 1 : 0);
+        c->warped.push_back(0);
         c->have_prev = true;
         return VEGAS_OK;
     }
@@ -448,11 +460,21 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
     fa.iter_out = c->at<double>(c->p.iter) + 2 * t;
     HIPCHK(launch_final(fa, c->stream));
     HIPCHK(c->mark());
-    const vegas_status s = run_update(c, t, lds_hist ? c->n_wg : 1, true);
+    vegas_status s = run_update(c, t, lds_hist ? c->n_wg : 1, true);
     if (s != VEGAS_OK) return s;
+    const bool warped = c->flow_on;
     c->n_run = t + 1;
     c->combined.push_back(integrate ? 1 : 0);
+    c->warped.push_back(warped ? 1 : 0);
     c->have_prev = true;
+    if (warped) {
+        const bool keep = c->fcfg.judge ? flow_judge(c, t) : true;
+        if (!c->flow_attached) return fail(VEGAS_EDEVICE, "flow judge failed");
+        if (keep && c->flow_on && c->fcfg.train) {
+            s = flow_train_step(c);
+            if (s != VEGAS_OK) return s;
+        }
+    }
     return VEGAS_OK;
 }
 
@@ -907,10 +929,10 @@ vegas_status vegas_sample_probe(vegas_ctx* c, uint32_t t, uint64_t k0, int64_t n
 namespace {
 
 struct FlowPlan {
-    size_t theta, packed, w, lj, om, total;
+    size_t theta, packed, w, lj, om, U, G0, G1, part, grad, m, v, sumsq, acc, total;
 };
 
-FlowPlan flow_plan(uint32_t n_eval)
+FlowPlan flow_plan(uint32_t n_eval, int n_wg)
 {
     FlowPlan p;
     size_t o = 0;
@@ -924,8 +946,96 @@ FlowPlan flow_plan(uint32_t n_eval)
     p.w = take(sizeof(float) * kFlowDim * (size_t)n_eval);
     p.lj = take(sizeof(float) * (size_t)n_eval);
     p.om = take(sizeof(float) * (size_t)n_eval);
+    p.U = take(sizeof(float) * 3 * kFlowDim * (size_t)n_eval);
+    p.G0 = take(sizeof(float) * kFlowDim * (size_t)n_eval);
+    p.G1 = take(sizeof(float) * kFlowDim * (size_t)n_eval);
+    p.part = take(sizeof(float) * kFLayer * (size_t)n_wg);
+    p.grad = take(sizeof(float) * kFParams);
+    p.m = take(sizeof(float) * kFParams);
+    p.v = take(sizeof(float) * kFParams);
+    p.sumsq = take(sizeof(double) * 2);
+    p.acc = take(sizeof(float) * kFParams);
     p.total = o;
     return p;
+}
+
+int flow_train_wg(const vegas_ctx* c) { return 2 * std::max(c->n_wg, 1); }
+
+FlowTrainArgs flow_train_args(vegas_ctx* c)
+{
+    FlowTrainArgs a;
+    a.n = c->g.n_eval;
+    a.layer = 0;
+    a.theta = reinterpret_cast<const float*>(c->fws + c->f_theta);
+    a.packed = c->fws + c->f_packed;
+    a.w = reinterpret_cast<const float*>(c->fws + c->f_w);
+    a.om = reinterpret_cast<const float*>(c->fws + c->f_om);
+    a.sumsq = reinterpret_cast<const double*>(c->fws + c->f_sumsq);
+    a.gamma = c->fcfg.loss == 1 ? 1 : 2;
+    a.U = reinterpret_cast<float*>(c->fws + c->f_U);
+    a.g_in = nullptr;
+    a.g_out = nullptr;
+    a.part = reinterpret_cast<float*>(c->fws + c->f_part);
+    return a;
+}
+
+// gradient of the warp's loss on the last warped iteration's samples
+vegas_status flow_gradient(vegas_ctx* c)
+{
+    HIPCHK(launch_flow_gradient(flow_train_args(c), c->f_nwg, reinterpret_cast<float*>(c->fws + c->f_G0),
+                                reinterpret_cast<float*>(c->fws + c->f_G1), reinterpret_cast<float*>(c->fws + c->f_grad),
+                                c->stream));
+    return VEGAS_OK;
+}
+
+// The judge of a warped iteration t (its estimate against the plain VEGAS+
+// reference taken when the warp was enabled: sigma^2 at most twice the
+// reference median, estimate within 5 sigma).  Kept: the warp that sampled
+// it becomes the accepted one.  Rejected: the accepted warp comes back, the
+// optimiser restarts, and after three rejections in a row the warp is
+// switched off (plain VEGAS+ continues).  Returns whether the warp stays.
+bool flow_judge(vegas_ctx* c, int t)
+{
+    double it[2];
+    if (hipMemcpy(it, c->at<double>(c->p.iter) + 2 * t, sizeof it, hipMemcpyDeviceToHost) != hipSuccess) {
+        c->flow_attached = false;
+        return false;
+    }
+    const double I = it[0], s2 = it[1];
+    // a single iteration's sigma^2 is a noisy figure: reject only what is
+    // clearly worse than plain VEGAS+ (twice its median)
+    bool ok = std::isfinite(I) && std::isfinite(s2) && s2 <= 2.0 * c->ref_s2;
+    if (ok && std::isfinite(c->ref_s2)) ok = std::fabs(I - c->ref_I) <= 5.0 * std::sqrt(s2 + c->ref_s2);
+    float* th = reinterpret_cast<float*>(c->fws + c->f_theta);
+    float* acc = reinterpret_cast<float*>(c->fws + c->f_acc);
+    if (ok) {
+        c->rejects = 0;
+        c->n_accepted += 1;
+        (void)hipMemcpyAsync(acc, th, sizeof(float) * kFParams, hipMemcpyDeviceToDevice, c->stream);
+        return true;
+    }
+    c->rejects += 1;
+    c->n_rejected += 1;
+    (void)hipMemcpyAsync(th, acc, sizeof(float) * kFParams, hipMemcpyDeviceToDevice, c->stream);
+    (void)launch_flow_pack(th, c->fws + c->f_packed, c->stream);
+    (void)launch_reset(reinterpret_cast<unsigned long long*>(c->fws + c->f_m), kFParams / 2, c->stream);
+    (void)launch_reset(reinterpret_cast<unsigned long long*>(c->fws + c->f_v), kFParams / 2, c->stream);
+    c->f_step = 0;
+    if (c->rejects >= 3) c->flow_on = false;
+    return false;
+}
+
+// one training step: gradient, Adam, BF16 repack
+vegas_status flow_train_step(vegas_ctx* c)
+{
+    vegas_status s = flow_gradient(c);
+    if (s != VEGAS_OK) return s;
+    c->f_step += 1;
+    float* th = reinterpret_cast<float*>(c->fws + c->f_theta);
+    HIPCHK(launch_flow_adam(th, reinterpret_cast<const float*>(c->fws + c->f_grad), reinterpret_cast<float*>(c->fws + c->f_m),
+                            reinterpret_cast<float*>(c->fws + c->f_v), c->fcfg.lr, c->f_step, c->stream));
+    HIPCHK(launch_flow_pack(th, c->fws + c->f_packed, c->stream));
+    return VEGAS_OK;
 }
 
 vegas_status flow_check(const vegas_ctx* c)
@@ -950,7 +1060,7 @@ vegas_status vegas_flow_workspace_size(const vegas_ctx* c, size_t* bytes)
     if (!c || !bytes) return fail(VEGAS_EINVAL, "bad arguments");
     const vegas_status s = flow_check(c);
     if (s != VEGAS_OK) return s;
-    *bytes = flow_plan(c->g.n_eval).total;
+    *bytes = flow_plan(c->g.n_eval, flow_train_wg(c)).total;
     return VEGAS_OK;
 }
 
@@ -961,9 +1071,11 @@ vegas_status vegas_flow_attach(vegas_ctx* c, const vegas_flow_config* cfg, const
     vegas_status s = flow_check(c);
     if (s != VEGAS_OK) return s;
     if (((uintptr_t)d_ws & 255u) != 0) return fail(VEGAS_EINVAL, "flow workspace must be 256-byte aligned");
-    const FlowPlan p = flow_plan(c->g.n_eval);
+    const int nwg = flow_train_wg(c);
+    const FlowPlan p = flow_plan(c->g.n_eval, nwg);
     if (bytes < p.total) return fail(VEGAS_ENOMEM, "flow workspace has %zu bytes, needs %zu", bytes, p.total);
     if (!(cfg->lr >= 0.f) || !std::isfinite(cfg->lr)) return fail(VEGAS_EINVAL, "lr must be finite and >= 0");
+    if (cfg->loss != 0 && cfg->loss != 1) return fail(VEGAS_EINVAL, "loss must be 0 (variance) or 1 (KL)");
     for (int i = 0; i < kFParams; ++i)
         if (!std::isfinite(params[i])) return fail(VEGAS_EINVAL, "flow parameter %d is not finite", i);
     c->fcfg = *cfg;
@@ -973,8 +1085,22 @@ vegas_status vegas_flow_attach(vegas_ctx* c, const vegas_flow_config* cfg, const
     c->f_w = p.w;
     c->f_lj = p.lj;
     c->f_om = p.om;
+    c->f_U = p.U;
+    c->f_G0 = p.G0;
+    c->f_G1 = p.G1;
+    c->f_part = p.part;
+    c->f_grad = p.grad;
+    c->f_m = p.m;
+    c->f_v = p.v;
+    c->f_sumsq = p.sumsq;
+    c->f_acc = p.acc;
+    c->f_nwg = nwg;
+    c->f_step = 0;
     c->flow_attached = true;
     c->flow_on = false;
+    HIPCHK(hipMemsetAsync(c->fws + p.m, 0, sizeof(float) * kFParams, c->stream));
+    HIPCHK(hipMemsetAsync(c->fws + p.v, 0, sizeof(float) * kFParams, c->stream));
+    HIPCHK(hipMemsetAsync(c->fws + p.om, 0, sizeof(float) * c->g.n_eval, c->stream));
     return vegas_flow_set_params(c, params);
 }
 
@@ -982,7 +1108,53 @@ vegas_status vegas_flow_enable(vegas_ctx* c, int32_t on)
 {
     if (!c) return fail(VEGAS_EINVAL, "bad arguments");
     if (on && !c->flow_attached) return fail(VEGAS_ESTATE, "no flow attached");
+    if (on && !c->flow_on) {
+        // the judge's reference: the last (up to five) plain iterations,
+        // median sigma^2 and inverse-variance mean
+        std::vector<double> I(c->n_run), s2(c->n_run);
+        if (c->n_run > 0) {
+            std::vector<double> buf(2 * (size_t)c->n_run);
+            HIPCHK(hipStreamSynchronize(c->stream));
+            HIPCHK(hipMemcpy(buf.data(), c->at<double>(c->p.iter), sizeof(double) * buf.size(), hipMemcpyDeviceToHost));
+            for (int t = 0; t < c->n_run; ++t) {
+                I[t] = buf[2 * t];
+                s2[t] = buf[2 * t + 1];
+            }
+        }
+        std::vector<double> rs2, rI;
+        for (int t = c->n_run - 1; t >= 0 && (int)rs2.size() < 5; --t)
+            if (!c->warped[t] && s2[t] > 0.0 && std::isfinite(s2[t])) {
+                rs2.push_back(s2[t]);
+                rI.push_back(I[t]);
+            }
+        if (rs2.empty()) {
+            c->ref_s2 = INFINITY;
+            c->ref_I = 0.0;
+        } else {
+            std::vector<double> sorted = rs2;
+            std::sort(sorted.begin(), sorted.end());
+            c->ref_s2 = sorted[sorted.size() / 2];
+            double w = 0.0, wi = 0.0;
+            for (size_t i = 0; i < rs2.size(); ++i) {
+                w += 1.0 / rs2[i];
+                wi += rI[i] / rs2[i];
+            }
+            c->ref_I = wi / w;
+        }
+        c->rejects = 0;
+        HIPCHK(hipMemcpyAsync(c->fws + c->f_acc, c->fws + c->f_theta, sizeof(float) * kFParams,
+                              hipMemcpyDeviceToDevice, c->stream));
+    }
     c->flow_on = on != 0;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_flow_status(const vegas_ctx* c, int32_t* on, int32_t* accepted, int32_t* rejected)
+{
+    if (!c) return fail(VEGAS_EINVAL, "bad arguments");
+    if (on) *on = c->flow_on ? 1 : 0;
+    if (accepted) *accepted = c->n_accepted;
+    if (rejected) *rejected = c->n_rejected;
     return VEGAS_OK;
 }
 
@@ -1014,6 +1186,17 @@ vegas_status vegas_flow_get_samples(vegas_ctx* c, float* w, float* lj, float* om
     if (w) HIPCHK(hipMemcpy(w, c->fws + c->f_w, sizeof(float) * kFlowDim * n, hipMemcpyDeviceToHost));
     if (lj) HIPCHK(hipMemcpy(lj, c->fws + c->f_lj, sizeof(float) * n, hipMemcpyDeviceToHost));
     if (om) HIPCHK(hipMemcpy(om, c->fws + c->f_om, sizeof(float) * n, hipMemcpyDeviceToHost));
+    return VEGAS_OK;
+}
+
+vegas_status vegas_flow_grad(vegas_ctx* c, float* grad)
+{
+    if (!c || !grad) return fail(VEGAS_EINVAL, "bad arguments");
+    if (!c->flow_attached) return fail(VEGAS_ESTATE, "no flow attached");
+    const vegas_status s = flow_gradient(c);
+    if (s != VEGAS_OK) return s;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(grad, c->fws + c->f_grad, sizeof(float) * kFParams, hipMemcpyDeviceToHost));
     return VEGAS_OK;
 }
 
@@ -1100,6 +1283,7 @@ vegas_status vegas_set_state(vegas_ctx* c, const void* buf, size_t bytes)
         HIPCHK(hipMemcpy(c->at<double>(c->p.iter), o, sizeof(double) * 2 * h.n_run, hipMemcpyHostToDevice));
     o += sizeof(double) * 2 * h.n_run;
     c->combined.assign(o, o + h.n_run);
+    c->warped.assign(h.n_run, 0);
     c->n_run = h.n_run;
     c->have_prev = h.have_prev != 0;
     unsigned long long bad = h.nonfinite;

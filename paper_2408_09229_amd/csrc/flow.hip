@@ -14,22 +14,11 @@
 #include "families.hpp"
 #include "fill_dev.hpp"
 #include "flow.hpp"
+#include "flow_dev.hpp"
 #include "launch.hpp"
 #include "layout.hpp"
 
 namespace vg {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-__device__ __forceinline__ f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c)
-{
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-}
-
-// output layout of the 32x32 product: register r of lane l holds row
-// mrow(l, r), column l % 32
-__device__ __forceinline__ int mrow(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
 // ---------------------------------------------------------------------------
 // operand packing (after every parameter change)
@@ -102,95 +91,6 @@ __global__ void k_mfma_probe(const float* A, const float* B, float* D)
     f32x16 c = {};
     c = mfma(a, b, c);
     for (int r = 0; r < 16; ++r) D[mrow(l, r) * 32 + (l & 31)] = c[r];
-}
-
-// ---------------------------------------------------------------------------
-// one coupling layer for the 32 samples of a wavefront (forward direction)
-// ---------------------------------------------------------------------------
-constexpr int kFlowWaves = 4;
-constexpr int kFlowThreads = 64 * kFlowWaves;
-struct __align__(16) FlowLds {
-    __bf16 h[kFlowWaves][32 * kFlowHidden];            // hidden activations [sample][unit]
-    float o[kFlowWaves][32 * kFlowHalf * kFlowBins];   // bin logits [sample][axis * 16 + bin]
-};
-
-// MLP of layer l for the wave's 32 samples: logits into o[sample][.]
-// z: the lane's 8 coordinates (axes 8 (lane/32) + j of sample lane % 32)
-__device__ __forceinline__ void flow_mlp(int l, const float (&z)[8], const float* __restrict__ P,
-                                         const bf16x8* __restrict__ pk, __bf16* hb, float* ob)
-{
-    const int lane = threadIdx.x & 63;
-    const int half = lane >> 5;
-    const int n32 = lane & 31;
-    bf16x8 xa;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) xa[j] = flow_in_a(l, 8 * half + j) ? (__bf16)(2.f * z[j] - 1.f) : (__bf16)0.f;
-    // h1 = relu(W1 x + b1)
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-        f32x16 acc = {};
-        acc = mfma(xa, pk[kPF1 + nt * 64 + lane], acc);
-        const float bias = P[kFB1 + nt * 32 + n32];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const float v = acc[r] + bias;
-            hb[mrow(lane, r) * kFlowHidden + nt * 32 + n32] = (__bf16)(v > 0.f ? v : 0.f);
-        }
-    }
-    __syncthreads();
-    // h2 = relu(W2 h1 + b2)
-    bf16x8 ha[4];
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) ha[ks] = *reinterpret_cast<const bf16x8*>(hb + n32 * kFlowHidden + ks * 16 + 8 * half);
-    f32x16 acc2[2];
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-        f32x16 acc = {};
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) acc = mfma(ha[ks], pk[kPF2 + (nt * 4 + ks) * 64 + lane], acc);
-        acc2[nt] = acc;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-        const float bias = P[kFB2 + nt * 32 + n32];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const float v = acc2[nt][r] + bias;
-            hb[mrow(lane, r) * kFlowHidden + nt * 32 + n32] = (__bf16)(v > 0.f ? v : 0.f);
-        }
-    }
-    __syncthreads();
-    // logits = W3 h2 + b3
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) ha[ks] = *reinterpret_cast<const bf16x8*>(hb + n32 * kFlowHidden + ks * 16 + 8 * half);
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        f32x16 acc = {};
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) acc = mfma(ha[ks], pk[kPF3 + (nt * 4 + ks) * 64 + lane], acc);
-        const float bias = P[kFB3 + nt * 32 + n32];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) ob[mrow(lane, r) * (kFlowHalf * kFlowBins) + nt * 32 + n32] = acc[r] + bias;
-    }
-    __syncthreads();
-}
-
-// bin probabilities of one moved axis from its 16 logits
-__device__ __forceinline__ void flow_probs(const float* lg, float (&p)[kFlowBins])
-{
-    float m = lg[0];
-#pragma unroll
-    for (int k = 1; k < kFlowBins; ++k) m = fmaxf(m, lg[k]);
-    float s = 0.f;
-#pragma unroll
-    for (int k = 0; k < kFlowBins; ++k) {
-        p[k] = expf(lg[k] - m);
-        s += p[k];
-    }
-    const float a = (1.f - kFlowEps) / s;
-#pragma unroll
-    for (int k = 0; k < kFlowBins; ++k) p[k] = fmaf(a, p[k], kFlowEps / kFlowBins);
 }
 
 // ---------------------------------------------------------------------------

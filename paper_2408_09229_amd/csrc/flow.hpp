@@ -68,4 +68,26 @@ struct FlowSampleArgs {
     float* lj;                    // [N] out: log J_F
 };
 
+// Training records.  The loss of an iteration is
+// L = sum_k c_k log J_F(F^-1(w_k)), c_k = |omega_k|^gamma / sum |omega|^gamma,
+// and its
+// gradient is taken through the inverse chain u_3 = w -> u_2 -> u_1 -> u_0:
+// the inverse pass stores u_0..u_2, then one backward pass per layer
+// (l = 0, 1, 2, 3) turns the upstream gradient g = dL/du_{l-1} into
+// dL/du_l and the layer's parameter gradient.
+struct FlowTrainArgs {
+    uint32_t n;                   // samples
+    int32_t layer;                // backward pass: layer index
+    const float* theta;
+    const void* packed;
+    const float* w;               // [N][16]
+    const float* om;              // [N] sample weights
+    const double* sumsq;          // sum of |om|^gamma
+    int32_t gamma;                // 2: variance loss, 1: KL loss
+    float* U;                     // [3][N][16]: u_0, u_1, u_2
+    const float* g_in;            // [N][16] upstream gradient (null: zero)
+    float* g_out;                 // [N][16]
+    float* part;                  // [n_wg][kFLayer] per-workgroup gradient
+};
+
 }  // namespace vg

@@ -1,0 +1,423 @@
+// Training of the learned warp on the samples of one iteration.
+//
+// Loss L = sum_k c_k log J_F(F^-1(w_k)) with c_k = |omega_k|^gamma / sum
+// |omega|^gamma.  gamma = 2: its gradient is a positive multiple of the
+// gradient of the estimator's variance (the warp's density at w is
+// 1 / J_F(F^-1(w))); gamma = 1: of the KL divergence from the normalised
+// |f| to the warp's density, whose sample gradient has lighter tails.  The gradient goes through
+// the inverse chain u_3 = w -> u_2 -> u_1 -> u_0:
+//   k_flow_sumsq    sum of omega^2 (one workgroup, fixed order)
+//   k_flow_inverse  u_2, u_1, u_0 of every sample (MLP on MFMA)
+//   k_flow_grad     one coupling layer l = 0..3 in turn: from the upstream
+//                   g = dL/du_{l-1}, the layer's log-Jacobian and inverse
+//                   transform give dL/dlogits; the MLP backward runs on MFMA
+//                   (dO W3, dA2 W2, dA1 W1); the weight gradients dW =
+//                   sum_samples delta^T activation are MFMA products over the
+//                   workgroup's 128 samples, each wave owning some output
+//                   tiles, accumulated across the workgroup's chunks
+//   k_flow_reduce   per-workgroup gradients summed in workgroup order
+//   k_flow_adam     Adam on the FP32 parameters (then the BF16 repack)
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "flow.hpp"
+#include "flow_dev.hpp"
+#include "launch.hpp"
+
+namespace vg {
+
+constexpr int kSumThreads = 1024;
+
+// sum of |omega|^gamma, gamma = 2 (variance loss) or 1 (KL loss)
+__global__ __launch_bounds__(kSumThreads) void k_flow_sumsq(const float* om, uint32_t n, int gamma, double* out)
+{
+    __shared__ double red[kSumThreads];
+    double s = 0.0;
+    for (uint32_t i = threadIdx.x; i < n; i += kSumThreads) {
+        const double v = fabs((double)om[i]);
+        s += gamma == 2 ? v * v : v;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kSumThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// inverse pass
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kFlowThreads) void k_flow_inverse(FlowTrainArgs a)
+{
+    __shared__ FlowLds S;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int half = lane >> 5;
+    const int n32 = lane & 31;
+    const uint32_t N = a.n;
+    const uint32_t chunks = (N + 31u) / 32u;
+    const uint32_t per_round = gridDim.x * kFlowWaves;
+    const uint32_t rounds = (chunks + per_round - 1u) / per_round;
+    const bf16x8* pk = reinterpret_cast<const bf16x8*>(a.packed);
+    for (uint32_t rd = 0; rd < rounds; ++rd) {
+        const uint32_t chunk = rd * per_round + blockIdx.x * kFlowWaves + wave;
+        const bool live = chunk < chunks;
+        const uint32_t k = live ? min(chunk * 32u + (uint32_t)n32, N - 1u) : 0u;
+        const bool valid = live && chunk * 32u + (uint32_t)n32 < N;
+        float z[8];
+        const float4* wi = reinterpret_cast<const float4*>(a.w + (size_t)k * kFlowDim + 8 * half);
+        const float4 w0 = wi[0], w1 = wi[1];
+        z[0] = w0.x; z[1] = w0.y; z[2] = w0.z; z[3] = w0.w;
+        z[4] = w1.x; z[5] = w1.y; z[6] = w1.z; z[7] = w1.w;
+        for (int l = kFlowLayers - 1; l >= 0; --l) {
+            flow_mlp(l, z, a.theta + (size_t)l * kFLayer, pk + (size_t)l * kPLayer, S.h[wave], S.o[wave]);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int c = 8 * half + j;
+                if (flow_in_a(l, c)) continue;
+                float p[kFlowBins];
+                flow_probs(S.o[wave] + n32 * (kFlowHalf * kFlowBins) + flow_pos(l, c) * kFlowBins, p);
+                const float v = z[j];
+                int b = 0;
+                float cb = 0.f, pb = p[0], cum = 0.f;
+#pragma unroll
+                for (int q = 0; q < kFlowBins; ++q) {
+                    if (cum <= v) {
+                        b = q;
+                        cb = cum;
+                        pb = p[q];
+                    }
+                    cum += p[q];
+                }
+                z[j] = fminf(fmaxf(((float)b + (v - cb) / pb) * (1.f / kFlowBins), 0.f), 1.f);
+            }
+            __syncthreads();
+            if (l > 0 && valid) {
+                float4* uo = reinterpret_cast<float4*>(a.U + ((size_t)(l - 1) * N + k) * kFlowDim + 8 * half);
+                uo[0] = make_float4(z[0], z[1], z[2], z[3]);
+                uo[1] = make_float4(z[4], z[5], z[6], z[7]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// backward pass of one coupling layer
+// ---------------------------------------------------------------------------
+struct __align__(16) FlowGradLds {
+    float o[kFlowWaves][32 * kFlowHalf * kFlowBins];    // logits, then dL/dlogits (FP32)
+    __bf16 h1[kFlowWaves][32 * kFlowHidden];
+    __bf16 h2[kFlowWaves][32 * kFlowHidden];
+    __bf16 da2[kFlowWaves][32 * kFlowHidden];
+    __bf16 da1[kFlowWaves][32 * kFlowHidden];
+    __bf16 x[kFlowWaves][32 * kFlowDim];
+    float dx[kFlowWaves][32 * 32];
+    float red[2][kFlowWaves][kFlowHidden];
+};
+
+__device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
+__global__ __launch_bounds__(kFlowThreads) void k_flow_grad(FlowTrainArgs a)
+{
+    __shared__ FlowGradLds S;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int half = lane >> 5;
+    const int n32 = lane & 31;
+    const int l = a.layer;
+    const uint32_t N = a.n;
+    const float* P = a.theta + (size_t)l * kFLayer;
+    const bf16x8* pk = reinterpret_cast<const bf16x8*>(a.packed) + (size_t)l * kPLayer;
+    const float* uin = l == kFlowLayers - 1 ? a.w : a.U + (size_t)l * N * kFlowDim;
+    const double ss = *a.sumsq;
+    const float inv_ss = ss > 0.0 ? (float)(1.0 / ss) : 0.f;
+    const uint32_t chunks = (N + 31u) / 32u;
+    const uint32_t per_round = gridDim.x * kFlowWaves;
+    const uint32_t rounds = (chunks + per_round - 1u) / per_round;
+    f32x16 acc3[2] = {}, acc2 = {}, acc1 = {};
+    float db3 = 0.f, db2[2] = {0.f, 0.f}, db1[2] = {0.f, 0.f};
+    for (uint32_t rd = 0; rd < rounds; ++rd) {
+        const uint32_t chunk = rd * per_round + blockIdx.x * kFlowWaves + wave;
+        const bool live = chunk < chunks;
+        const uint32_t k = live ? min(chunk * 32u + (uint32_t)n32, N - 1u) : 0u;
+        const bool valid = live && chunk * 32u + (uint32_t)n32 < N;
+        float u[8], g[8];
+        {
+            const float4* ui = reinterpret_cast<const float4*>(uin + (size_t)k * kFlowDim + 8 * half);
+            const float4 u0 = ui[0], u1 = ui[1];
+            u[0] = u0.x; u[1] = u0.y; u[2] = u0.z; u[3] = u0.w;
+            u[4] = u1.x; u[5] = u1.y; u[6] = u1.z; u[7] = u1.w;
+        }
+        if (a.g_in && valid) {
+            const float4* gi = reinterpret_cast<const float4*>(a.g_in + (size_t)k * kFlowDim + 8 * half);
+            const float4 g0 = gi[0], g1 = gi[1];
+            g[0] = g0.x; g[1] = g0.y; g[2] = g0.z; g[3] = g0.w;
+            g[4] = g1.x; g[5] = g1.y; g[6] = g1.z; g[7] = g1.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) g[j] = 0.f;
+        }
+        const float omk = valid ? fabsf(a.om[k]) : 0.f;
+        const float coef = (a.gamma == 2 ? omk * omk : omk) * inv_ss;
+
+        // ---- recompute the conditioner of this layer -----------------------
+        flow_mlp(l, u, P, pk, S.h1[wave], S.o[wave], S.h2[wave], S.x[wave]);
+
+        // ---- log-Jacobian and inverse transform: dL/dlogits ---------------
+        float gn[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int c = 8 * half + j;
+            gn[j] = g[j];
+            if (flow_in_a(l, c)) continue;
+            float* lg = S.o[wave] + n32 * (kFlowHalf * kFlowBins) + flow_pos(l, c) * kFlowBins;
+            float sm[kFlowBins], p[kFlowBins];
+            flow_softmax(lg, sm, p);
+            const float v = u[j];
+            int b = 0;
+            float cb = 0.f, pb = p[0], cum = 0.f;
+#pragma unroll
+            for (int q = 0; q < kFlowBins; ++q) {
+                if (cum <= v) {
+                    b = q;
+                    cb = cum;
+                    pb = p[q];
+                }
+                cum += p[q];
+            }
+            const float gz = g[j];
+            const float ipb = 1.f / pb;
+            const float below = -gz * ipb * (1.f / kFlowBins);
+            const float atb = -gz * (v - cb) * ipb * ipb * (1.f / kFlowBins) + coef * ipb;
+            float dp[kFlowBins], dot = 0.f;
+#pragma unroll
+            for (int q = 0; q < kFlowBins; ++q) {
+                dp[q] = (1.f - kFlowEps) * (q < b ? below : (q == b ? atb : 0.f));
+                dot = fmaf(sm[q], dp[q], dot);
+            }
+#pragma unroll
+            for (int q = 0; q < kFlowBins; ++q) lg[q] = sm[q] * (dp[q] - dot);
+            gn[j] = gz * ipb * (1.f / kFlowBins);
+        }
+        __syncthreads();
+
+        // ---- dH2 = dO W3; dA2 = dH2 (h2 > 0) -------------------------------
+        {
+            f32x16 t[2] = {};
+            const float* orow = S.o[wave] + n32 * (kFlowHalf * kFlowBins) + 8 * half;
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) {
+                bf16x8 av;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) av[j] = (__bf16)orow[ks * 16 + j];
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) t[nt] = mfma(av, pk[kPR3 + (nt * 8 + ks) * 64 + lane], t[nt]);
+            }
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int idx = mrow(lane, r) * kFlowHidden + nt * 32 + n32;
+                    const float d = (float)S.h2[wave][idx] > 0.f ? t[nt][r] : 0.f;
+                    db2[nt] += d;
+                    S.da2[wave][idx] = (__bf16)d;
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- dH1 = dA2 W2; dA1 = dH1 (h1 > 0) ------------------------------
+        {
+            f32x16 t[2] = {};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const bf16x8 av = ld8(S.da2[wave] + n32 * kFlowHidden + ks * 16 + 8 * half);
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) t[nt] = mfma(av, pk[kPR2 + (nt * 4 + ks) * 64 + lane], t[nt]);
+            }
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int idx = mrow(lane, r) * kFlowHidden + nt * 32 + n32;
+                    const float d = (float)S.h1[wave][idx] > 0.f ? t[nt][r] : 0.f;
+                    db1[nt] += d;
+                    S.da1[wave][idx] = (__bf16)d;
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- dX = dA1 W1 (columns = axes) ---------------------------------
+        {
+            f32x16 t = {};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+                t = mfma(ld8(S.da1[wave] + n32 * kFlowHidden + ks * 16 + 8 * half), pk[kPR1 + ks * 64 + lane], t);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) S.dx[wave][mrow(lane, r) * 32 + n32] = t[r];
+        }
+        __syncthreads();
+
+        // ---- dL/du_l: conditioning axes add the MLP's input gradient -------
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int c = 8 * half + j;
+            if (flow_in_a(l, c)) gn[j] = g[j] + 2.f * S.dx[wave][n32 * 32 + c];
+        }
+        if (valid) {
+            float4* go = reinterpret_cast<float4*>(a.g_out + (size_t)k * kFlowDim + 8 * half);
+            go[0] = make_float4(gn[0], gn[1], gn[2], gn[3]);
+            go[1] = make_float4(gn[4], gn[5], gn[6], gn[7]);
+        }
+
+        // ---- weight gradients over the workgroup's 128 samples ------------
+        // dW3[o][h] += sum_s dO[s][o] h2[s][h]: wave owns rows o in
+        // [32 wave, 32 wave + 32), both column tiles
+#pragma unroll 1
+        for (int ks = 0; ks < 8; ++ks) {
+            const int ws = ks >> 1;
+            const int s0 = (ks & 1) * 16 + 8 * half;
+            bf16x8 av, bv0, bv1;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                av[j] = (__bf16)S.o[ws][(s0 + j) * (kFlowHalf * kFlowBins) + wave * 32 + n32];
+                bv0[j] = S.h2[ws][(s0 + j) * kFlowHidden + n32];
+                bv1[j] = S.h2[ws][(s0 + j) * kFlowHidden + 32 + n32];
+            }
+            acc3[0] = mfma(av, bv0, acc3[0]);
+            acc3[1] = mfma(av, bv1, acc3[1]);
+        }
+        // dW2[n2][n1] += sum_s dA2[s][n2] h1[s][n1]: one tile per wave
+        {
+            const int mt = wave >> 1, nt = wave & 1;
+#pragma unroll 1
+            for (int ks = 0; ks < 8; ++ks) {
+                const int ws = ks >> 1;
+                const int s0 = (ks & 1) * 16 + 8 * half;
+                bf16x8 av, bv;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    av[j] = S.da2[ws][(s0 + j) * kFlowHidden + mt * 32 + n32];
+                    bv[j] = S.h1[ws][(s0 + j) * kFlowHidden + nt * 32 + n32];
+                }
+                acc2 = mfma(av, bv, acc2);
+            }
+        }
+        // dW1[h][axis] += sum_s dA1[s][h] x[s][axis]: waves 0 and 1
+        if (wave < 2) {
+#pragma unroll 1
+            for (int ks = 0; ks < 8; ++ks) {
+                const int ws = ks >> 1;
+                const int s0 = (ks & 1) * 16 + 8 * half;
+                bf16x8 av, bv;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    av[j] = S.da1[ws][(s0 + j) * kFlowHidden + wave * 32 + n32];
+                    bv[j] = n32 < kFlowDim ? S.x[ws][(s0 + j) * kFlowDim + n32] : (__bf16)0.f;
+                }
+                acc1 = mfma(av, bv, acc1);
+            }
+        }
+        // db3: one output per thread, FP32
+        if (threadIdx.x < kFlowHalf * kFlowBins) {
+            for (int ws = 0; ws < kFlowWaves; ++ws)
+                for (int s = 0; s < 32; ++s) db3 += S.o[ws][s * (kFlowHalf * kFlowBins) + threadIdx.x];
+        }
+        __syncthreads();
+    }
+
+    // ---- this workgroup's gradient of layer l ------------------------------
+    float* out = a.part + (size_t)blockIdx.x * kFLayer;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            out[kFW3 + (wave * 32 + mrow(lane, r)) * kFlowHidden + nt * 32 + n32] = acc3[nt][r];
+    {
+        const int mt = wave >> 1, nt = wave & 1;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            out[kFW2 + (mt * 32 + mrow(lane, r)) * kFlowHidden + nt * 32 + n32] = acc2[r];
+    }
+    if (wave < 2 && n32 < kFlowDim && flow_in_a(l, n32)) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            out[kFW1 + (wave * 32 + mrow(lane, r)) * kFlowHalf + flow_pos(l, n32)] = acc1[r];
+    }
+    if (threadIdx.x < kFlowHalf * kFlowBins) out[kFB3 + threadIdx.x] = db3;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        db2[nt] += __shfl_xor(db2[nt], 32, 64);
+        db1[nt] += __shfl_xor(db1[nt], 32, 64);
+        if (half == 0) {
+            S.red[0][wave][nt * 32 + n32] = db2[nt];
+            S.red[1][wave][nt * 32 + n32] = db1[nt];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kFlowHidden) {
+        float s2 = 0.f, s1 = 0.f;
+        for (int w = 0; w < kFlowWaves; ++w) {
+            s2 += S.red[0][w][threadIdx.x];
+            s1 += S.red[1][w][threadIdx.x];
+        }
+        out[kFB2 + threadIdx.x] = s2;
+        out[kFB1 + threadIdx.x] = s1;
+    }
+}
+
+// per-workgroup gradients of layer l summed in workgroup order
+__global__ void k_flow_reduce(const float* part, int n_wg, int layer, float* grad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kFLayer) return;
+    float s = 0.f;
+    for (int w = 0; w < n_wg; ++w) s += part[(size_t)w * kFLayer + i];
+    grad[(size_t)layer * kFLayer + i] = s;
+}
+
+__global__ void k_flow_adam(float* theta, const float* grad, float* m, float* v, float lr, float c1, float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kFParams) return;
+    const float gi = grad[i];
+    const float mi = fmaf(0.9f, m[i], 0.1f * gi);
+    const float vi = fmaf(0.999f, v[i], 0.001f * gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    theta[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, float* G1, float* grad,
+                                hipStream_t st)
+{
+    hipLaunchKernelGGL(k_flow_sumsq, dim3(1), dim3(kSumThreads), 0, st, base.om, base.n, base.gamma,
+                       const_cast<double*>(base.sumsq));
+    hipLaunchKernelGGL(k_flow_inverse, dim3(n_wg), dim3(kFlowThreads), 0, st, base);
+    for (int l = 0; l < kFlowLayers; ++l) {
+        FlowTrainArgs a = base;
+        a.layer = l;
+        a.g_in = l == 0 ? nullptr : ((l & 1) ? G0 : G1);
+        a.g_out = (l & 1) ? G1 : G0;
+        hipLaunchKernelGGL(k_flow_grad, dim3(n_wg), dim3(kFlowThreads), 0, st, a);
+        hipLaunchKernelGGL(k_flow_reduce, dim3((kFLayer + 255) / 256), dim3(256), 0, st, (const float*)a.part, n_wg,
+                           l, grad);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_adam(float* theta, const float* grad, float* m, float* v, float lr, int step, hipStream_t st)
+{
+    const float c1 = 1.f / (1.f - powf(0.9f, (float)step));
+    const float c2 = 1.f / (1.f - powf(0.999f, (float)step));
+    hipLaunchKernelGGL(k_flow_adam, dim3((kFParams + 255) / 256), dim3(256), 0, st, theta, grad, m, v, lr, c1, c2);
+    return hipGetLastError();
+}
+
+}  // namespace vg

@@ -128,3 +128,77 @@ def test_fixed_warp_unbiased():
     say(f"  {r.integral:.6f} +- {math.sqrt(r.sigma2):.2e} (exact {exact:.6f})")
     assert abs(r.integral - exact) < 3.0 * math.sqrt(r.sigma2)
     v.close()
+
+
+def test_flow_grad_parity():
+    """GPU gradient of the warp's loss against the oracle with BF16
+    emulation, per layer (relative L2)."""
+    w = corr16()
+    say("[flow grad]")
+    v = make(w)
+    th = random_theta(3).astype(np.float32)
+    v.attach_flow(th)
+    v.enable_flow(True)
+    v.adapt(1)
+    W, LJ, OM = v.flow_samples()
+    g_gpu = v.flow_grad().astype(np.float64)
+    om = OM.astype(np.float64)
+    coef = om * om / np.sum(om * om)
+    _, g_orc = fl.loss_grad(th.astype(np.float64), W.astype(np.float64), coef, emu=True)
+    n = fl.n_params(16) // 4
+    for l in range(4):
+        a, b = g_gpu[l * n:(l + 1) * n], g_orc[l * n:(l + 1) * n]
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        say(f"  layer {l}: |g| {np.linalg.norm(b):.3e} rel L2 {rel:.2e}")
+        assert rel < 2e-2
+    v.close()
+
+
+def test_flow_training_gain():
+    """Trained warp against plain VEGAS+ on a correlated 16-d Gaussian
+    (s 0.2, rho 0.5): after 100 training steps the median iteration variance
+    at equal evaluations is below 0.6 of plain VEGAS+, the judge keeps the
+    warp, and the combined
+    warped and plain estimates agree."""
+    w = vi.Workload("corr16_train", 16, vi.GAUSS_CORR, np.array([0.5, 0.2, 0.5]), n_g=64, n_eval=200_003,
+                    n_iter=1, precision="f32")
+    say("[flow train]")
+    v = make(w)
+    v.adapt(6)
+    v.integrate(10)
+    plain = v.result()
+    v.attach_flow(fl.init_params(16, 0).astype(np.float32), lr=3e-4, train=True, judge=True)
+    v.enable_flow(True)
+    v.adapt(100)
+    I, s2 = v.get_iterations()
+    on, kept, rejected = v.flow_status()
+    plain_s2 = np.median(s2[6:16])
+    warped_s2 = np.median(s2[-10:])
+    say(f"  plain median sigma^2 {plain_s2:.3e}, warped (last 10) {warped_s2:.3e}, ratio "
+        f"{warped_s2 / plain_s2:.3f}; judge kept {kept} rejected {rejected}, on={on}")
+    assert on and kept >= 80
+    assert warped_s2 < 0.6 * plain_s2
+    Iw = np.sum(I[-10:] / s2[-10:]) / np.sum(1 / s2[-10:])
+    sw = 1.0 / np.sum(1 / s2[-10:])
+    assert abs(Iw - plain.integral) < 4.0 * math.sqrt(sw + plain.sigma2), (Iw, plain.integral)
+    v.close()
+
+
+def test_flow_judge_falls_back():
+    """A badly scaled fixed warp: the judge rejects it three times, switches
+    it off, and plain VEGAS+ carries on."""
+    w = vi.Workload("corr16_judge", 16, vi.GAUSS_CORR, np.array([0.5, 0.2, 0.5]), n_g=64, n_eval=100_003,
+                    n_iter=1, precision="f32")
+    say("[flow judge]")
+    v = make(w)
+    v.adapt(6)
+    v.attach_flow(random_theta(9, scale=30.0).astype(np.float32), judge=True)
+    v.enable_flow(True)
+    v.adapt(6)
+    on, kept, rejected = v.flow_status()
+    say(f"  kept {kept} rejected {rejected} on={on}")
+    assert not on and rejected >= 3
+    v.integrate(3)
+    r = v.result()
+    assert math.isfinite(r.integral) and r.sigma2 > 0
+    v.close()
