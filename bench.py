@@ -60,6 +60,7 @@ WORKLOADS = {
     "ridge_4d": "d=4 ridge of 1000 Gaussians s=0.01 on the diagonal, 1024 intervals, FP32 + FP64 accumulators",
     "gauss_prod_4d": "d=4 Gaussian product s=0.1, 128 intervals, FP64 throughout",
     "corr_gauss_16d": "d=16 correlated Gaussian rho=0.9 s=0.03, 1024 intervals, FP32 + FP64 accumulators",
+    "corr_gauss_16d_mild": "d=16 correlated Gaussian rho=0.3 s=0.2, 64 intervals, FP32 + FP64 accumulators",
     "genz_batch": "4096 Genz product-peak / Gaussian integrals, d in 3..12, budgets log-uniform in 1e4..1e7 "
                   "evals/iteration, 256 intervals, one batched launch per phase, FP32 sample path + FP64 "
                   "accumulators",
@@ -197,6 +198,91 @@ def run_batch(args):
     b.close()
 
 
+def run_warp_compare(args, w):
+    """Learned warp against plain VEGAS+ on a correlated Gaussian: the same
+    warm-up for both (for the sharp target a continuation from a wide,
+    uncorrelated Gaussian), then iterations combined until the relative
+    error estimate reaches 1e-4 or the caps.  Wall time counts from create."""
+    import numpy as np
+    import torch
+    import vegas_inputs as vi
+    from oracle import flow as fl
+    from paper_2408_09229_amd import Vegas, make_config
+    target = 1e-4
+    sharp = w.name == "corr_gauss_16d"
+    warm = vi.continuation(w, 20) if sharp else [w.params] * w.n_adapt
+    per = 2 if sharp else 1
+    cap_it, cap_s = args.cap_iters, args.cap_seconds
+    from tests import closed_forms as cf
+    exact = cf.exact(w)
+    torch.cuda.set_device(0)
+    out = {}
+    for method in ("plain", "warp"):
+        cfg = make_config(w.dim, w.n_g, w.n_eval, precision="f32", max_iter=len(warm) * per + cap_it + 16)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        v = Vegas(cfg, w.family, warm[0])
+        for p in warm:
+            v.set_params(p)
+            v.adapt(per)
+        n0 = len(warm) * per
+        if method == "warp":
+            v.attach_flow(fl.init_params(w.dim, 0).astype(np.float32), lr=args.flow_lr, train=True, judge=True)
+            v.enable_flow(True)
+        rel = math.inf
+        n = 0
+        t_int = 0.0
+        while n < cap_it and time.perf_counter() - t0 < cap_s:
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            v.integrate(10)
+            torch.cuda.synchronize()
+            t_int += time.perf_counter() - ta
+            n += 10
+            I, s2 = v.get_iterations()
+            Ii, si = I[n0:], s2[n0:]
+            wgt = 1.0 / si
+            Ic = float(np.sum(Ii * wgt) / np.sum(wgt))
+            rel = math.sqrt(1.0 / np.sum(wgt)) / abs(Ic) if Ic != 0 else math.inf
+            if rel <= target:
+                break
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        I, s2 = v.get_iterations()
+        Ic = float(np.sum(I[n0:] / s2[n0:]) / np.sum(1.0 / s2[n0:]))
+        rec = {"iterations": n, "wall_s": wall, "reached": rel <= target, "integral": Ic, "rel_err_estimate": rel,
+               "true_rel_err": abs(Ic - exact) / exact,
+               "evals_per_s": w.n_eval * n / t_int if t_int > 0 else None,
+               "median_var_per_eval_rel": float(np.median(s2[n0:] * w.n_eval)) / Ic ** 2 if Ic else None}
+        if method == "warp":
+            on, kept, rej = v.flow_status()
+            rec["judge"] = {"warp_on_at_end": on, "kept": kept, "rejected": rej}
+        out[method] = rec
+        print(f"[bench] {method}: {rec}", file=sys.stderr, flush=True)
+        v.close()
+    line = {
+        "metric": "integrand evals/sec and wall time to 1e-4 rel. error; learned warp vs plain VEGAS+",
+        "value": out["warp"]["evals_per_s"],
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": out["warp"]["iterations"],
+        "warmup": len(warm) * per,
+        "ms_per_step": 1e3 * w.n_eval / out["warp"]["evals_per_s"] if out["warp"]["evals_per_s"] else None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+bf16",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {WORKLOADS[w.name]}, {w.n_eval:.0e} evals/iteration; learned warp "
+                               f"4 coupling layers, 2x64 BF16 MLPs, 16 bins; lr {args.flow_lr}",
+                   "n_eval": w.n_eval, "dim": w.dim, "n_intervals": w.n_g, "target_rel_err": target,
+                   "caps": {"iterations": cap_it, "seconds": cap_s}, "parallelism": "single-gpu"},
+        "exact": exact,
+        "comparison": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,6 +298,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for scaling HBM counters)")
     ap.add_argument("--tune-cache", default="", help="autotuner cache of the batched workload")
+    ap.add_argument("--cap-iters", type=int, default=400, help="warp comparison: iteration cap per method")
+    ap.add_argument("--cap-seconds", type=float, default=30.0, help="warp comparison: time cap per method")
+    ap.add_argument("--flow-lr", type=float, default=3e-4, help="warp comparison: Adam step of the warp")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the VEGAS+ path here "
@@ -231,6 +320,12 @@ def main():
         return
 
     import vegas_inputs as vi
+    if args.workload == "genz_batch":
+        run_batch(args)
+        return
+    if args.workload in ("corr_gauss_16d", "corr_gauss_16d_mild"):
+        run_warp_compare(args, getattr(vi, args.workload)())
+        return
     from paper_2408_09229_amd import Vegas, make_config
 
     w = getattr(vi, args.workload)()

@@ -50,6 +50,23 @@ def genz_gauss(params, dim) -> float:
     return float(A * p)
 
 
+def gauss_corr(params, dim) -> float:
+    """Mass of N(mu 1, s^2 ((1-rho) I + rho 1 1^T)) in [0,1]^D.  With
+    x_i = mu + s (sqrt(1-rho) z_i + sqrt(rho) t), t and z_i standard normal,
+    the box probability is int phi(t) [Phi(b(t)) - Phi(a(t))]^D dt,
+    a(t) = (-mu/s - sqrt(rho) t)/sqrt(1-rho), b(t) = ((1-mu)/s - sqrt(rho) t)/sqrt(1-rho)."""
+    mu, s, rho = (mp.mpf(v) for v in params[:3])
+    r1, rr = mp.sqrt(1 - rho), mp.sqrt(rho)
+    Phi = lambda v: (1 + mp.erf(v / mp.sqrt(2))) / 2
+
+    def g(t):
+        a = (-mu / s - rr * t) / r1
+        b = ((1 - mu) / s - rr * t) / r1
+        return mp.npdf(t) * (Phi(b) - Phi(a)) ** dim
+
+    return float(mp.quad(g, [-mp.inf, -8, -4, 0, 4, 8, mp.inf]))
+
+
 def linear(params, dim) -> float:
     return float(params[0]) * dim / 2.0
 
@@ -76,6 +93,8 @@ def exact(w: vi.Workload) -> float:
         return genz_ppeak(w.params, w.dim)
     if f == vi.GENZ_GAUSS:
         return genz_gauss(w.params, w.dim)
+    if f == vi.GAUSS_CORR:
+        return gauss_corr(w.params, w.dim)
     if f == vi.LINEAR:
         return linear(w.params, w.dim)
     if f == vi.ROOS:

@@ -65,3 +65,21 @@ def test_gauss_diag_multi_d_is_product(orc):
         x = rng.random(4)
         want = np.prod(np.exp(-(x - 0.5) ** 2 / (2 * 0.01)))
         assert abs(orc.integrand(w.family, x, w.params) - want) <= 1e-14
+
+
+def test_gauss_corr_closed_form_against_direct_sampling():
+    """The box mass of the equicorrelated Gaussian (a 1-d quadrature) against
+    direct sampling of the normal distribution, and at rho = 0 against the
+    product of erfs."""
+    from tests import closed_forms as cf
+    rng = np.random.default_rng(0)
+    for s, rho in [(0.2, 0.5), (0.15, 0.3)]:
+        want = cf.gauss_corr(np.array([0.5, s, rho]), 16)
+        n = 2_000_000
+        z = rng.standard_normal((n, 17))
+        x = 0.5 + s * (np.sqrt(1 - rho) * z[:, :16] + np.sqrt(rho) * z[:, 16:17])
+        p = np.count_nonzero(np.all((x >= 0) & (x <= 1), axis=1)) / n
+        assert abs(p - want) < 5 * np.sqrt(p * (1 - p) / n), (s, rho, p, want)
+    s = 0.2
+    prod = cf.gauss_diag(np.array([1.0, s, 1.0, 0.5]), 6) / (2 * np.pi * s * s) ** 3
+    assert abs(cf.gauss_corr(np.array([0.5, s, 0.0]), 6) - prod) < 1e-12

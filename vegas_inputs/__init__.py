@@ -117,6 +117,26 @@ def corr_gauss_16d() -> Workload:
                     n_g=1024, n_eval=1_000_000, n_iter=20, n_adapt=5, precision="f32")
 
 
+def corr_gauss_16d_mild() -> Workload:
+    """The same density family with s=0.2, rho=0.3 (finite variance for a
+    separable importance density, which needs rho < 1/2), 64 intervals,
+    2e5 evals/iteration."""
+    return Workload("corr_gauss_16d_mild", 16, GAUSS_CORR, np.array([0.5, 0.2, 0.3]),
+                    n_g=64, n_eval=200_003, n_iter=20, n_adapt=6, precision="f32")
+
+
+def continuation(w: Workload, steps: int):
+    """Parameter schedule of the warm-up of a GAUSS_CORR workload: widths
+    geometric from 0.3 down to the target, correlation linear from 0 up to
+    the target, one entry per step (the last is the workload itself)."""
+    mu, s, rho = (float(v) for v in w.params)
+    out = []
+    for i in range(steps):
+        f = i / (steps - 1) if steps > 1 else 1.0
+        out.append(np.array([mu, 0.3 * (s / 0.3) ** f, rho * f]))
+    return out
+
+
 @dataclass
 class BatchInstance:
     family: int
