@@ -250,6 +250,8 @@ struct vegas_ctx {
     int f_nwg = 0;                     // workgroups of the training passes
     int f_step = 0;                    // Adam steps taken
     size_t f_acc = 0;                  // last accepted parameters
+    size_t f_seg = 0;                  // segment sums of the gradient reduction
+    int n_cus = 1;
     std::vector<uint8_t> warped;       // per iteration: 1 = sampled through the warp
     double ref_I = 0.0, ref_s2 = INFINITY;   // plain VEGAS+ reference of the judge
     int rejects = 0;                   // consecutive rejected warped iterations
@@ -610,6 +612,7 @@ vegas_status vegas_create(const vegas_config* cfg, const vegas_integrand* f, voi
     c->stream = (hipStream_t)hip_stream;
     c->ws = (unsigned char*)d_workspace;
     c->n_wg = std::max(1, std::min({cus, kMaxWG, g.n_tiles}));
+    c->n_cus = std::max(1, cus);
     c->cur = 0;
     c->max_iter = max_iter;
     c->n_run = 0;
@@ -929,7 +932,7 @@ vegas_status vegas_sample_probe(vegas_ctx* c, uint32_t t, uint64_t k0, int64_t n
 namespace {
 
 struct FlowPlan {
-    size_t theta, packed, w, lj, om, U, G0, G1, part, grad, m, v, sumsq, acc, total;
+    size_t theta, packed, w, lj, om, U, G0, G1, part, seg, grad, m, v, sumsq, acc, total;
 };
 
 FlowPlan flow_plan(uint32_t n_eval, int n_wg)
@@ -950,16 +953,22 @@ FlowPlan flow_plan(uint32_t n_eval, int n_wg)
     p.G0 = take(sizeof(float) * kFlowDim * (size_t)n_eval);
     p.G1 = take(sizeof(float) * kFlowDim * (size_t)n_eval);
     p.part = take(sizeof(float) * kFLayer * (size_t)n_wg);
+    p.seg = take(sizeof(float) * kFLayer * 16);
     p.grad = take(sizeof(float) * kFParams);
     p.m = take(sizeof(float) * kFParams);
     p.v = take(sizeof(float) * kFParams);
-    p.sumsq = take(sizeof(double) * 2);
+    p.sumsq = take(sizeof(double) * (1 + 256));
     p.acc = take(sizeof(float) * kFParams);
     p.total = o;
     return p;
 }
 
-int flow_train_wg(const vegas_ctx* c) { return 2 * std::max(c->n_wg, 1); }
+// one training workgroup per CU (150 KB of LDS each)
+int flow_train_wg(const vegas_ctx* c)
+{
+    const int chunks = (int)((c->g.n_eval + 127) / 128);
+    return std::max(1, std::min(c->n_cus, chunks));
+}
 
 FlowTrainArgs flow_train_args(vegas_ctx* c)
 {
@@ -984,7 +993,7 @@ vegas_status flow_gradient(vegas_ctx* c)
 {
     HIPCHK(launch_flow_gradient(flow_train_args(c), c->f_nwg, reinterpret_cast<float*>(c->fws + c->f_G0),
                                 reinterpret_cast<float*>(c->fws + c->f_G1), reinterpret_cast<float*>(c->fws + c->f_grad),
-                                c->stream));
+                                reinterpret_cast<float*>(c->fws + c->f_seg), c->stream));
     return VEGAS_OK;
 }
 
@@ -1094,6 +1103,7 @@ vegas_status vegas_flow_attach(vegas_ctx* c, const vegas_flow_config* cfg, const
     c->f_v = p.v;
     c->f_sumsq = p.sumsq;
     c->f_acc = p.acc;
+    c->f_seg = p.seg;
     c->f_nwg = nwg;
     c->f_step = 0;
     c->flow_attached = true;

@@ -6,7 +6,7 @@
 // 1 / J_F(F^-1(w))); gamma = 1: of the KL divergence from the normalised
 // |f| to the warp's density, whose sample gradient has lighter tails.  The gradient goes through
 // the inverse chain u_3 = w -> u_2 -> u_1 -> u_0:
-//   k_flow_sumsq    sum of omega^2 (one workgroup, fixed order)
+//   k_flow_sumsq    sum of |omega|^gamma (block partials, then in order)
 //   k_flow_inverse  u_2, u_1, u_0 of every sample (MLP on MFMA)
 //   k_flow_grad     one coupling layer l = 0..3 in turn: from the upstream
 //                   g = dL/du_{l-1}, the layer's log-Jacobian and inverse
@@ -15,7 +15,7 @@
 //                   sum_samples delta^T activation are MFMA products over the
 //                   workgroup's 128 samples, each wave owning some output
 //                   tiles, accumulated across the workgroup's chunks
-//   k_flow_reduce   per-workgroup gradients summed in workgroup order
+//   k_flow_reduce   per-workgroup gradients summed in a fixed order
 //   k_flow_adam     Adam on the FP32 parameters (then the BF16 repack)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -26,14 +26,16 @@
 
 namespace vg {
 
-constexpr int kSumThreads = 1024;
+constexpr int kSumThreads = 256;
+constexpr int kSumBlocks = 256;
 
-// sum of |omega|^gamma, gamma = 2 (variance loss) or 1 (KL loss)
-__global__ __launch_bounds__(kSumThreads) void k_flow_sumsq(const float* om, uint32_t n, int gamma, double* out)
+// sum of |omega|^gamma, gamma = 2 (variance loss) or 1 (KL loss): block
+// partials (strided samples), then the partials in block order
+__global__ __launch_bounds__(kSumThreads) void k_flow_sumsq(const float* om, uint32_t n, int gamma, double* part)
 {
     __shared__ double red[kSumThreads];
     double s = 0.0;
-    for (uint32_t i = threadIdx.x; i < n; i += kSumThreads) {
+    for (uint32_t i = blockIdx.x * kSumThreads + threadIdx.x; i < n; i += kSumThreads * kSumBlocks) {
         const double v = fabs((double)om[i]);
         s += gamma == 2 ? v * v : v;
     }
@@ -43,7 +45,19 @@ __global__ __launch_bounds__(kSumThreads) void k_flow_sumsq(const float* om, uin
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = red[0];
+    if (threadIdx.x == 0) part[1 + blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kSumThreads) void k_flow_sumsq_final(double* part)
+{
+    __shared__ double red[kSumThreads];
+    red[threadIdx.x] = threadIdx.x < kSumBlocks ? part[1 + threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int w = kSumThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[0] = red[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -369,13 +383,29 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_grad(FlowTrainArgs a)
     }
 }
 
-// per-workgroup gradients of layer l summed in workgroup order
-__global__ void k_flow_reduce(const float* part, int n_wg, int layer, float* grad)
+// per-workgroup gradients of layer l summed in a fixed order: segments of
+// consecutive workgroups first (one thread per parameter and segment), then
+// the segments in order
+constexpr int kRedSegs = 16;
+
+__global__ void k_flow_reduce_seg(const float* part, int n_wg, float* seg)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kFLayer) return;
+    const int per = (n_wg + kRedSegs - 1) / kRedSegs;
+    const int w0 = blockIdx.y * per;
+    const int w1 = min(w0 + per, n_wg);
+    float s = 0.f;
+    for (int w = w0; w < w1; ++w) s += part[(size_t)w * kFLayer + i];
+    seg[(size_t)blockIdx.y * kFLayer + i] = s;
+}
+
+__global__ void k_flow_reduce(const float* seg, int layer, float* grad)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kFLayer) return;
     float s = 0.f;
-    for (int w = 0; w < n_wg; ++w) s += part[(size_t)w * kFLayer + i];
+    for (int g = 0; g < kRedSegs; ++g) s += seg[(size_t)g * kFLayer + i];
     grad[(size_t)layer * kFLayer + i] = s;
 }
 
@@ -395,19 +425,22 @@ __global__ void k_flow_adam(float* theta, const float* grad, float* m, float* v,
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, float* G1, float* grad,
-                                hipStream_t st)
+                                float* seg, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_flow_sumsq, dim3(1), dim3(kSumThreads), 0, st, base.om, base.n, base.gamma,
-                       const_cast<double*>(base.sumsq));
-    hipLaunchKernelGGL(k_flow_inverse, dim3(n_wg), dim3(kFlowThreads), 0, st, base);
+    double* ss = const_cast<double*>(base.sumsq);
+    hipLaunchKernelGGL(k_flow_sumsq, dim3(kSumBlocks), dim3(kSumThreads), 0, st, base.om, base.n, base.gamma, ss);
+    hipLaunchKernelGGL(k_flow_sumsq_final, dim3(1), dim3(kSumThreads), 0, st, ss);
+    // the inverse pass holds 80 KB of LDS: two workgroups per CU
+    hipLaunchKernelGGL(k_flow_inverse, dim3(2 * n_wg), dim3(kFlowThreads), 0, st, base);
     for (int l = 0; l < kFlowLayers; ++l) {
         FlowTrainArgs a = base;
         a.layer = l;
         a.g_in = l == 0 ? nullptr : ((l & 1) ? G0 : G1);
         a.g_out = (l & 1) ? G1 : G0;
         hipLaunchKernelGGL(k_flow_grad, dim3(n_wg), dim3(kFlowThreads), 0, st, a);
-        hipLaunchKernelGGL(k_flow_reduce, dim3((kFLayer + 255) / 256), dim3(256), 0, st, (const float*)a.part, n_wg,
-                           l, grad);
+        hipLaunchKernelGGL(k_flow_reduce_seg, dim3((kFLayer + 255) / 256, kRedSegs), dim3(256), 0, st,
+                           (const float*)a.part, n_wg, seg);
+        hipLaunchKernelGGL(k_flow_reduce, dim3((kFLayer + 255) / 256), dim3(256), 0, st, (const float*)seg, l, grad);
     }
     return hipGetLastError();
 }

@@ -56,11 +56,12 @@ __device__ __forceinline__ void prep_problem(const PrepArgs& a, int tid, int nth
 // ---------------------------------------------------------------------------
 // allocation
 // ---------------------------------------------------------------------------
-// floor(R C / T) exactly, R < 2^32, C <= T < 2^63: a double estimate is
-// within one of the answer; 128-bit products settle it.
-__device__ __forceinline__ uint64_t floor_mul_div(uint64_t R, uint64_t C, uint64_t T)
+// floor(R C / T) exactly, R < 2^32, C <= T < 2^63.  rT = R/T rounded to
+// double: the estimate C rT is within a few 2^-53 relative of R C/T < 2^32,
+// so within one of the answer; 128-bit products settle it.
+__device__ __forceinline__ uint64_t floor_mul_div(uint64_t R, uint64_t C, uint64_t T, double rT)
 {
-    const double est = ((double)R * (double)C) / (double)T;
+    const double est = (double)C * rT;
     uint64_t m = (uint64_t)est;
     const unsigned __int128 rc = (unsigned __int128)R * C;
     unsigned __int128 mt = (unsigned __int128)m * T;
@@ -185,12 +186,13 @@ __device__ __forceinline__ void alloc_write_block(const AllocArgs& a, const unsi
     uint64_t total;
     uint64_t Cprev = boff + block_exscan(s, sh, total);
     const uint64_t R = a.R;
-    uint64_t lo = floor_mul_div(R, Cprev, T);
+    const double rT = (double)R / (double)T;
+    uint64_t lo = floor_mul_div(R, Cprev, T, rT);
     for (int i = 0; i < kAllocPerThread; ++i) {
         const uint32_t h = base + threadIdx.x * kAllocPerThread + i;
         if (h >= a.n_cubes) break;
         const uint64_t C = Cprev + Q[i];
-        const uint64_t hi = floor_mul_div(R, C, T);
+        const uint64_t hi = floor_mul_div(R, C, T, rT);
         const uint32_t start = h * a.n_min + (uint32_t)lo;
         const uint32_t nh = a.n_min + (uint32_t)(hi - lo);
         a.start[h] = start;
