@@ -62,8 +62,8 @@ WORKLOADS = {
     "corr_gauss_16d": "d=16 correlated Gaussian rho=0.9 s=0.03, 1024 intervals, FP32 + FP64 accumulators",
     "corr_gauss_16d_mild": "d=16 correlated Gaussian rho=0.3 s=0.2, 64 intervals, FP32 + FP64 accumulators",
     "genz_batch": "4096 Genz product-peak / Gaussian integrals, d in 3..12, budgets log-uniform in 1e4..1e7 "
-                  "evals/iteration, 256 intervals, one batched launch per phase, FP32 sample path + FP64 "
-                  "accumulators",
+                  "evals/iteration, 256 intervals, streams schedule (one context per problem over autotuned "
+                  "streams), FP32 sample path + FP64 accumulators",
 }
 
 
@@ -144,8 +144,8 @@ def run_batch(args):
     inf = b.info()
     n_eval = inf.n_eval_total
     print(f"[bench] genz_batch: n={len(insts)} evals/iteration={n_eval:.4e} cubes={inf.n_cubes_total:.3e} "
-          f"layout per_lane={inf.per_lane} item={inf.item_samples} items={inf.n_items} tuned={inf.tuned} "
-          f"({inf.tune_ms:.2f} ms) ws={inf.workspace_bytes / 2**30:.2f} GiB", file=sys.stderr, flush=True)
+          f"streams={inf.n_streams} tuned={inf.tuned} ({inf.tune_ms:.2f} ms fill pass) "
+          f"ws={inf.workspace_bytes / 2**30:.2f} GiB", file=sys.stderr, flush=True)
     b.adapt(args.warmup)
     torch.cuda.synchronize()
     b.set_timing(True)
@@ -159,16 +159,18 @@ def run_batch(args):
     ms = e0.elapsed_time(e1)
     phases, n_timed = b.get_timing()
     res = b.results()
-    fill_ms = phases[0] / max(n_timed, 1)
+    # streams schedule: the timed span is the whole iteration of every
+    # problem (fills and updates on all streams), so the fill's rate below is
+    # a lower bound
+    iter_ms = phases[0] / max(n_timed, 1)
     ops = sum(valu_ops_per_eval(x.dim, x.family) * x.n_eval for x in insts)
-    ach = ops / (fill_ms / 1e3)
+    ach = ops / (iter_ms / 1e3)
     ex = np.array([cf.genz_ppeak(x.params, x.dim) if x.family == vi.GENZ_PPEAK else cf.genz_gauss(x.params, x.dim)
                    for x in insts])
     z = (res["integral"] - ex) / np.sqrt(res["sigma2"])
     rel = np.abs(res["integral"] / ex - 1.0)
-    print(f"[bench] phases ms/it: fill {fill_ms:.3f} fixup+est {phases[1] / n_timed:.3f} alloc "
-          f"{phases[2] / n_timed:.3f} map {phases[3] / n_timed:.3f}; max|z| {np.abs(z).max():.2f}",
-          file=sys.stderr, flush=True)
+    print(f"[bench] iteration of all problems {iter_ms:.3f} ms; max|z| {np.abs(z).max():.2f}, "
+          f"|z|>3 {np.mean(np.abs(z) > 3):.4f}", file=sys.stderr, flush=True)
     out = {
         "metric": "integrand evals/sec (VEGAS+ iteration)",
         "value": n_eval * args.steps / (ms / 1e3),
@@ -184,11 +186,12 @@ def run_batch(args):
         "data": "synthetic",
         "config": {"workload": f"genz_batch: {WORKLOADS['genz_batch']}, {n_eval:.3e} evals/iteration",
                    "n_problems": len(insts), "n_eval": n_eval, "n_intervals": vi.BATCH_N_G,
-                   "layout": {"per_lane": inf.per_lane, "item_samples": inf.item_samples, "tuned": inf.tuned},
+                   "schedule": {"kind": "streams", "n_streams": inf.n_streams, "tuned": inf.tuned},
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
                      "unit": "T VALU issue-slots/s", "frac": ach / VALU_LANE_OPS_PEAK,
-                     "traffic": profiled_traffic("genz_batch"), "kernel": "k_batch_fill", "kernel_ms": fill_ms},
+                     "traffic": profiled_traffic("genz_batch"),
+                     "kernel": "k_fill of every problem, timed as the whole iteration", "kernel_ms": iter_ms},
         "result": {"iterations_combined": int(res["n_iter_combined"][0]), "max_abs_z": float(np.abs(z).max()),
                    "frac_abs_z_gt3": float(np.mean(np.abs(z) > 3)), "median_rel_err": float(np.median(rel))},
     }

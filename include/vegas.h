@@ -37,7 +37,8 @@ typedef enum {
     VEGAS_ENOMEM = -2,        /* workspace too small / sizes overflow */
     VEGAS_EDEVICE = -3,       /* a HIP call failed (message has the HIP error) */
     VEGAS_ESTATE = -4,        /* call not valid in the context's state */
-    VEGAS_ENONFINITE = -5,    /* the integrand returned NaN/Inf (counted; those samples weigh 0) */
+    VEGAS_ENONFINITE = -5,    /* the integrand returned NaN/Inf (counted; those samples weigh 0),
+                                 or an iteration's estimate or variance is not finite */
     VEGAS_EUNSUPPORTED = -6   /* valid request this build does not implement */
 } vegas_status;
 
@@ -47,7 +48,9 @@ enum { VEGAS_PREC_FP64 = 0, VEGAS_PREC_FP32 = 1 };
 /* Accumulation of per-cube sums and iteration totals.
  *  FP64    : shifted FP64 sums per cube, FP64 totals (default).
  *  KAHAN   : FP32 sample path with per-cube sums and totals in compensated
- *            FP32 (Kahan) form.
+ *            FP32 (Kahan) form.  Squares of weights must fit FP32 (|w| below
+ *            about 1e19); past that an iteration's variance overflows and
+ *            vegas_result reports VEGAS_ENONFINITE.
  *  ORDERED : every sum taken in increasing sample order, as a sequential
  *            program would; bit-reproducible, for small problems only
  *            (n_eval * n_intervals <= 2^26). */
@@ -275,60 +278,82 @@ vegas_status vegas_mfma_probe(const float* d_A, const float* d_B, float* d_D);
 
 /* ---- batches: many independent problems advanced together ------------- */
 /* A batch holds n problems, each with its own configuration (dimension,
- * intervals, budget, alpha, beta, seed, instance) and integrand.  All n
- * run one iteration at a time together: one persistent fill launch whose
- * workgroups pop work items (runs of consecutive sample tiles of one
- * problem) from a queue ordered longest first, then one launch per update
- * phase for all problems.  Every problem computes what a single context
- * with the same config computes (Alg. 1-2, Eq. 5-9); only the order of
- * floating-point sums differs.
- * Status: vegas_batch_create currently returns VEGAS_EUNSUPPORTED (the
- * batched iteration is switched off after a device fault whose cause is
- * not yet found); vegas_batch_workspace_size validates and sizes.
+ * intervals, budget, alpha, beta, seed, instance) and integrand, advanced
+ * one iteration at a time together.  Every problem computes exactly what a
+ * single context with the same config computes (Alg. 1-2, Eq. 5-9).
+ * Two launch schedules:
+ *  - VEGAS_BATCH_STREAMS: each problem runs the single-problem kernels in a
+ *    context of its own; the problems are spread over a few streams of the
+ *    library (longest first onto the least loaded stream), which start after
+ *    the caller's stream and which the caller's stream waits for at the end
+ *    of every iteration.  The stream count (1, 2, 4 or 8) comes from the
+ *    autotuner, which times the fill of every problem under each count.
+ *    Results do not depend on the stream count.
+ *  - VEGAS_BATCH_PERSISTENT: one persistent fill launch whose workgroups pop
+ *    work items (runs of consecutive sample tiles of one problem) from a
+ *    queue ordered longest first, then one launch per update phase for all
+ *    problems.  Switched off: its first device run ended in a memory fault
+ *    whose cause is not yet found, so vegas_batch_create returns
+ *    VEGAS_EUNSUPPORTED for it (vegas_batch_workspace_size still sizes it).
  * Restrictions: families GENZ_PPEAK, GENZ_GAUSS and GAUSS_DIAG; dim <= 12;
- * every config has the same precision, and accum FP64 or KAHAN;
- * n in 1..2^20.  The iteration log holds max(max_iter) iterations (256 if
- * every max_iter is 0). */
+ * every config has the same precision and accumulation, FP64 or KAHAN (or
+ * ORDERED under the streams schedule, which then follows the single
+ * contexts bit for bit); n in 1..2^20.  The iteration log holds
+ * max(max_iter) iterations (256 if every max_iter is 0).  With FP64 or
+ * KAHAN accumulation the histogram bins are LDS atomic sums whose last bits
+ * follow the order of the adds, as in a single context. */
 typedef struct vegas_batch vegas_batch;
+
+typedef enum { VEGAS_BATCH_STREAMS = 0, VEGAS_BATCH_PERSISTENT = 1 } vegas_batch_schedule;
 
 typedef struct {
     int32_t n;                /* problems */
-    int32_t per_lane;         /* layout: samples per lane (small problems use fewer) */
-    int64_t item_samples;     /* layout: target samples per work item */
-    int64_t n_items;          /* work items per fill */
-    int64_t n_tiles;
-    int32_t n_workgroups;     /* persistent fill workgroups */
-    int32_t tuned;            /* 0 default layout, 1 timed at create, 2 read from the cache */
-    double  tune_ms;          /* fill time of the chosen layout when tuned */
-    size_t  lds_bytes;        /* LDS of the fill */
-    size_t  workspace_bytes;  /* bytes of the workspace the layout uses */
+    int32_t per_lane;         /* persistent layout: samples per lane (0 for streams) */
+    int64_t item_samples;     /* persistent layout: target samples per work item (0 for streams) */
+    int64_t n_items;          /* persistent: work items per fill; streams: n */
+    int64_t n_tiles;          /* sample tiles of all problems */
+    int32_t n_workgroups;     /* persistent fill workgroups; streams: sum over problems */
+    int32_t tuned;            /* 0 default, 1 timed at create, 2 read from the cache */
+    double  tune_ms;          /* fill time of the chosen schedule when tuned */
+    size_t  lds_bytes;        /* largest LDS of a fill launch */
+    size_t  workspace_bytes;  /* bytes of the workspace in use */
     int64_t n_eval_total;     /* sum of n_eval over the problems (one iteration) */
     int64_t n_cubes_total;
+    int32_t schedule;         /* vegas_batch_schedule */
+    int32_t n_streams;        /* streams schedule: streams in use */
 } vegas_batch_info;
 
-/* Bytes of device workspace for n problems (cfgs[n], fs[n], host arrays):
- * enough for every layout the autotuner may pick.  No HIP call. */
+/* Bytes of device workspace for n problems (cfgs[n], fs[n], host arrays)
+ * under a schedule (for the persistent one: enough for every layout the
+ * autotuner may pick).  No HIP call. */
 vegas_status vegas_batch_workspace_size(int32_t n, const vegas_config* cfgs,
-                                        const vegas_integrand* fs, size_t* bytes);
+                                        const vegas_integrand* fs, int32_t schedule, size_t* bytes);
 
 /* Validate and set up n problems in the caller's workspace (device,
- * 256-byte aligned, >= the size above) on hip_stream.  tune_cache: path of
- * a text file of tuned layouts, or NULL for the default layout.  When the
- * file has no entry for this batch shape on this device, the fill is timed
- * over the candidate layouts, the fastest is used, and a line is appended
- * to the file (a file that cannot be written is ignored).  Synchronous.
- * *out is released by vegas_batch_destroy. */
+ * 256-byte aligned, >= the size above for the same schedule) after the work
+ * already queued on hip_stream.  tune_cache: path of a text file of tuned
+ * schedules, or NULL for the default (4 streams; the first persistent
+ * layout).  When the file has no entry for this batch shape on this device,
+ * the fill is timed over the candidates, the fastest is used, and a line is
+ * appended to the file (a file that cannot be written is ignored).
+ * Synchronous.  *out is released by vegas_batch_destroy. */
 vegas_status vegas_batch_create(int32_t n, const vegas_config* cfgs, const vegas_integrand* fs,
-                                void* d_workspace, size_t bytes, void* hip_stream,
+                                void* d_workspace, size_t bytes, void* hip_stream, int32_t schedule,
                                 const char* tune_cache, vegas_batch** out);
-/* Synchronous: release the handle. */
+/* Synchronous: release the handle (and the streams the batch made). */
 void vegas_batch_destroy(vegas_batch* b);
-/* Choose one of the candidate layouts by hand (per_lane 8/4/2 with
- * item_samples 2^16, 2^18 or 2^20, as listed by the tuner); only before the
- * first iteration.  Synchronous; VEGAS_EINVAL for other values. */
+/* Persistent schedule: choose one of the candidate layouts by hand
+ * (per_lane 8/4/2 with item_samples 2^16, 2^18 or 2^20, as listed by the
+ * tuner); only before the first iteration.  Synchronous; VEGAS_EINVAL for
+ * other values, VEGAS_EUNSUPPORTED under the streams schedule. */
 vegas_status vegas_batch_set_layout(vegas_batch* b, int32_t per_lane, int64_t item_samples);
+/* Streams schedule: choose the stream count (1..8) by hand; only before the
+ * first iteration.  Synchronous; VEGAS_EUNSUPPORTED under the persistent
+ * schedule. */
+vegas_status vegas_batch_set_streams(vegas_batch* b, int32_t n_streams);
 /* Iterations for every problem: discarded (adapt) or combined by Eq. 8-9
- * (integrate).  Asynchronous. */
+ * (integrate).  Asynchronous with respect to the host; ordered on the
+ * caller's stream. */
 vegas_status vegas_batch_adapt(vegas_batch* b, int32_t n_iter);
 vegas_status vegas_batch_integrate(vegas_batch* b, int32_t n_iter);
 /* Synchronous: out[n] (host) receives each problem's combined estimate.
@@ -341,9 +366,10 @@ vegas_status vegas_batch_get_iterations(vegas_batch* b, int32_t i, double* I, do
 vegas_status vegas_batch_get_map(vegas_batch* b, int32_t i, double* grid);
 vegas_status vegas_batch_get_nh(vegas_batch* b, int32_t i, uint32_t* nh);
 vegas_status vegas_batch_get_info(const vegas_batch* b, vegas_batch_info* out);
-/* Phase timing as for vegas_set_timing / vegas_get_timing, summed over all
- * problems: ms[0] fill, ms[1] fix-up + estimates, ms[2] allocation,
- * ms[3] map refinement. */
+/* Timing of the iterations that follow.  Persistent schedule: per phase,
+ * summed over all problems (ms[0] fill, ms[1] fix-up + estimates, ms[2]
+ * allocation, ms[3] map refinement).  Streams schedule: ms[0] is the whole
+ * iteration of all problems on the caller's stream, ms[1..3] are 0. */
 vegas_status vegas_batch_set_timing(vegas_batch* b, int32_t on);
 vegas_status vegas_batch_get_timing(vegas_batch* b, double* ms, int32_t* n_iter);
 

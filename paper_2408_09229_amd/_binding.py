@@ -29,6 +29,8 @@ VEGAS_OK, VEGAS_EINVAL, VEGAS_ENOMEM, VEGAS_EDEVICE, VEGAS_ESTATE, VEGAS_ENONFIN
     0, -1, -2, -3, -4, -5, -6
 PREC_FP64, PREC_FP32 = 0, 1
 ACC_FP64, ACC_KAHAN, ACC_ORDERED = 0, 1, 2
+BATCH_STREAMS, BATCH_PERSISTENT = 0, 1
+_SCHEDULES = {"streams": BATCH_STREAMS, "persistent": BATCH_PERSISTENT}
 
 
 class vegas_config(C.Structure):
@@ -65,7 +67,8 @@ class vegas_batch_info(C.Structure):
     _fields_ = [("n", C.c_int32), ("per_lane", C.c_int32), ("item_samples", C.c_int64),
                 ("n_items", C.c_int64), ("n_tiles", C.c_int64), ("n_workgroups", C.c_int32),
                 ("tuned", C.c_int32), ("tune_ms", C.c_double), ("lds_bytes", C.c_size_t),
-                ("workspace_bytes", C.c_size_t), ("n_eval_total", C.c_int64), ("n_cubes_total", C.c_int64)]
+                ("workspace_bytes", C.c_size_t), ("n_eval_total", C.c_int64), ("n_cubes_total", C.c_int64),
+                ("schedule", C.c_int32), ("n_streams", C.c_int32)]
 
 
 _vp = C.c_void_p
@@ -103,10 +106,12 @@ _DECL = {
     "vegas_flow_get_samples": (_st, [_vp, _vp, _vp, _vp]),
     "vegas_flow_grad": (_st, [_vp, _vp]),
     "vegas_mfma_probe": (_st, [_vp, _vp, _vp]),
-    "vegas_batch_workspace_size": (_st, [C.c_int32, _vp, _vp, C.POINTER(C.c_size_t)]),
-    "vegas_batch_create": (_st, [C.c_int32, _vp, _vp, _vp, C.c_size_t, _vp, C.c_char_p, C.POINTER(_vp)]),
+    "vegas_batch_workspace_size": (_st, [C.c_int32, _vp, _vp, C.c_int32, C.POINTER(C.c_size_t)]),
+    "vegas_batch_create": (_st, [C.c_int32, _vp, _vp, _vp, C.c_size_t, _vp, C.c_int32, C.c_char_p,
+                                 C.POINTER(_vp)]),
     "vegas_batch_destroy": (None, [_vp]),
     "vegas_batch_set_layout": (_st, [_vp, C.c_int32, C.c_int64]),
+    "vegas_batch_set_streams": (_st, [_vp, C.c_int32]),
     "vegas_batch_adapt": (_st, [_vp, C.c_int32]),
     "vegas_batch_integrate": (_st, [_vp, C.c_int32]),
     "vegas_batch_results": (_st, [_vp, _vp]),
@@ -379,10 +384,11 @@ class _BatchSpec:
         self.n = n
 
 
-def batch_workspace_size(cfgs, integrands) -> int:
+def batch_workspace_size(cfgs, integrands, schedule: str = "streams") -> int:
     sp = _BatchSpec(cfgs, integrands)
     n = C.c_size_t()
-    check(vegas_batch_workspace_size(sp.n, sp.cfgs, sp.fs, C.byref(n)), "vegas_batch_workspace_size")
+    check(vegas_batch_workspace_size(sp.n, sp.cfgs, sp.fs, _SCHEDULES[schedule], C.byref(n)),
+          "vegas_batch_workspace_size")
     return n.value
 
 
@@ -390,24 +396,27 @@ class VegasBatch:
     """n independent VEGAS+ problems advanced together on the current device.
 
     ``cfgs`` is a list of vegas_config, ``integrands`` a list of
-    (family, params[, lo, hi]) tuples.  ``tune_cache``: path of the
-    autotuner's text cache, or None for the default layout.
+    (family, params[, lo, hi]) tuples.  ``schedule``: "streams" (one
+    context per problem over a few streams) or "persistent" (switched off in
+    the library).  ``tune_cache``: path of the autotuner's text cache, or
+    None for the default schedule.
     """
 
-    def __init__(self, cfgs, integrands, *, tune_cache=None, stream=None, device=None):
+    def __init__(self, cfgs, integrands, *, schedule="streams", tune_cache=None, stream=None, device=None):
         import torch
         self._spec = _BatchSpec(cfgs, integrands)
         self.n = self._spec.n
         self.cfgs = list(cfgs)
+        self.schedule = _SCHEDULES[schedule]
         nb = C.c_size_t()
-        check(vegas_batch_workspace_size(self.n, self._spec.cfgs, self._spec.fs, C.byref(nb)),
+        check(vegas_batch_workspace_size(self.n, self._spec.cfgs, self._spec.fs, self.schedule, C.byref(nb)),
               "vegas_batch_workspace_size")
         self.device = torch.device(device or "cuda")
         self.ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = C.c_void_p()
         check(vegas_batch_create(self.n, self._spec.cfgs, self._spec.fs, C.c_void_p(self.ws.data_ptr()), nb.value,
-                                 C.c_void_p(self.stream.cuda_stream),
+                                 C.c_void_p(self.stream.cuda_stream), self.schedule,
                                  None if tune_cache is None else os.fsencode(tune_cache), C.byref(h)),
               "vegas_batch_create")
         self.h = h
@@ -427,6 +436,9 @@ class VegasBatch:
 
     def set_layout(self, per_lane: int, item_samples: int):
         check(vegas_batch_set_layout(self.h, per_lane, item_samples), "vegas_batch_set_layout")
+
+    def set_streams(self, n_streams: int):
+        check(vegas_batch_set_streams(self.h, n_streams), "vegas_batch_set_streams")
 
     def adapt(self, n: int):
         check(vegas_batch_adapt(self.h, n), "vegas_batch_adapt")

@@ -37,7 +37,7 @@ vegas_status fail(vegas_status s, const char* fmt, ...)
     return s;
 }
 
-constexpr int kMaxWG = 512;            // histogram slots reserved in the workspace
+constexpr int kMaxWG = 256;            // fill workgroups at most (one per CU of the 256); histogram slots
 
 // largest m with m^D <= lim, without overflow
 bool pow_at_most(uint64_t m, int D, uint64_t lim, uint64_t* out)
@@ -200,7 +200,9 @@ Plan plan(const Geometry& g, int max_iter, bool ordered)
     p.wg_part = take(sizeof(double) * 2 * kMaxWG);
     p.side = take(sizeof(TileSide) * g.n_tiles);
     p.fix_part = take(sizeof(double) * 2 * g.n_tiles);
-    const size_t slots = g.lds_hist_ok ? kMaxWG : 1;
+    // one slot per fill workgroup; a problem never runs more workgroups
+    // than tiles
+    const size_t slots = g.lds_hist_ok ? (size_t)std::min(kMaxWG, g.n_tiles) : 1;
     p.histH = take(sizeof(double) * nb * slots);
     p.histC = take(sizeof(uint32_t) * nb * slots);
     p.partH = take(sizeof(double) * nb * kHistParts);
@@ -369,6 +371,32 @@ vegas_status run_update(vegas_ctx* c, int t, int n_slots, bool timed)
 vegas_status flow_train_step(vegas_ctx* c);
 bool flow_judge(vegas_ctx* c, int t);
 
+// the fill's launch record for iteration t over the current map and
+// allocation; non-finite weights are counted into *nonfinite
+FillArgs fill_args(vegas_ctx* c, int t, unsigned long long* nonfinite)
+{
+    const bool fp64 = c->cfg.precision == VEGAS_PREC_FP64;
+    FillArgs a;
+    a.sc = sample_const(c);
+    a.t = (uint32_t)t;
+    a.tile = c->g.tile;
+    a.per_lane = c->g.per_lane;
+    a.n_tiles = c->g.n_tiles;
+    a.lds_hist = c->g.lds_hist_ok ? 1 : 0;
+    a.accum = c->cfg.accum;
+    a.grid = fp64 ? (const void*)c->at<double>(c->p.grid64) : (const void*)c->at<float>(c->p.grid32);
+    a.start = c->at<uint32_t>(c->p.start[c->cur]);
+    a.tile_first = c->at<uint32_t>(c->p.tfirst[c->cur]);
+    a.v_out = c->at<double>(c->p.v);
+    a.wg_part = c->at<double>(c->p.wg_part);
+    a.side = c->at<TileSide>(c->p.side);
+    a.hist_H = c->at<double>(c->p.histH);
+    a.hist_C = c->at<uint32_t>(c->p.histC);
+    a.vmax = c->vmax(t);
+    a.nonfinite = nonfinite;
+    return a;
+}
+
 vegas_status run_iteration(vegas_ctx* c, bool integrate)
 {
     if (c->n_run >= c->max_iter) return fail(VEGAS_ESTATE, "iteration log full (max_iter = %d)", c->max_iter);
@@ -410,24 +438,7 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
         HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histH), nb, c->stream));
         HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histC), (nb + 1) / 2, c->stream));
     }
-    FillArgs a;
-    a.sc = sample_const(c);
-    a.t = (uint32_t)t;
-    a.tile = c->g.tile;
-    a.per_lane = c->g.per_lane;
-    a.n_tiles = c->g.n_tiles;
-    a.lds_hist = lds_hist;
-    a.accum = c->cfg.accum;
-    a.grid = fp64 ? (const void*)c->at<double>(c->p.grid64) : (const void*)c->at<float>(c->p.grid32);
-    a.start = c->at<uint32_t>(c->p.start[c->cur]);
-    a.tile_first = c->at<uint32_t>(c->p.tfirst[c->cur]);
-    a.v_out = c->at<double>(c->p.v);
-    a.wg_part = c->at<double>(c->p.wg_part);
-    a.side = c->at<TileSide>(c->p.side);
-    a.hist_H = c->at<double>(c->p.histH);
-    a.hist_C = c->at<uint32_t>(c->p.histC);
-    a.vmax = c->vmax(t);
-    a.nonfinite = c->nonfinite();
+    const FillArgs a = fill_args(c, t, c->nonfinite());
     const size_t lds = fill_lds_bytes(c->g.D, c->g.ng, fp64, lds_hist, c->g.tile, c->g.n_aux);
     HIPCHK(c->mark());
     if (c->flow_on) {
@@ -549,6 +560,29 @@ void combine(const std::vector<double>& I, const std::vector<double>& s2, double
     *Ib = m;
     *s2b = 1.0 / w;
     *chi = n > 1 ? c2 / (double)(n - 1) : 0.0;
+}
+
+void ctx_set_stream(vegas_ctx* c, hipStream_t s) { c->stream = s; }
+
+vegas_status ctx_fill_pass(vegas_ctx* c)
+{
+    if (c->flow_on || c->cfg.accum == VEGAS_ACC_ORDERED)
+        return fail(VEGAS_EUNSUPPORTED, "a bare fill pass is for the plain FP64 / Kahan iteration");
+    const int t = c->n_run;
+    const bool fp64 = c->cfg.precision == VEGAS_PREC_FP64;
+    const int lds_hist = c->g.lds_hist_ok ? 1 : 0;
+    const int nb = c->g.D * c->g.ng;
+    HIPCHK(launch_reset(c->vmax(t), 1, c->stream));
+    if (!lds_hist) {
+        HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histH), nb, c->stream));
+        HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histC), (nb + 1) / 2, c->stream));
+    }
+    // non-finite weights of this pass go to a spare counter, so the
+    // iteration's own count is not touched
+    const FillArgs a = fill_args(c, t, c->nonfinite() + 1);
+    const size_t lds = fill_lds_bytes(c->g.D, c->g.ng, fp64, lds_hist, c->g.tile, c->g.n_aux);
+    HIPCHK(launch_fill(a, fp64, c->n_wg, lds, c->stream));
+    return VEGAS_OK;
 }
 
 }  // namespace vgh
@@ -724,6 +758,11 @@ vegas_status vegas_result(vegas_ctx* c, vegas_estimate* out)
     HIPCHK(hipMemcpy(&bad, c->nonfinite(), sizeof bad, hipMemcpyDeviceToHost));
     out->n_nonfinite = (int64_t)bad;
     if (bad) return fail(VEGAS_ENONFINITE, "%llu sample weights were NaN/Inf and counted as 0", bad);
+    for (int t = 0; t < n; ++t)
+        if (!std::isfinite(I[t]) || !std::isfinite(s2[t]))
+            return fail(VEGAS_ENONFINITE, "iteration %d: estimate %g, variance %g are not finite (with KAHAN "
+                                          "accumulation the sums are FP32: |w| must stay below about 1e19)",
+                        t, I[t], s2[t]);
     return VEGAS_OK;
 }
 

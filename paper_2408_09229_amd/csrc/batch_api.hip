@@ -2,13 +2,21 @@
 //
 // A batch holds n independent problems (each with its own dimension,
 // intervals, budget, integrand and Philox stream) that advance one
-// iteration at a time together: one persistent fill launch for all of them,
-// then batched estimate, allocation and map kernels (batch.hip).
+// iteration at a time together, under one of two launch schedules:
+//  - streams: one single-problem context per problem (the kernels of one
+//    problem are the single-problem kernels), the problems spread over a
+//    few streams of the batch, longest first onto the least loaded stream;
+//    fork from and join to the caller's stream around every iteration.  An
+//    autotuner times the fill of all problems under each stream count and
+//    keeps the fastest in a text cache.
+//  - persistent: one persistent fill launch for all problems, then batched
+//    estimate, allocation and map kernels (batch.hip).  Switched off: its
+//    first device run faulted and the cause is not yet found.
 //
-// Host work: validation, the work layout (tile size per problem, tiles per
-// work item, the longest-first queue order), workspace carving, the
-// autotuner that times the fill over a few layouts and remembers the best one
-// in a text cache, and the Eq. 8-9 combination per problem on request.
+// Host work of the persistent schedule: validation, the work layout (tile
+// size per problem, tiles per work item, the longest-first queue order),
+// workspace carving, its autotuner over layouts, and the Eq. 8-9
+// combination per problem on request.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,7 +39,13 @@ namespace {
 
 constexpr int kBatchMaxDim = 12;
 constexpr int kBatchDefaultLog = 256;      // iteration log capacity when max_iter = 0
-constexpr bool kBatchDisabled = true;
+constexpr bool kPersistentDisabled = true;
+
+// streams schedule: candidate stream counts (the first entry after the
+// default is timed first) and the default without tuning
+const int kStreamCandidates[] = {1, 2, 4, 8};
+constexpr int kDefaultStreams = 4;
+constexpr int kMaxStreams = 8;
 
 // A work layout: samples per lane (upper bound; small problems use fewer)
 // and the target number of samples in one work item.
@@ -146,17 +160,21 @@ BatchPlan batch_plan(const std::vector<Geometry>& gs, const Layout& L, int max_i
 }
 
 // validation of the batch as a whole; fills gs
-vegas_status batch_geometry(int32_t n, const vegas_config* cfgs, const vegas_integrand* fs, std::vector<Geometry>& gs,
-                            int* max_iter)
+vegas_status batch_geometry(int32_t n, const vegas_config* cfgs, const vegas_integrand* fs, int32_t schedule,
+                            std::vector<Geometry>& gs, int* max_iter)
 {
     if (n < 1 || n > (1 << 20)) return fail(VEGAS_EINVAL, "batch size must be 1..2^20");
     if (!cfgs || !fs) return fail(VEGAS_EINVAL, "null configs or integrands");
+    if (schedule != VEGAS_BATCH_STREAMS && schedule != VEGAS_BATCH_PERSISTENT)
+        return fail(VEGAS_EINVAL, "unknown batch schedule %d", schedule);
     gs.resize(n);
     int mi = 0;
     for (int i = 0; i < n; ++i) {
         const vegas_config& c = cfgs[i];
-        if (c.accum != VEGAS_ACC_FP64 && c.accum != VEGAS_ACC_KAHAN)
-            return fail(VEGAS_EUNSUPPORTED, "problem %d: a batch accumulates in FP64 or KAHAN form", i);
+        const bool ordered_ok = schedule == VEGAS_BATCH_STREAMS && c.accum == VEGAS_ACC_ORDERED;
+        if (c.accum != VEGAS_ACC_FP64 && c.accum != VEGAS_ACC_KAHAN && !ordered_ok)
+            return fail(VEGAS_EUNSUPPORTED, "problem %d: a batch accumulates in FP64 or KAHAN form (or ORDERED "
+                                            "under the streams schedule)", i);
         if (c.precision != cfgs[0].precision || c.accum != cfgs[0].accum)
             return fail(VEGAS_EINVAL, "problem %d: precision and accumulation must agree across the batch", i);
         const vegas_status s = geometry(&c, &fs[i], &gs[i]);
@@ -221,9 +239,24 @@ struct vegas_batch {
     bool timing;
     std::vector<hipEvent_t> events;
 
+    // streams schedule
+    bool streams = false;
+    std::vector<vegas_ctx*> ctx;           // one per problem
+    std::vector<size_t> ctx_off;           // its workspace slice
+    std::vector<hipStream_t> lanes;        // kMaxStreams streams of the batch
+    std::vector<hipEvent_t> joins;         // one per stream
+    hipEvent_t fork = nullptr;
+    int n_lanes = 0;                       // streams in use
+    std::vector<uint32_t> order;           // problems, most expensive first
+
     ~vegas_batch()
     {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        for (vegas_ctx* c : ctx)
+            if (c) vegas_destroy(c);
+        for (hipEvent_t e : joins) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
+        for (hipStream_t q : lanes) (void)hipStreamDestroy(q);
     }
     hipError_t mark()
     {
@@ -503,39 +536,295 @@ vegas_status batch_iteration(vegas_batch* b, bool integrate)
     return VEGAS_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// streams schedule
+// ---------------------------------------------------------------------------
+
+// workspace slices: problem i as a single context whose log holds max_iter
+vegas_status streams_layout(int32_t n, const vegas_config* cfgs, const vegas_integrand* fs, int max_iter,
+                            std::vector<size_t>* off, size_t* total)
+{
+    size_t o = 0;
+    if (off) off->resize(n);
+    for (int i = 0; i < n; ++i) {
+        vegas_config c = cfgs[i];
+        c.max_iter = max_iter;
+        size_t bytes = 0;
+        const vegas_status s = vegas_workspace_size(&c, &fs[i], &bytes);
+        if (s != VEGAS_OK) {
+            std::string m = vegas_last_error();
+            return fail(s, "problem %d: %s", i, m.c_str());
+        }
+        if (off) (*off)[i] = o;
+        o += (bytes + 255) & ~(size_t)255;
+    }
+    *total = o;
+    return VEGAS_OK;
+}
+
+// relative cost of one iteration of a problem: samples times per-sample
+// work, plus the fixed cost of its dozen small launches
+double problem_cost(const Geometry& g) { return (double)g.n_eval * (16.0 + 6.0 * g.D) + 2.0e6; }
+
+// spread the problems over S streams: most expensive first, each onto the
+// stream with the least work so far (ties to the lower index).  Only between
+// iterations, with every stream idle.
+void assign_lanes(vegas_batch* b, int S)
+{
+    std::vector<double> load(S, 0.0);
+    for (uint32_t i : b->order) {
+        int q = 0;
+        for (int r = 1; r < S; ++r)
+            if (load[r] < load[q]) q = r;
+        load[q] += problem_cost(b->g[i]);
+        ctx_set_stream(b->ctx[i], b->lanes[q]);
+    }
+    b->n_lanes = S;
+}
+
+// the streams in use start after the work queued on the caller's stream ...
+vegas_status fork_lanes(vegas_batch* b)
+{
+    HIPCHK(hipEventRecord(b->fork, b->stream));
+    for (int q = 0; q < b->n_lanes; ++q) HIPCHK(hipStreamWaitEvent(b->lanes[q], b->fork, 0));
+    return VEGAS_OK;
+}
+
+// ... and the caller's stream waits for all of them
+vegas_status join_lanes(vegas_batch* b)
+{
+    for (int q = 0; q < b->n_lanes; ++q) {
+        HIPCHK(hipEventRecord(b->joins[q], b->lanes[q]));
+        HIPCHK(hipStreamWaitEvent(b->stream, b->joins[q], 0));
+    }
+    return VEGAS_OK;
+}
+
+vegas_status sync_lanes(vegas_batch* b)
+{
+    for (hipStream_t q : b->lanes) HIPCHK(hipStreamSynchronize(q));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return VEGAS_OK;
+}
+
+vegas_status streams_iteration(vegas_batch* b, bool integrate)
+{
+    if (b->n_run >= b->max_iter) return fail(VEGAS_ESTATE, "iteration log full (max_iter = %d)", b->max_iter);
+    HIPCHK(b->mark());
+    vegas_status s = fork_lanes(b);
+    if (s != VEGAS_OK) return s;
+    for (uint32_t i : b->order) {
+        s = integrate ? vegas_integrate(b->ctx[i], 1) : vegas_adapt(b->ctx[i], 1);
+        if (s != VEGAS_OK) {
+            std::string m = vegas_last_error();
+            return fail(s, "problem %u: %s", i, m.c_str());
+        }
+    }
+    s = join_lanes(b);
+    if (s != VEGAS_OK) return s;
+    HIPCHK(b->mark());
+    b->n_run += 1;
+    b->combined.push_back(integrate ? 1 : 0);
+    return VEGAS_OK;
+}
+
+// the fill of the next iteration of every problem under S streams, timed
+// on the caller's stream
+vegas_status time_streams(vegas_batch* b, int S, float* ms)
+{
+    assign_lanes(b, S);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    hipError_t r = hipEventRecord(e0, b->stream);
+    vegas_status s = r == hipSuccess ? fork_lanes(b) : VEGAS_EDEVICE;
+    for (size_t j = 0; s == VEGAS_OK && j < b->order.size(); ++j) s = ctx_fill_pass(b->ctx[b->order[j]]);
+    if (s == VEGAS_OK) s = join_lanes(b);
+    if (s == VEGAS_OK) r = hipEventRecord(e1, b->stream);
+    if (s == VEGAS_OK && r == hipSuccess) r = hipEventSynchronize(e1);
+    if (s == VEGAS_OK && r == hipSuccess) r = hipEventElapsedTime(ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != VEGAS_OK) return s;
+    HIPCHK(r);
+    return VEGAS_OK;
+}
+
+// one warm-up and the better of two timed passes per stream count
+vegas_status tune_streams(vegas_batch* b, int* best, double* best_ms)
+{
+    double bm = INFINITY;
+    int bs = kDefaultStreams;
+    for (int S : kStreamCandidates) {
+        float t0 = 0.f, t1 = 0.f, t2 = 0.f;
+        vegas_status s;
+        if ((s = time_streams(b, S, &t0)) != VEGAS_OK) return s;
+        if ((s = time_streams(b, S, &t1)) != VEGAS_OK) return s;
+        if ((s = time_streams(b, S, &t2)) != VEGAS_OK) return s;
+        const double t = std::min(t1, t2);
+        if (t < bm) {
+            bm = t;
+            bs = S;
+        }
+    }
+    *best = bs;
+    *best_ms = bm;
+    return VEGAS_OK;
+}
+
+bool streams_cache_lookup(const char* path, uint64_t key, int* S, double* ms)
+{
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[256];
+    bool hit = false;
+    while (std::fgets(line, sizeof line, f)) {
+        unsigned long long k;
+        int q;
+        double t;
+        if (std::sscanf(line, "%llx streams %d %lf", &k, &q, &t) != 3 || k != key) continue;
+        for (int c : kStreamCandidates)
+            if (c == q) {
+                *S = q;
+                *ms = t;
+                hit = true;
+            }
+    }
+    std::fclose(f);
+    return hit;
+}
+
+void streams_cache_store(const char* path, uint64_t key, int S, double ms)
+{
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%016llx streams %d %.6f\n", (unsigned long long)key, S, ms);
+    std::fclose(f);
+}
+
+// set up every problem as a context in its slice of the workspace, then
+// choose the stream count
+vegas_status create_streams(vegas_batch* b, const vegas_config* cfgs, const vegas_integrand* fs,
+                            const char* tune_cache)
+{
+    const int n = b->n;
+    size_t total = 0;
+    vegas_status s = streams_layout(n, cfgs, fs, b->max_iter, &b->ctx_off, &total);
+    if (s != VEGAS_OK) return s;
+    if (b->ws_bytes < total) return fail(VEGAS_ENOMEM, "workspace has %zu bytes, needs %zu", b->ws_bytes, total);
+    b->ws_bytes = total;
+    b->lanes.resize(kMaxStreams);
+    b->joins.resize(kMaxStreams);
+    for (int q = 0; q < kMaxStreams; ++q) {
+        HIPCHK(hipStreamCreateWithFlags(&b->lanes[q], hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&b->joins[q], hipEventDisableTiming));
+    }
+    HIPCHK(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    b->order.resize(n);
+    std::iota(b->order.begin(), b->order.end(), 0u);
+    std::stable_sort(b->order.begin(), b->order.end(),
+                     [&](uint32_t x, uint32_t y) { return problem_cost(b->g[x]) > problem_cost(b->g[y]); });
+    b->n_lanes = kMaxStreams;
+    if ((s = fork_lanes(b)) != VEGAS_OK) return s;
+    b->ctx.assign(n, nullptr);
+    for (int i = 0; i < n; ++i) {
+        vegas_config c = cfgs[i];
+        c.max_iter = b->max_iter;
+        const size_t end = i + 1 < n ? b->ctx_off[i + 1] : total;
+        s = vegas_create(&c, &fs[i], b->ws + b->ctx_off[i], end - b->ctx_off[i], b->lanes[i % kMaxStreams],
+                         &b->ctx[i]);
+        if (s != VEGAS_OK) {
+            std::string m = vegas_last_error();
+            return fail(s, "problem %d: %s", i, m.c_str());
+        }
+    }
+    if ((s = sync_lanes(b)) != VEGAS_OK) return s;
+    int S = kDefaultStreams;
+    // (the bare fill pass the tuner times has no ORDERED form)
+    if (tune_cache && cfgs[0].accum != VEGAS_ACC_ORDERED) {
+        const uint64_t key = fnv1a(batch_key(b), "streams", 7);
+        double ms = 0.0;
+        if (streams_cache_lookup(tune_cache, key, &S, &ms)) {
+            b->tuned = 2;
+            b->tune_ms = ms;
+        } else {
+            if ((s = tune_streams(b, &S, &ms)) != VEGAS_OK) return s;
+            b->tuned = 1;
+            b->tune_ms = ms;
+            streams_cache_store(tune_cache, key, S, ms);
+        }
+    }
+    assign_lanes(b, S);
+    return sync_lanes(b);
+}
+
 }  // namespace
 
 extern "C" {
 
-vegas_status vegas_batch_workspace_size(int32_t n, const vegas_config* cfgs, const vegas_integrand* fs, size_t* bytes)
+vegas_status vegas_batch_workspace_size(int32_t n, const vegas_config* cfgs, const vegas_integrand* fs,
+                                        int32_t schedule, size_t* bytes)
 {
     std::vector<Geometry> gs;
     int max_iter = 0;
-    const vegas_status s = batch_geometry(n, cfgs, fs, gs, &max_iter);
+    const vegas_status s = batch_geometry(n, cfgs, fs, schedule, gs, &max_iter);
     if (s != VEGAS_OK) return s;
     if (!bytes) return fail(VEGAS_EINVAL, "null bytes");
+    if (schedule == VEGAS_BATCH_STREAMS) return streams_layout(n, cfgs, fs, max_iter, nullptr, bytes);
     *bytes = batch_bytes(gs, max_iter);
     return VEGAS_OK;
 }
 
 vegas_status vegas_batch_create(int32_t n, const vegas_config* cfgs, const vegas_integrand* fs, void* d_workspace,
-                                size_t bytes, void* hip_stream, const char* tune_cache, vegas_batch** out)
+                                size_t bytes, void* hip_stream, int32_t schedule, const char* tune_cache,
+                                vegas_batch** out)
 {
     if (!out) return fail(VEGAS_EINVAL, "null out");
     *out = nullptr;
     std::vector<Geometry> gs;
     int max_iter = 0;
-    vegas_status s = batch_geometry(n, cfgs, fs, gs, &max_iter);
+    vegas_status s = batch_geometry(n, cfgs, fs, schedule, gs, &max_iter);
     if (s != VEGAS_OK) return s;
     if (!d_workspace) return fail(VEGAS_EINVAL, "null workspace");
     if (((uintptr_t)d_workspace & 255u) != 0) return fail(VEGAS_EINVAL, "workspace must be 256-byte aligned");
+    if (schedule == VEGAS_BATCH_STREAMS) {
+        vegas_batch* b = new vegas_batch();
+        b->n = n;
+        b->cfg.assign(cfgs, cfgs + n);
+        b->g = gs;
+        b->fp64 = cfgs[0].precision == VEGAS_PREC_FP64;
+        b->kahan = cfgs[0].accum == VEGAS_ACC_KAHAN;
+        b->any_general_beta = false;
+        b->max_ng = 1;
+        b->max_iter = max_iter;
+        b->stream = (hipStream_t)hip_stream;
+        b->ws = (unsigned char*)d_workspace;
+        b->ws_bytes = bytes;
+        b->n_wg = 0;
+        b->cur = 0;
+        b->n_run = 0;
+        b->tuned = 0;
+        b->tune_ms = 0.0;
+        b->timing = false;
+        b->lds = 0;
+        b->streams = true;
+        s = create_streams(b, cfgs, fs, tune_cache);
+        if (s != VEGAS_OK) {
+            (void)sync_lanes(b);
+            delete b;
+            return s;
+        }
+        *out = b;
+        return VEGAS_OK;
+    }
     // Switched off: the first device run of the batched iteration ended in a
     // memory fault whose cause is not found (a CPU emulation of the same
     // kernels is clean and matches the oracle).  Validation and sizing stay
     // available.
-    if (kBatchDisabled)
-        return fail(VEGAS_EUNSUPPORTED, "the batched iteration is switched off: its device run faulted and the "
-                                        "cause is not yet found");
+    if (kPersistentDisabled)
+        return fail(VEGAS_EUNSUPPORTED, "the persistent batch schedule is switched off: its device run faulted "
+                                        "and the cause is not yet found");
     const size_t need = batch_bytes(gs, max_iter);
     if (bytes < need) return fail(VEGAS_ENOMEM, "workspace has %zu bytes, needs %zu", bytes, need);
     int dev = 0, cus = 0;
@@ -601,13 +890,27 @@ vegas_status vegas_batch_create(int32_t n, const vegas_config* cfgs, const vegas
 void vegas_batch_destroy(vegas_batch* b)
 {
     if (!b) return;
+    if (b->streams) (void)sync_lanes(b);
     (void)hipStreamSynchronize(b->stream);
     delete b;
+}
+
+vegas_status vegas_batch_set_streams(vegas_batch* b, int32_t n_streams)
+{
+    if (!b) return fail(VEGAS_EINVAL, "null batch");
+    if (!b->streams) return fail(VEGAS_EUNSUPPORTED, "the stream count belongs to the streams schedule");
+    if (b->n_run != 0) return fail(VEGAS_ESTATE, "the stream count is fixed once iterations have run");
+    if (n_streams < 1 || n_streams > kMaxStreams) return fail(VEGAS_EINVAL, "n_streams must be 1..%d", kMaxStreams);
+    vegas_status s = sync_lanes(b);
+    if (s != VEGAS_OK) return s;
+    assign_lanes(b, n_streams);
+    return VEGAS_OK;
 }
 
 vegas_status vegas_batch_set_layout(vegas_batch* b, int32_t per_lane, int64_t item_samples)
 {
     if (!b) return fail(VEGAS_EINVAL, "null batch");
+    if (b->streams) return fail(VEGAS_EUNSUPPORTED, "layouts belong to the persistent schedule");
     if (b->n_run != 0) return fail(VEGAS_ESTATE, "the layout is fixed once iterations have run");
     for (const Layout& c : kCandidates)
         if (c.per_lane == per_lane && c.item_samples == item_samples) return apply_layout(b, c);
@@ -618,7 +921,7 @@ vegas_status vegas_batch_adapt(vegas_batch* b, int32_t n_iter)
 {
     if (!b || n_iter < 0) return fail(VEGAS_EINVAL, "bad arguments");
     for (int i = 0; i < n_iter; ++i) {
-        const vegas_status s = batch_iteration(b, false);
+        const vegas_status s = b->streams ? streams_iteration(b, false) : batch_iteration(b, false);
         if (s != VEGAS_OK) return s;
     }
     return VEGAS_OK;
@@ -628,7 +931,7 @@ vegas_status vegas_batch_integrate(vegas_batch* b, int32_t n_iter)
 {
     if (!b || n_iter < 0) return fail(VEGAS_EINVAL, "bad arguments");
     for (int i = 0; i < n_iter; ++i) {
-        const vegas_status s = batch_iteration(b, true);
+        const vegas_status s = b->streams ? streams_iteration(b, true) : batch_iteration(b, true);
         if (s != VEGAS_OK) return s;
     }
     return VEGAS_OK;
@@ -638,6 +941,16 @@ vegas_status vegas_batch_results(vegas_batch* b, vegas_estimate* out)
 {
     if (!b || !out) return fail(VEGAS_EINVAL, "bad arguments");
     HIPCHK(hipStreamSynchronize(b->stream));
+    if (b->streams) {
+        int64_t bad = 0;
+        for (int i = 0; i < b->n; ++i) {
+            const vegas_status s = vegas_result(b->ctx[i], &out[i]);
+            if (s != VEGAS_OK && s != VEGAS_ENONFINITE) return s;
+            bad += out[i].n_nonfinite;
+        }
+        if (bad) return fail(VEGAS_ENONFINITE, "%lld sample weights were NaN/Inf and counted as 0", (long long)bad);
+        return VEGAS_OK;
+    }
     const size_t n = (size_t)b->n;
     std::vector<double> it(2 * (size_t)b->max_iter * n);
     std::vector<unsigned long long> ctr(8 * n);
@@ -668,6 +981,12 @@ vegas_status vegas_batch_get_iterations(vegas_batch* b, int32_t i, double* I, do
 {
     if (!b || i < 0 || i >= b->n || cap < 0 || (cap > 0 && (!I || !sigma2))) return fail(VEGAS_EINVAL, "bad arguments");
     HIPCHK(hipStreamSynchronize(b->stream));
+    if (b->streams) {
+        int32_t m = 0;
+        const vegas_status s = vegas_get_iterations(b->ctx[i], I, sigma2, cap, &m);
+        if (s == VEGAS_OK && n) *n = m;
+        return s;
+    }
     const int m = std::min(cap, b->n_run);
     std::vector<double> buf(2 * (size_t)std::max(m, 1));
     if (m > 0)
@@ -685,6 +1004,7 @@ vegas_status vegas_batch_get_map(vegas_batch* b, int32_t i, double* grid)
 {
     if (!b || i < 0 || i >= b->n || !grid) return fail(VEGAS_EINVAL, "bad arguments");
     HIPCHK(hipStreamSynchronize(b->stream));
+    if (b->streams) return vegas_get_map(b->ctx[i], grid);
     const Geometry& g = b->g[i];
     HIPCHK(hipMemcpy(grid, b->at<double>(b->p.grid64[i]), sizeof(double) * g.D * (g.ng + 1), hipMemcpyDeviceToHost));
     return VEGAS_OK;
@@ -694,6 +1014,7 @@ vegas_status vegas_batch_get_nh(vegas_batch* b, int32_t i, uint32_t* nh)
 {
     if (!b || i < 0 || i >= b->n || !nh) return fail(VEGAS_EINVAL, "bad arguments");
     HIPCHK(hipStreamSynchronize(b->stream));
+    if (b->streams) return vegas_get_nh(b->ctx[i], nh);
     const Geometry& g = b->g[i];
     std::vector<uint32_t> st((size_t)g.n_cubes + 1);
     HIPCHK(hipMemcpy(st.data(), b->at<uint32_t>(b->cur ? b->p.start1[i] : b->p.start0[i]),
@@ -706,6 +1027,36 @@ vegas_status vegas_batch_get_info(const vegas_batch* b, vegas_batch_info* out)
 {
     if (!b || !out) return fail(VEGAS_EINVAL, "bad arguments");
     out->n = b->n;
+    out->schedule = b->streams ? VEGAS_BATCH_STREAMS : VEGAS_BATCH_PERSISTENT;
+    out->n_streams = b->streams ? b->n_lanes : 0;
+    if (b->streams) {
+        out->per_lane = 0;
+        out->item_samples = 0;
+        out->n_items = b->n;
+        int64_t tiles = 0, ne = 0, nc = 0;
+        int32_t wg = 0;
+        size_t lds = 0;
+        for (int i = 0; i < b->n; ++i) {
+            const Geometry& g = b->g[i];
+            vegas_info ci;
+            const vegas_status s = vegas_get_info(b->ctx[i], &ci);
+            if (s != VEGAS_OK) return s;
+            tiles += g.n_tiles;
+            wg += ci.n_workgroups;
+            ne += g.n_eval;
+            nc += g.n_cubes;
+            lds = std::max(lds, fill_lds_bytes(g.D, g.ng, b->fp64, ci.lds_hist, g.tile, g.n_aux));
+        }
+        out->n_tiles = tiles;
+        out->n_workgroups = wg;
+        out->tuned = b->tuned;
+        out->tune_ms = b->tune_ms;
+        out->lds_bytes = lds;
+        out->workspace_bytes = b->ws_bytes;
+        out->n_eval_total = ne;
+        out->n_cubes_total = nc;
+        return VEGAS_OK;
+    }
     out->per_lane = b->layout.per_lane;
     out->item_samples = b->layout.item_samples;
     out->n_items = b->p.n_items;
@@ -728,6 +1079,10 @@ vegas_status vegas_batch_get_info(const vegas_batch* b, vegas_batch_info* out)
 vegas_status vegas_batch_set_timing(vegas_batch* b, int32_t on)
 {
     if (!b) return fail(VEGAS_EINVAL, "bad arguments");
+    if (b->streams) {
+        const vegas_status s = sync_lanes(b);
+        if (s != VEGAS_OK) return s;
+    }
     HIPCHK(hipStreamSynchronize(b->stream));
     for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
     b->events.clear();
@@ -742,6 +1097,16 @@ vegas_status vegas_batch_get_timing(vegas_batch* b, double* ms, int32_t* n_iter)
     for (int i = 0; i < 4; ++i) ms[i] = 0.0;
     size_t i = 0;
     int n = 0;
+    if (b->streams) {
+        // two marks per iteration: before the fork, after the join
+        for (; i + 2 <= b->events.size(); i += 2, ++n) {
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, b->events[i], b->events[i + 1]));
+            ms[0] += t;
+        }
+        if (n_iter) *n_iter = n;
+        return VEGAS_OK;
+    }
     while (i + 5 <= b->events.size()) {
         for (int q = 0; q < 4; ++q) {
             float t = 0.f;

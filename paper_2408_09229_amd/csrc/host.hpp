@@ -47,4 +47,12 @@ vegas_status geometry(const vegas_config* c, const vegas_integrand* f, Geometry*
 // iteration estimates (iterations with sigma^2 = 0 are exact and decide)
 void combine(const std::vector<double>& I, const std::vector<double>& s2, double* Ib, double* s2b, double* chi);
 
+// Hooks for the batch driver, which runs one single-problem context per
+// problem: move a context to another stream (between iterations only), and
+// enqueue the fill of the next iteration alone, leaving the iteration count,
+// the allocation and the map as they are (its accumulators are overwritten
+// by the iteration itself; used to time launch schedules).
+void ctx_set_stream(vegas_ctx* c, hipStream_t s);
+vegas_status ctx_fill_pass(vegas_ctx* c);
+
 }  // namespace vgh

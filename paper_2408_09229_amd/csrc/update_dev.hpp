@@ -89,7 +89,9 @@ __device__ __forceinline__ QPlan q_plan(const AllocArgs& a, const unsigned long 
     if (!p.uniform) {
         if (beta_monotone(a.beta)) p.qmax = pow_half_beta(__longlong_as_double((long long)*a.vmax), a.beta);
         else p.qmax = __longlong_as_double((long long)*qmax_bits);
-        if (!(p.qmax > 0.0)) p.uniform = 1;
+        // a zero, infinite or NaN maximum (an overflowed variance) leaves no
+        // usable weights: fall back to the uniform allocation, so T > 0
+        if (!(p.qmax > 0.0) || !(p.qmax <= 1.7976931348623157e308)) p.uniform = 1;
     }
     return p;
 }
@@ -98,7 +100,9 @@ __device__ __forceinline__ uint64_t quant(const AllocArgs& a, const QPlan& p, ui
 {
     if (p.uniform) return 1ull;
     const double q = pow_half_beta(a.v[h], a.beta);
-    return (uint64_t)floor((q / p.qmax) * 4294967296.0);
+    const double r = q / p.qmax;
+    // r is in [0, 1] for finite variances; a NaN weight counts as 0
+    return r >= 0.0 ? (uint64_t)floor(fmin(r, 1.0) * 4294967296.0) : 0ull;
 }
 
 // block blk of a problem's cubes: the block's largest q into qmax_bits

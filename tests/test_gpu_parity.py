@@ -271,3 +271,23 @@ def test_kahan_accumulation(V, w):
     assert abs(r.integral - exact) < 3.0 * math.sqrt(r.sigma2), (r.integral, exact, math.sqrt(r.sigma2))
     a.close()
     b.close()
+
+
+def test_kahan_overflow_reported(V):
+    """Squared weights beyond FP32 range: the compensated FP32 variance
+    overflows.  The result says so (VEGAS_ENONFINITE) and the allocation
+    falls back to uniform instead of using the overflowed variances."""
+    from paper_2408_09229_amd import VegasError
+    D = 12
+    # typical weights ~1e20 (squares past FP32), the largest well inside FP32
+    prm = np.concatenate([[1e8], np.full(D, 20.0), np.full(D, 0.5)])
+    w = vi.Workload("ppeak12_kahan", D, vi.GENZ_PPEAK, prm, n_g=64, n_eval=200_000, n_iter=1)
+    say(f"[kahan overflow] {w.name}")
+    v = V(w, precision="f32", accum="kahan")
+    v.adapt(2)
+    nh = v.get_nh()
+    assert int(nh.sum()) == w.n_eval and int(nh.min()) >= w.n_min
+    with pytest.raises(VegasError) as e:
+        v.result()
+    assert e.value.status == -5
+    v.close()
