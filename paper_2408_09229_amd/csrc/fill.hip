@@ -36,7 +36,7 @@
 
 namespace vg {
 
-template <typename R, int FAM, int MAXD, bool KAHAN>
+template <typename R, int FAM, int MAXD, bool KAHAN, bool EXACT>
 __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs a)
         }
     }
 
-    SamplePath<R, FAM, MAXD> sp(sc, L.auxl);
+    SamplePath<R, FAM, MAXD, EXACT> sp(sc, L.auxl);
     LaneTotal<KAHAN> totI, totV;
     double vmax = 0.0;
     unsigned long long bad = 0;
@@ -186,23 +186,29 @@ __global__ void k_probe(ProbeArgs a)
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
+// the kernel for dimension bound MAXD; its guard-free form when D == MAXD
+template <typename R, int FAM, int MAXD, bool KAHAN>
+static void launch_fill_d(const FillArgs& a, int n_wg, size_t lds, hipStream_t st)
+{
+    if (a.sc.D == MAXD) {
+        hipFuncSetAttribute((const void*)k_fill<R, FAM, MAXD, KAHAN, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_fill<R, FAM, MAXD, KAHAN, true>), dim3(n_wg), dim3(kFillThreads), lds, st, a);
+    } else {
+        hipFuncSetAttribute((const void*)k_fill<R, FAM, MAXD, KAHAN, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_fill<R, FAM, MAXD, KAHAN, false>), dim3(n_wg), dim3(kFillThreads), lds, st, a);
+    }
+}
+
 template <typename R, int FAM, bool KAHAN>
 static hipError_t launch_fill_k(const FillArgs& a, int n_wg, size_t lds, hipStream_t st)
 {
     const int D = a.sc.D;
-    if (D <= 4) {
-        hipFuncSetAttribute((const void*)k_fill<R, FAM, 4, KAHAN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_fill<R, FAM, 4, KAHAN>), dim3(n_wg), dim3(kFillThreads), lds, st, a);
-    } else if (D <= 8) {
-        hipFuncSetAttribute((const void*)k_fill<R, FAM, 8, KAHAN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_fill<R, FAM, 8, KAHAN>), dim3(n_wg), dim3(kFillThreads), lds, st, a);
-    } else if (D <= 12) {
-        hipFuncSetAttribute((const void*)k_fill<R, FAM, 12, KAHAN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_fill<R, FAM, 12, KAHAN>), dim3(n_wg), dim3(kFillThreads), lds, st, a);
-    } else {
-        hipFuncSetAttribute((const void*)k_fill<R, FAM, 16, KAHAN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_fill<R, FAM, 16, KAHAN>), dim3(n_wg), dim3(kFillThreads), lds, st, a);
-    }
+    if (D <= 4) launch_fill_d<R, FAM, 4, KAHAN>(a, n_wg, lds, st);
+    else if (D <= 8) launch_fill_d<R, FAM, 8, KAHAN>(a, n_wg, lds, st);
+    else if (D <= 12) launch_fill_d<R, FAM, 12, KAHAN>(a, n_wg, lds, st);
+    else launch_fill_d<R, FAM, 16, KAHAN>(a, n_wg, lds, st);
     return hipGetLastError();
 }
 

@@ -366,7 +366,7 @@ __device__ __forceinline__ void fill_tile(int tile, const TileIO& io, const Fill
                 if (io.lds_hist) {
 #pragma unroll
                     for (int d = 0; d < MAXD; ++d) {
-                        if (d < D) {
+                        if (Path::kExact || d < D) {
                             const uint32_t bi = (uint32_t)d * ng + bins[d];
                             atomicAdd(hl + bi, w2);
                             atomicAdd(cl + bi, 1u);
@@ -375,7 +375,7 @@ __device__ __forceinline__ void fill_tile(int tile, const TileIO& io, const Fill
                 } else {
 #pragma unroll
                     for (int d = 0; d < MAXD; ++d) {
-                        if (d < D) {
+                        if (Path::kExact || d < D) {
                             const uint32_t bi = (uint32_t)d * ng + bins[d];
                             unsafeAtomicAdd(io.hist_H + bi, w2);
                             atomicAdd(io.hist_C + bi, 1u);

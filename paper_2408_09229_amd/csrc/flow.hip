@@ -181,6 +181,7 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_sample(FlowSampleArgs a)
 // The stratum digits are not needed (the sampling pass used them).
 template <int FAM>
 struct WarpedPath {
+    static constexpr bool kExact = true;       // D = 16 always
     const SampleConst& sc;
     Fn<float, FAM> fn;
     float ngR;

@@ -15,8 +15,11 @@ namespace vg {
 // ---------------------------------------------------------------------------
 // the per-sample path shared by the fill and the probe
 // ---------------------------------------------------------------------------
-template <typename R, int FAM, int MAXD>
+// MAXD bounds the dimension; EXACT says D == MAXD, which drops the per-axis
+// guards (and the register moves and lane-mask copies they cost).
+template <typename R, int FAM, int MAXD, bool EXACT = false>
 struct SamplePath {
+    static constexpr bool kExact = EXACT;
     const SampleConst& sc;
     Fn<R, FAM> fn;
     PhiloxKeys keys;
@@ -34,6 +37,8 @@ struct SamplePath {
         nst_d = (double)c.nst;
         inv_nst_f = (float)(1.0 / (double)c.nst);
     }
+
+    __device__ __forceinline__ bool has(int d) const { return EXACT || d < sc.D; }
 
     // digits of cube h in base N_st, axis 0 fastest
     __device__ __forceinline__ void digits(uint32_t h, uint32_t (&s)[MAXD]) const
@@ -77,7 +82,7 @@ struct SamplePath {
         uint32_t wd[MAXD];
 #pragma unroll
         for (int b = 0; b < (MAXD + 3) / 4; ++b) {
-            if (4 * b < sc.D) {
+            if (has(4 * b)) {
                 const W4 o = philox10(k, 0u, t, sc.ctr3 | (uint32_t)b, keys);
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
@@ -89,7 +94,7 @@ struct SamplePath {
         const uint32_t row = sc.ng + 1u;
 #pragma unroll
         for (int d = 0; d < MAXD; ++d) {
-            if (d < sc.D) {
+            if (has(d)) {
                 const BinSplit p = bin_split(s[d], wd[d], sc.ng, sc.nst, sc.nst_magic, sc.nst_shift);
                 bins[d] = p.bin;
                 R delta;
