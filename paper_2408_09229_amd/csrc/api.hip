@@ -137,7 +137,7 @@ vegas_status geometry(const vegas_config* c, const vegas_integrand* f, Geometry*
     g->n_cubes = (uint32_t)nc;
     g->R = (uint64_t)c->n_eval - (uint64_t)c->n_min * nc;
     if (m == 1) {
-        g->magic = 0;
+        g->magic = 0x80000000u;      // q2 2^31 / 2^32 = q, with shift -1
         g->shift = -1;
     } else {
         int l = 0;

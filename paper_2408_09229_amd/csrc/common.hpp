@@ -89,11 +89,17 @@ __device__ __forceinline__ uint32_t div_magic(uint32_t q, uint32_t magic, int sh
 // ---------------------------------------------------------------------------
 struct BinSplit {
     uint32_t bin;
-    uint32_t c;       // q mod N_st
+    uint32_t c2;      // 2 (q mod N_st)
     uint32_t p_lo;    // N_g (2r+1) = p_hi 2^32 + p_lo
     uint32_t p_hi;
 };
 
+// q is carried doubled, q2 = 2q < 2^32.  Then floor(q / N_st) =
+// floor(floor(q2 magic / 2^32) / 2^(shift+1)), the same nested floors as
+// umulhi(q, magic) >> shift, and one formula covers N_st = 1 as well (magic
+// 2^31, shift -1), so the split has no branch.  The remainder comes back
+// doubled too, 2 (q mod N_st) = q2 - bin (2 N_st), in one 24-bit
+// multiply-add.
 __device__ __forceinline__ BinSplit bin_split(uint32_t s, uint32_t r, uint32_t ng, uint32_t nst,
                                               uint32_t nst_magic, int nst_shift)
 {
@@ -102,30 +108,32 @@ __device__ __forceinline__ BinSplit bin_split(uint32_t s, uint32_t r, uint32_t n
     BinSplit o;
     o.p_lo = (uint32_t)P;
     o.p_hi = (uint32_t)(P >> 32);
-    const uint32_t a = o.p_hi >> 1;                 // floor(P / 2^33)
-    // N_g, N_st < 2^24 and N_g s < 2^31: 24-bit multiplies are exact
-    const uint32_t q = __umul24(ng, s) + a;
-    o.bin = div_magic(q, nst_magic, nst_shift);
-    o.c = q - __umul24(o.bin, nst);
+    // 2 floor(P / 2^33) = p_hi with its low bit cleared; N_g, N_st < 2^24
+    // and 2 N_g s < 2^32: the 24-bit products are exact
+    const uint32_t q2 = __umul24(2u * ng, s) + (o.p_hi & ~1u);
+    o.bin = __umulhi(q2, nst_magic) >> (uint32_t)(nst_shift + 1);
+    o.c2 = (uint32_t)((int32_t)q2 + __mul24((int32_t)o.bin, -2 * (int32_t)nst));
     return o;
 }
 
 // delta = rho / (N_st 2^33) with rho = c 2^33 + (P mod 2^33), rounded once:
-// rho 2^-33 is exact in FP64 when rho < 2^53, and dividing the exact value by
-// N_st rounds once.
-__device__ __forceinline__ double delta_f64(const BinSplit& p, double nst_d)
+// rho 2^-32 = 2c + (P mod 2^33) 2^-32 is exact in FP64 when 2 rho < 2^53,
+// and dividing that exact value by 2 N_st rounds once (to the same double as
+// rho 2^-33 / N_st).
+__device__ __forceinline__ double delta_f64(const BinSplit& p, double nst2_d)
 {
     const double b = (double)(p.p_hi & 1u) * 4294967296.0 + (double)p.p_lo;
-    const double num = (double)p.c + b * 0x1p-33;
-    return num / nst_d;
+    const double num2 = (double)p.c2 + b * 0x1p-32;
+    return num2 / nst2_d;
 }
 
 // FP32 path: delta to float precision from the top 32 of the 33 fractional
-// bits, (P mod 2^33) >> 1.
-__device__ __forceinline__ float delta_f32(const BinSplit& p, float inv_nst)
+// bits, (P mod 2^33) >> 1, with the doubled remainder: fma(frac, 2^-31, 2c)
+// is exactly twice fma(frac, 2^-32, c), and half_inv_nst = (1/N_st)/2.
+__device__ __forceinline__ float delta_f32(const BinSplit& p, float half_inv_nst)
 {
     const uint32_t frac = __builtin_amdgcn_alignbit(p.p_hi, p.p_lo, 1);
-    return fmaf((float)frac, 0x1p-32f, (float)p.c) * inv_nst;
+    return fmaf((float)frac, 0x1p-31f, (float)p.c2) * half_inv_nst;
 }
 
 // ---------------------------------------------------------------------------

@@ -34,7 +34,7 @@ struct SampleConst {
     uint32_t ng;
     uint32_t nst;
     uint32_t nst_magic;
-    int32_t nst_shift;         // -1: N_st = 1
+    int32_t nst_shift;         // -1: N_st = 1 (magic 2^31)
     uint32_t n_eval;
     uint32_t n_cubes;
     uint32_t key0, key1;       // Philox key = seed

@@ -24,8 +24,8 @@ struct SamplePath {
     Fn<R, FAM> fn;
     PhiloxKeys keys;
     R ngR;
-    double nst_d;
-    float inv_nst_f;
+    double nst2_d;        // 2 N_st
+    float half_inv_nst_f; // (1 / N_st) / 2
 
     // aux: the family's derived table in the path's precision (LDS in the
     // fill, global memory in the probe)
@@ -34,8 +34,8 @@ struct SamplePath {
         fn.setup(c, aux);
         keys = philox_keys<std::is_same<R, float>::value && MAXD <= 8>(c.key0, c.key1);
         ngR = (R)c.ng;
-        nst_d = (double)c.nst;
-        inv_nst_f = (float)(1.0 / (double)c.nst);
+        nst2_d = 2.0 * (double)c.nst;
+        half_inv_nst_f = 0.5f * (float)(1.0 / (double)c.nst);
     }
 
     __device__ __forceinline__ bool has(int d) const { return EXACT || d < sc.D; }
@@ -98,8 +98,8 @@ struct SamplePath {
                 const BinSplit p = bin_split(s[d], wd[d], sc.ng, sc.nst, sc.nst_magic, sc.nst_shift);
                 bins[d] = p.bin;
                 R delta;
-                if constexpr (std::is_same<R, double>::value) delta = delta_f64(p, nst_d);
-                else delta = delta_f32(p, inv_nst_f);
+                if constexpr (std::is_same<R, double>::value) delta = delta_f64(p, nst2_d);
+                else delta = delta_f32(p, half_inv_nst_f);
                 const R* gd = g + d * row;
                 const R xl = gd[p.bin];
                 const R dx = gd[p.bin + 1] - xl;
