@@ -169,7 +169,7 @@ namespace {
 
 // Workspace carving: offsets of every device array (256-byte aligned).
 struct Plan {
-    size_t prm, lo, hi, aux_d, aux_f, grid64, grid32, start[2], tfirst[2], v, wg_part, side, fix_part,
+    size_t prm, lo, hi, aux_d, aux_f, grid64, grid32, start[2], tfirst[2], v, qbuf, wg_part, side, fix_part,
         histH, histC, partH, partC, Hsum, Csum, counters, bsum, boff, iter, ord_w, ord_bins, ord_m, total;
 };
 
@@ -197,6 +197,7 @@ Plan plan(const Geometry& g, int max_iter, bool ordered)
         p.tfirst[b] = take(sizeof(uint32_t) * ((size_t)g.n_tiles + 1));
     }
     p.v = take(sizeof(double) * g.n_cubes);
+    p.qbuf = take(sizeof(uint32_t) * g.n_cubes);
     p.wg_part = take(sizeof(double) * 2 * kMaxWG);
     p.side = take(sizeof(TileSide) * g.n_tiles);
     p.fix_part = take(sizeof(double) * 2 * g.n_tiles);
@@ -325,6 +326,7 @@ AllocArgs alloc_args(vegas_ctx* c, int t, int uniform)
     a.boff = c->at<unsigned long long>(c->p.boff);
     a.start = c->at<uint32_t>(c->p.start[1 - c->cur]);
     a.tile_first = c->at<uint32_t>(c->p.tfirst[1 - c->cur]);
+    a.qbuf = c->at<uint32_t>(c->p.qbuf);
     return a;
 }
 

@@ -257,6 +257,7 @@ __device__ __forceinline__ AllocArgs inst_alloc(const BatchArgs& a, const BatchI
     r.boff = in.boff;
     r.start = in.start[1 - a.cur];
     r.tile_first = in.tfirst[1 - a.cur];
+    r.qbuf = nullptr;
     return r;
 }
 

@@ -102,6 +102,7 @@ struct AllocArgs {
     unsigned long long* boff;   // [n_blocks] exclusive offsets; boff[n_blocks] = T
     uint32_t* start;            // [N_c+1] out
     uint32_t* tile_first;       // [n_tiles+1] out
+    uint32_t* qbuf;             // [N_c] Q_h saturated at 2^32-1 (null: recompute)
 };
 
 constexpr int kHistParts = 8;          // first-level slot groups of the histogram reduce

@@ -96,13 +96,19 @@ __device__ __forceinline__ QPlan q_plan(const AllocArgs& a, const unsigned long 
     return p;
 }
 
+// Q = floor(q / q_max 2^32) of a variance v
+__device__ __forceinline__ uint64_t quant_v(double v, double beta, double qmax)
+{
+    const double q = pow_half_beta(v, beta);
+    const double r = q / qmax;
+    // r is in [0, 1] for finite variances; a NaN weight counts as 0
+    return r >= 0.0 ? (uint64_t)floor(fmin(r, 1.0) * 4294967296.0) : 0ull;
+}
+
 __device__ __forceinline__ uint64_t quant(const AllocArgs& a, const QPlan& p, uint32_t h)
 {
     if (p.uniform) return 1ull;
-    const double q = pow_half_beta(a.v[h], a.beta);
-    const double r = q / p.qmax;
-    // r is in [0, 1] for finite variances; a NaN weight counts as 0
-    return r >= 0.0 ? (uint64_t)floor(fmin(r, 1.0) * 4294967296.0) : 0ull;
+    return quant_v(a.v[h], a.beta, p.qmax);
 }
 
 // block blk of a problem's cubes: the block's largest q into qmax_bits
@@ -157,16 +163,43 @@ __device__ __forceinline__ uint64_t block_exscan(uint64_t v, uint64_t* sh, uint6
     return r;
 }
 
-// block blk: the sum of its Q_h into *bsum
+// the Q_h of the kPerThread consecutive cubes h0.. of one thread (cubes past
+// the end give 0); v is read 16 bytes at a time when all are in range
+__device__ __forceinline__ void quant_run(const AllocArgs& a, const QPlan& p, uint32_t h0, uint64_t (&Q)[kAllocPerThread])
+{
+    static_assert(kAllocPerThread == 4, "two 16-byte loads per thread");
+    if (p.uniform) {
+        for (int i = 0; i < kAllocPerThread; ++i) Q[i] = h0 + (uint32_t)i < a.n_cubes ? 1ull : 0ull;
+        return;
+    }
+    if (h0 + (uint32_t)kAllocPerThread <= a.n_cubes) {
+        const double2 v01 = *reinterpret_cast<const double2*>(a.v + h0);
+        const double2 v23 = *reinterpret_cast<const double2*>(a.v + h0 + 2);
+        const double v[4] = {v01.x, v01.y, v23.x, v23.y};
+        for (int i = 0; i < kAllocPerThread; ++i) Q[i] = quant_v(v[i], a.beta, p.qmax);
+        return;
+    }
+    for (int i = 0; i < kAllocPerThread; ++i) Q[i] = h0 + (uint32_t)i < a.n_cubes ? quant(a, p, h0 + i) : 0ull;
+}
+
+// block blk: the sum of its Q_h into *bsum; Q_h (saturated) into qbuf
 __device__ __forceinline__ void alloc_sum_block(const AllocArgs& a, const unsigned long long* qmax_bits, uint32_t blk,
                                                 unsigned long long* bsum, uint64_t* sh)
 {
     const QPlan p = q_plan(a, qmax_bits);
-    const uint32_t base = blk * (uint32_t)kAllocPerBlock;
+    const uint32_t h0 = blk * (uint32_t)kAllocPerBlock + threadIdx.x * kAllocPerThread;
+    uint64_t Q[kAllocPerThread];
+    quant_run(a, p, h0, Q);
     uint64_t s = 0;
-    for (int i = 0; i < kAllocPerThread; ++i) {
-        const uint32_t h = base + threadIdx.x * kAllocPerThread + i;
-        if (h < a.n_cubes) s += quant(a, p, h);
+    for (int i = 0; i < kAllocPerThread; ++i) s += Q[i];
+    if (a.qbuf && !p.uniform) {
+        uint32_t q32[kAllocPerThread];
+        for (int i = 0; i < kAllocPerThread; ++i) q32[i] = Q[i] > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)Q[i];
+        if (h0 + (uint32_t)kAllocPerThread <= a.n_cubes)
+            *reinterpret_cast<uint4*>(a.qbuf + h0) = make_uint4(q32[0], q32[1], q32[2], q32[3]);
+        else
+            for (int i = 0; i < kAllocPerThread; ++i)
+                if (h0 + (uint32_t)i < a.n_cubes) a.qbuf[h0 + i] = q32[i];
     }
     uint64_t total;
     block_exscan(s, sh, total);
@@ -174,32 +207,48 @@ __device__ __forceinline__ void alloc_sum_block(const AllocArgs& a, const unsign
 }
 
 // block blk: n_h, first samples and tile table from the exclusive offset
-// boff of the block and the total T
+// boff of the block and the total T.  Q_h comes from qbuf (written by the
+// sum pass), recomputed exactly where it saturated.
 __device__ __forceinline__ void alloc_write_block(const AllocArgs& a, const unsigned long long* qmax_bits, uint32_t blk,
                                                   uint64_t boff, uint64_t T, uint64_t* sh)
 {
     const QPlan p = q_plan(a, qmax_bits);
-    const uint32_t base = blk * (uint32_t)kAllocPerBlock;
+    const uint32_t h0 = blk * (uint32_t)kAllocPerBlock + threadIdx.x * kAllocPerThread;
+    const bool full = h0 + (uint32_t)kAllocPerThread <= a.n_cubes;
     uint64_t Q[kAllocPerThread];
-    uint64_t s = 0;
-    for (int i = 0; i < kAllocPerThread; ++i) {
-        const uint32_t h = base + threadIdx.x * kAllocPerThread + i;
-        Q[i] = h < a.n_cubes ? quant(a, p, h) : 0ull;
-        s += Q[i];
+    if (a.qbuf && !p.uniform) {
+        uint32_t q32[kAllocPerThread] = {0u, 0u, 0u, 0u};
+        if (full) {
+            const uint4 v = *reinterpret_cast<const uint4*>(a.qbuf + h0);
+            q32[0] = v.x;
+            q32[1] = v.y;
+            q32[2] = v.z;
+            q32[3] = v.w;
+        } else {
+            for (int i = 0; i < kAllocPerThread; ++i)
+                if (h0 + (uint32_t)i < a.n_cubes) q32[i] = a.qbuf[h0 + i];
+        }
+        for (int i = 0; i < kAllocPerThread; ++i)
+            Q[i] = q32[i] == 0xFFFFFFFFu ? quant(a, p, h0 + i) : (uint64_t)q32[i];
+    } else {
+        quant_run(a, p, h0, Q);
     }
+    uint64_t s = 0;
+    for (int i = 0; i < kAllocPerThread; ++i) s += Q[i];
     uint64_t total;
     uint64_t Cprev = boff + block_exscan(s, sh, total);
     const uint64_t R = a.R;
     const double rT = (double)R / (double)T;
     uint64_t lo = floor_mul_div(R, Cprev, T, rT);
+    uint32_t st[kAllocPerThread];
     for (int i = 0; i < kAllocPerThread; ++i) {
-        const uint32_t h = base + threadIdx.x * kAllocPerThread + i;
+        const uint32_t h = h0 + (uint32_t)i;
         if (h >= a.n_cubes) break;
         const uint64_t C = Cprev + Q[i];
         const uint64_t hi = floor_mul_div(R, C, T, rT);
         const uint32_t start = h * a.n_min + (uint32_t)lo;
         const uint32_t nh = a.n_min + (uint32_t)(hi - lo);
-        a.start[h] = start;
+        st[i] = start;
         // tiles whose first sample lies in this cube
         const uint64_t end = (uint64_t)start + nh;
         for (uint64_t j = ((uint64_t)start + (uint64_t)a.tile - 1u) >> a.tile_shift; (j << a.tile_shift) < end; ++j)
@@ -210,6 +259,12 @@ __device__ __forceinline__ void alloc_write_block(const AllocArgs& a, const unsi
         }
         Cprev = C;
         lo = hi;
+    }
+    if (full) {
+        *reinterpret_cast<uint4*>(a.start + h0) = make_uint4(st[0], st[1], st[2], st[3]);
+    } else {
+        for (int i = 0; i < kAllocPerThread; ++i)
+            if (h0 + (uint32_t)i < a.n_cubes) a.start[h0 + i] = st[i];
     }
 }
 
