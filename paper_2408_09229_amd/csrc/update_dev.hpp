@@ -284,6 +284,8 @@ __device__ __forceinline__ double damp(double e, double alpha)
 
 // axis d of a problem (one 1024-lane workgroup); smem holds 3 (N_g+1)
 // doubles, S_sh one shared double
+constexpr int kSeqChunk = 16;           // LDS reads in flight in the sequential sums
+
 __device__ __forceinline__ void map_update_axis(const MapArgs& a, int d, unsigned char* smem, double& S_sh)
 {
     const int ng = a.ng;
@@ -322,8 +324,17 @@ __device__ __forceinline__ void map_update_axis(const MapArgs& a, int d, unsigne
     }
     __syncthreads();
     if (tid == 0) {
+        // in interval order; the reads go ahead in chunks, the adds do not
         double S = 0.0;
-        for (int i = 0; i < ng; ++i) S += B[i];
+        int i = 0;
+        for (; i + kSeqChunk <= ng; i += kSeqChunk) {
+            double v[kSeqChunk];
+#pragma unroll
+            for (int k = 0; k < kSeqChunk; ++k) v[k] = B[i + k];
+#pragma unroll
+            for (int k = 0; k < kSeqChunk; ++k) S += v[k];
+        }
+        for (; i < ng; ++i) S += B[i];
         S_sh = S;
     }
     __syncthreads();
@@ -332,9 +343,23 @@ __device__ __forceinline__ void map_update_axis(const MapArgs& a, int d, unsigne
     for (int i = tid; i < ng; i += 1024) A[i] = damp(B[i] / S, a.alpha);
     __syncthreads();
     if (tid == 0) {
+        // sequential prefix; a chunk of A is read before its prefixes are
+        // written (A and B do not overlap), so the LDS reads do not wait on
+        // the writes one by one
         double c = 0.0;
         B[0] = 0.0;
-        for (int i = 0; i < ng; ++i) {
+        int i = 0;
+        for (; i + kSeqChunk <= ng; i += kSeqChunk) {
+            double v[kSeqChunk];
+#pragma unroll
+            for (int k = 0; k < kSeqChunk; ++k) v[k] = A[i + k];
+#pragma unroll
+            for (int k = 0; k < kSeqChunk; ++k) {
+                c = c + v[k];
+                B[i + 1 + k] = c;
+            }
+        }
+        for (; i < ng; ++i) {
             c = c + A[i];
             B[i + 1] = c;
         }
