@@ -255,6 +255,7 @@ struct vegas_ctx {
     size_t f_acc = 0;                  // last accepted parameters
     size_t f_seg = 0;                  // segment sums of the gradient reduction
     int n_cus = 1;
+    bool fused = false;                // small problem: one launch after the fill
     std::vector<uint8_t> warped;       // per iteration: 1 = sampled through the warp
     double ref_I = 0.0, ref_s2 = INFINITY;   // plain VEGAS+ reference of the judge
     int rejects = 0;                   // consecutive rejected warped iterations
@@ -330,6 +331,24 @@ AllocArgs alloc_args(vegas_ctx* c, int t, int uniform)
     return a;
 }
 
+// the map refinement's record over n_slots histogram slots added in order
+MapArgs map_args(vegas_ctx* c, int n_slots)
+{
+    MapArgs m;
+    m.D = c->g.D;
+    m.ng = c->g.ng;
+    m.n_slots = n_slots;
+    m.parts = 0;
+    m.alpha = c->cfg.adapt_map ? c->cfg.alpha : 0.0;
+    m.hist_H = c->at<double>(c->p.histH);
+    m.hist_C = c->at<uint32_t>(c->p.histC);
+    m.grid64 = c->at<double>(c->p.grid64);
+    m.grid32 = c->at<float>(c->p.grid32);
+    m.Hsum = c->at<double>(c->p.Hsum);
+    m.Csum = c->at<double>(c->p.Csum);
+    return m;
+}
+
 // allocation then map refinement from the accumulators of "slot set" t
 vegas_status run_update(vegas_ctx* c, int t, int n_slots, bool timed)
 {
@@ -338,13 +357,7 @@ vegas_status run_update(vegas_ctx* c, int t, int n_slots, bool timed)
     HIPCHK(launch_alloc(aa, c->qmax(t), c->stream));
     c->cur = 1 - c->cur;
     if (timed) HIPCHK(c->mark());
-    MapArgs m;
-    m.D = c->g.D;
-    m.ng = c->g.ng;
-    m.n_slots = n_slots;
-    m.alpha = c->cfg.adapt_map ? c->cfg.alpha : 0.0;
-    m.hist_H = c->at<double>(c->p.histH);
-    m.hist_C = c->at<uint32_t>(c->p.histC);
+    MapArgs m = map_args(c, n_slots);
     if (n_slots > kHistParts) {
         // many workgroup slots: a wide first-level reduce, then the map
         // kernel adds kHistParts partials in order
@@ -361,10 +374,6 @@ vegas_status run_update(vegas_ctx* c, int t, int n_slots, bool timed)
         m.hist_H = hr.part_H;
         m.hist_C = hr.part_C;
     }
-    m.grid64 = c->at<double>(c->p.grid64);
-    m.grid32 = c->at<float>(c->p.grid32);
-    m.Hsum = c->at<double>(c->p.Hsum);
-    m.Csum = c->at<double>(c->p.Csum);
     HIPCHK(launch_map_update(m, c->stream));
     if (timed) HIPCHK(c->mark());
     return VEGAS_OK;
@@ -465,7 +474,6 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
     fx.v_out = a.v_out;
     fx.fix_part = c->at<double>(c->p.fix_part);
     fx.vmax = a.vmax;
-    HIPCHK(launch_fixup(fx, c->stream));
     FinalArgs fa;
     fa.n_wg = c->n_wg;
     fa.n_tiles = c->g.n_tiles;
@@ -473,10 +481,31 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
     fa.wg_part = a.wg_part;
     fa.fix_part = fx.fix_part;
     fa.iter_out = c->at<double>(c->p.iter) + 2 * t;
-    HIPCHK(launch_final(fa, c->stream));
-    HIPCHK(c->mark());
-    vegas_status s = run_update(c, t, lds_hist ? c->n_wg : 1, true);
-    if (s != VEGAS_OK) return s;
+    const int n_slots = lds_hist ? c->n_wg : 1;
+    if (c->fused) {
+        // small problem: fix-up, estimate and map in one launch, then the
+        // allocation (the timing puts the map into the estimate phase)
+        UpdateArgs u;
+        u.fx = fx;
+        u.fin = fa;
+        u.map = map_args(c, n_slots);
+        u.map.parts = n_slots > kHistParts ? kHistParts : 0;
+        HIPCHK(launch_update_small(u, c->stream));
+        HIPCHK(c->mark());
+        const bool adapt_strat = c->cfg.adapt_strat && c->cfg.beta > 0.0;
+        const AllocArgs aa = alloc_args(c, t, adapt_strat ? 0 : 1);
+        HIPCHK(launch_alloc(aa, c->qmax(t), c->stream));
+        c->cur = 1 - c->cur;
+        HIPCHK(c->mark());
+        HIPCHK(c->mark());
+    } else {
+        HIPCHK(launch_fixup(fx, c->stream));
+        HIPCHK(launch_final(fa, c->stream));
+        HIPCHK(c->mark());
+        const vegas_status s = run_update(c, t, n_slots, true);
+        if (s != VEGAS_OK) return s;
+    }
+    vegas_status s = VEGAS_OK;
     const bool warped = c->flow_on;
     c->n_run = t + 1;
     c->combined.push_back(integrate ? 1 : 0);
@@ -649,6 +678,9 @@ vegas_status vegas_create(const vegas_config* cfg, const vegas_integrand* f, voi
     c->ws = (unsigned char*)d_workspace;
     c->n_wg = std::max(1, std::min({cus, kMaxWG, g.n_tiles}));
     c->n_cus = std::max(1, cus);
+    // one launch for the fix-up, estimate and map where the map is cheap
+    // against a launch (few intervals); larger maps keep their own kernel
+    c->fused = cfg->accum != VEGAS_ACC_ORDERED && g.n_tiles <= 4096 && g.ng <= 512;
     c->cur = 0;
     c->max_iter = max_iter;
     c->n_run = 0;

@@ -324,6 +324,7 @@ __global__ __launch_bounds__(1024) void k_batch_map(BatchArgs a)
     m.D = in.sc.D;
     m.ng = (int)in.sc.ng;
     m.n_slots = (int)in.n_items;
+    m.parts = 0;
     m.alpha = in.adapt_map ? in.alpha : 0.0;
     m.hist_H = in.hist_H;
     m.hist_C = in.hist_C;

@@ -121,30 +121,7 @@ __global__ void k_fixup(FixupArgs a)
 __global__ __launch_bounds__(1024) void k_final(FinalArgs a)
 {
     __shared__ double rI[1024], rV[1024];
-    const int tid = threadIdx.x;
-    double sI = 0.0, sV = 0.0;
-    for (int i = tid; i < a.n_wg; i += 1024) {
-        sI += a.wg_part[2 * i];
-        sV += a.wg_part[2 * i + 1];
-    }
-    for (int i = tid; i < a.n_tiles; i += 1024) {
-        sI += a.fix_part[2 * i];
-        sV += a.fix_part[2 * i + 1];
-    }
-    rI[tid] = sI;
-    rV[tid] = sV;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (tid < w) {
-            rI[tid] += rI[tid + w];
-            rV[tid] += rV[tid + w];
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        a.iter_out[0] = rI[0] / a.n_cubes;
-        a.iter_out[1] = rV[0] / (a.n_cubes * a.n_cubes);
-    }
+    final_reduce(a, rI, rV);
 }
 
 // ---------------------------------------------------------------------------

@@ -538,6 +538,37 @@ __device__ __forceinline__ void wg_reduce_totals(double accI, double accV, doubl
 // has a tail that does not span the whole tile): merge the heads of the
 // following tiles in tile order until the cube ends.  Writes v of the cube
 // and returns (mean, v/n) in out[0..1]; zeros for tiles that own none.
+// iteration estimate: fixed-order sum of the workgroup and fix-up partials
+// (per thread strided, then a tree over the 1024 threads); rI, rV hold 1024
+// doubles each; called by 1024 threads
+__device__ __forceinline__ void final_reduce(const FinalArgs& a, double* rI, double* rV)
+{
+    const int tid = threadIdx.x;
+    double sI = 0.0, sV = 0.0;
+    for (int i = tid; i < a.n_wg; i += 1024) {
+        sI += a.wg_part[2 * i];
+        sV += a.wg_part[2 * i + 1];
+    }
+    for (int i = tid; i < a.n_tiles; i += 1024) {
+        sI += a.fix_part[2 * i];
+        sV += a.fix_part[2 * i + 1];
+    }
+    rI[tid] = sI;
+    rV[tid] = sV;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (tid < w) {
+            rI[tid] += rI[tid + w];
+            rV[tid] += rV[tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        a.iter_out[0] = rI[0] / a.n_cubes;
+        a.iter_out[1] = rV[0] / (a.n_cubes * a.n_cubes);
+    }
+}
+
 __device__ __forceinline__ void fixup_chain(const TileSide* side, int n_tiles, int j, double* v_out,
                                             unsigned long long* vmax, double* out)
 {

@@ -66,6 +66,7 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t st);
 hipError_t launch_ordered(const OrderedArgs& a, hipStream_t st);
 hipError_t launch_alloc(const AllocArgs& a, unsigned long long* qmax_bits, hipStream_t st);
 hipError_t launch_map_update(const MapArgs& a, hipStream_t st);
+hipError_t launch_update_small(const UpdateArgs& u, hipStream_t st);
 hipError_t launch_hist_reduce(const HistReduceArgs& a, hipStream_t st);
 hipError_t launch_reset(unsigned long long* p, int n, hipStream_t st);
 hipError_t launch_grid32(const double* g64, float* g32, int n, hipStream_t st);

@@ -121,6 +121,10 @@ struct MapArgs {
     int32_t D;
     int32_t ng;
     int32_t n_slots;            // partial histograms to add, in order
+    int32_t parts;              // 0: add the slots in order; > 0: in `parts`
+                                // consecutive groups, each in order, then the
+                                // groups in order (what k_hist_reduce followed
+                                // by a map over its groups adds)
     double alpha;
     const double* hist_H;       // [n_slots][D*N_g]
     const uint32_t* hist_C;
@@ -128,6 +132,16 @@ struct MapArgs {
     float* grid32;              // [D][N_g+1] out (FP32 copy)
     double* Hsum;               // [D][N_g] reduced histogram (kept for inspection; may be null)
     double* Csum;
+};
+
+// The cube fix-up, the iteration estimate and the map refinement of a small
+// problem (few tiles, few histogram slots) in one launch of D + 1
+// workgroups: workgroup d < D refines axis d, workgroup D runs the fix-up and
+// then the estimate.
+struct UpdateArgs {
+    FixupArgs fx;
+    FinalArgs fin;
+    MapArgs map;
 };
 
 // ---------------------------------------------------------------------------

@@ -22,6 +22,7 @@
 
 #include "common.hpp"
 #include "families.hpp"
+#include "fill_dev.hpp"
 #include "launch.hpp"
 #include "update_dev.hpp"
 
@@ -148,6 +149,46 @@ hipError_t launch_map_update(const MapArgs& a, hipStream_t st)
     const size_t lds = (size_t)3 * (a.ng + 1) * sizeof(double);
     hipFuncSetAttribute((const void*)k_map_update, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_map_update, dim3(a.D), dim3(1024), lds, st, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// the cube fix-up, the iteration estimate and the map refinement of a small
+// problem in one launch: workgroup d < D refines axis d; workgroup D runs the
+// fix-up and then the estimate (the same device code and order of operations
+// as the separate kernels).  The allocation follows in its own kernels,
+// whose blocks then run on as many CUs.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_update_small(UpdateArgs u)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double S_sh;
+    if ((int)blockIdx.x < u.map.D) {
+        map_update_axis(u.map, (int)blockIdx.x, smem, S_sh);
+        return;
+    }
+    const int tid = threadIdx.x;
+    for (int j = tid; j < u.fx.n_tiles; j += 1024)
+        fixup_chain(u.fx.side, u.fx.n_tiles, j, u.fx.v_out, u.fx.vmax, u.fx.fix_part + 2 * j);
+    // the fix-up's partials are read below by other lanes
+    __threadfence();
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(smem);      // 2 x 1024 doubles
+    final_reduce(u.fin, red, red + 1024);
+}
+
+size_t update_small_lds(int ng, int parts)
+{
+    const size_t map = (size_t)3 * (ng + 1) * sizeof(double) + (size_t)parts * ng * (sizeof(double) + sizeof(uint32_t));
+    const size_t red = (size_t)2 * 1024 * sizeof(double);
+    return map > red ? map : red;
+}
+
+hipError_t launch_update_small(const UpdateArgs& u, hipStream_t st)
+{
+    const size_t lds = update_small_lds(u.map.ng, u.map.parts);
+    hipFuncSetAttribute((const void*)k_update_small, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_update_small, dim3(u.map.D + 1), dim3(1024), lds, st, u);
     return hipGetLastError();
 }
 

@@ -296,14 +296,42 @@ __device__ __forceinline__ void map_update_axis(const MapArgs& a, int d, unsigne
     const int row = ng + 1;
     const int nbins = a.D * ng;
     for (int i = tid; i <= ng; i += 1024) x[i] = a.grid64[d * row + i];
+    // slot groups: one lane per (group, interval) adds its group's slots in
+    // order into LDS (after x, A, B: parts x N_g doubles, then as many u32)
+    double* Hp = B + (ng + 1);
+    uint32_t* Cp = reinterpret_cast<uint32_t*>(Hp + (size_t)a.parts * ng);
+    if (a.parts > 0) {
+        const int per = (a.n_slots + a.parts - 1) / a.parts;
+        for (int idx = tid; idx < a.parts * ng; idx += 1024) {
+            const int p = idx / ng;
+            const int bi = d * ng + (idx - p * ng);
+            const int w1 = min((p + 1) * per, a.n_slots);
+            double h = 0.0;
+            uint32_t c = 0;
+            for (int w = p * per; w < w1; ++w) {
+                h += a.hist_H[(size_t)w * nbins + bi];
+                c += a.hist_C[(size_t)w * nbins + bi];
+            }
+            Hp[idx] = h;
+            Cp[idx] = c;
+        }
+        __syncthreads();
+    }
     int any = 0;
     for (int i = tid; i < ng; i += 1024) {
         double H = 0.0;
         uint64_t C = 0;
         const int bi = d * ng + i;
-        for (int w = 0; w < a.n_slots; ++w) {
-            H += a.hist_H[(size_t)w * nbins + bi];
-            C += a.hist_C[(size_t)w * nbins + bi];
+        if (a.parts > 0) {
+            for (int p = 0; p < a.parts; ++p) {
+                H += Hp[p * ng + i];
+                C += Cp[p * ng + i];
+            }
+        } else {
+            for (int w = 0; w < a.n_slots; ++w) {
+                H += a.hist_H[(size_t)w * nbins + bi];
+                C += a.hist_C[(size_t)w * nbins + bi];
+            }
         }
         if (a.Hsum) {
             a.Hsum[bi] = H;
