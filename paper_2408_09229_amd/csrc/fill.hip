@@ -110,9 +110,11 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs a)
 // ---------------------------------------------------------------------------
 __global__ void k_fixup(FixupArgs a)
 {
+    // one maximum per wavefront: the lanes' atomics on one address would
+    // queue one behind another
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= a.n_tiles) return;
-    fixup_chain(a.side, a.n_tiles, j, a.v_out, a.vmax, a.fix_part + 2 * j);
+    const unsigned long long vb = j < a.n_tiles ? fixup_chain_v(a.side, a.n_tiles, j, a.v_out, a.fix_part + 2 * j) : 0ull;
+    wave_atomic_max(vb, a.vmax);
 }
 
 // ---------------------------------------------------------------------------

@@ -569,10 +569,15 @@ __device__ __forceinline__ void final_reduce(const FinalArgs& a, double* rI, dou
     }
 }
 
-__device__ __forceinline__ void fixup_chain(const TileSide* side, int n_tiles, int j, double* v_out,
-                                            unsigned long long* vmax, double* out)
+// Tile j's tail run merged with the heads of the tiles it reaches into; the
+// finished cube's variance goes to v_out and its partials to out[0..1].
+// Returns the variance's bit pattern for the maximum (0 when tile j
+// finishes no cube).
+__device__ __forceinline__ unsigned long long fixup_chain_v(const TileSide* side, int n_tiles, int j, double* v_out,
+                                                            double* out)
 {
     double mI = 0.0, mV = 0.0;
+    unsigned long long vb = 0ull;
     const uint32_t f = side[j].flags;
     if ((f & kHasTail) && !(f & kSpan)) {
         Partial cur = side[j].tail;
@@ -587,10 +592,30 @@ __device__ __forceinline__ void fixup_chain(const TileSide* side, int n_tiles, i
         v_out[cur.h] = v;
         mI = cur.mean;
         mV = v / (double)cur.n;
-        atomicMax(vmax, (unsigned long long)__double_as_longlong(v));
+        vb = (unsigned long long)__double_as_longlong(v);
     }
     out[0] = mI;
     out[1] = mV;
+    return vb;
+}
+
+__device__ __forceinline__ void fixup_chain(const TileSide* side, int n_tiles, int j, double* v_out,
+                                            unsigned long long* vmax, double* out)
+{
+    const unsigned long long vb = fixup_chain_v(side, n_tiles, j, v_out, out);
+    if (vb) atomicMax(vmax, vb);
+}
+
+// the largest of the wavefront's bit patterns into *p with one atomic (the
+// same maximum as one atomicMax per lane); all 64 lanes call it
+__device__ __forceinline__ void wave_atomic_max(unsigned long long b, unsigned long long* p)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(b, o, 64);
+        b = y > b ? y : b;
+    }
+    if ((threadIdx.x & 63) == 0 && b) atomicMax(p, b);
 }
 
 }  // namespace vg

@@ -168,8 +168,12 @@ __global__ __launch_bounds__(1024) void k_update_small(UpdateArgs u)
         return;
     }
     const int tid = threadIdx.x;
-    for (int j = tid; j < u.fx.n_tiles; j += 1024)
-        fixup_chain(u.fx.side, u.fx.n_tiles, j, u.fx.v_out, u.fx.vmax, u.fx.fix_part + 2 * j);
+    unsigned long long vb = 0ull;
+    for (int j = tid; j < u.fx.n_tiles; j += 1024) {
+        const unsigned long long b = fixup_chain_v(u.fx.side, u.fx.n_tiles, j, u.fx.v_out, u.fx.fix_part + 2 * j);
+        vb = b > vb ? b : vb;
+    }
+    wave_atomic_max(vb, u.fx.vmax);
     // the fix-up's partials are read below by other lanes
     __threadfence();
     __syncthreads();
