@@ -538,6 +538,8 @@ __device__ __forceinline__ void wg_reduce_totals(double accI, double accV, doubl
 // has a tail that does not span the whole tile): merge the heads of the
 // following tiles in tile order until the cube ends.  Writes v of the cube
 // and returns (mean, v/n) in out[0..1]; zeros for tiles that own none.
+constexpr int kFixAhead = 8;            // side records in flight in the fix-up
+
 // iteration estimate: fixed-order sum of the workgroup and fix-up partials
 // (per thread strided, then a tree over the 1024 threads); rI, rV hold 1024
 // doubles each; called by 1024 threads
@@ -581,12 +583,29 @@ __device__ __forceinline__ unsigned long long fixup_chain_v(const TileSide* side
     const uint32_t f = side[j].flags;
     if ((f & kHasTail) && !(f & kSpan)) {
         Partial cur = side[j].tail;
+        // the heads of the following tiles, merged in tile order up to the
+        // first tile the cube does not span; their loads go out kFixAhead at
+        // a time, since a cube can span many tiles
         int m = j + 1;
-        while (m < n_tiles) {
-            const TileSide& ts = side[m];
-            cur = merge(cur, ts.head);
-            if (!(ts.flags & kSpan)) break;
-            ++m;
+        bool open = true;
+        while (open && m < n_tiles) {
+            Partial hd[kFixAhead];
+            uint32_t fl[kFixAhead];
+#pragma unroll
+            for (int q = 0; q < kFixAhead; ++q) {
+                if (m + q < n_tiles) {
+                    hd[q] = side[m + q].head;
+                    fl[q] = side[m + q].flags;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kFixAhead; ++q) {
+                if (open && m + q < n_tiles) {
+                    cur = merge(cur, hd[q]);
+                    if (!(fl[q] & kSpan)) open = false;
+                }
+            }
+            m += kFixAhead;
         }
         const double v = unbiased_var(cur);
         v_out[cur.h] = v;

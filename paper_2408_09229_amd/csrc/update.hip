@@ -174,8 +174,9 @@ __global__ __launch_bounds__(1024) void k_update_small(UpdateArgs u)
         vb = b > vb ? b : vb;
     }
     wave_atomic_max(vb, u.fx.vmax);
-    // the fix-up's partials are read below by other lanes
-    __threadfence();
+    // the fix-up's partials are read below by other lanes of this workgroup:
+    // the barrier's workgroup-scope release and acquire order them (a
+    // device-scope fence here would write back the whole L2)
     __syncthreads();
     double* red = reinterpret_cast<double*>(smem);      // 2 x 1024 doubles
     final_reduce(u.fin, red, red + 1024);

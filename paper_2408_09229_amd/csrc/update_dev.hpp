@@ -308,7 +308,18 @@ __device__ __forceinline__ void map_update_axis(const MapArgs& a, int d, unsigne
             const int w1 = min((p + 1) * per, a.n_slots);
             double h = 0.0;
             uint32_t c = 0;
-            for (int w = p * per; w < w1; ++w) {
+            int w = p * per;
+            // four loads in flight, the adds in slot order
+            for (; w + 4 <= w1; w += 4) {
+                const double h0 = a.hist_H[(size_t)w * nbins + bi];
+                const double h1 = a.hist_H[(size_t)(w + 1) * nbins + bi];
+                const double h2 = a.hist_H[(size_t)(w + 2) * nbins + bi];
+                const double h3 = a.hist_H[(size_t)(w + 3) * nbins + bi];
+                c += a.hist_C[(size_t)w * nbins + bi] + a.hist_C[(size_t)(w + 1) * nbins + bi] +
+                     a.hist_C[(size_t)(w + 2) * nbins + bi] + a.hist_C[(size_t)(w + 3) * nbins + bi];
+                h = (((h + h0) + h1) + h2) + h3;
+            }
+            for (; w < w1; ++w) {
                 h += a.hist_H[(size_t)w * nbins + bi];
                 c += a.hist_C[(size_t)w * nbins + bi];
             }
