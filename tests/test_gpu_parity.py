@@ -126,6 +126,11 @@ def test_iteration_fp64_parity(orc, V, w):
         assert np.allclose(H, o.H, rtol=1e-12, atol=1e-300)
         scale = max(o.v.max(), 1e-300)
         assert np.allclose(vv, o.v, rtol=1e-10, atol=1e-12 * scale)
+        # the GPU's own update of this iteration (for these sizes the fix-up,
+        # estimate and map run in one launch), bit-exact against the oracle
+        # applied to the GPU's accumulators
+        assert np.array_equal(v.get_map(), orc.map_update(grid, H, Cn, w.alpha))
+        assert np.array_equal(v.get_nh(), orc.alloc(vv, w.n_min, w.n_eval, w.beta))
         # the oracle's own next state
         nh = orc.alloc(o.v, w.n_min, w.n_eval, w.beta)
         grid = orc.map_update(grid, o.H, o.C, w.alpha)
