@@ -297,7 +297,8 @@ def main():
     ap.add_argument("--cpu-evals", type=float, default=1.5e7)
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--issue-rates", action="store_true",
-                    help="only measure VALU issue rates of the instruction kinds the path uses")
+                    help="only measure the issue rates of the VALU instruction kinds the path uses and the "
+                         "LDS atomic add rates")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for scaling HBM counters)")
     ap.add_argument("--tune-cache", default="", help="autotuner cache of the batched workload")
@@ -319,7 +320,14 @@ def main():
         torch.cuda.set_device(0)
         assert lib.vegas_issue_rates(out, 6, ctypes.c_double(2.4), 1024) == 0
         names = ["fma_f32", "mul+exp2_f32", "mad_u64_u32+xor", "fma_f64", "bitop3", "add_f64+rcp_f64"]
-        print(json.dumps({n: round(v, 3) for n, v in zip(names, out)}))
+        rates = {n: round(v, 3) for n, v in zip(names, out)}
+        lds = (ctypes.c_double * 6)()
+        assert lib.vegas_lds_atomic_rates(lds, ctypes.c_double(2.4), 256) == 0
+        lnames = ["ds_add_u32", "ds_add_f32", "ds_add_f64"]
+        rates["lds_atomic_adds_per_cu_cycle"] = {
+            "conflict_free": {n: round(lds[i], 2) for i, n in enumerate(lnames)},
+            "random_1024": {n: round(lds[3 + i], 2) for i, n in enumerate(lnames)}}
+        print(json.dumps(rates))
         return
 
     import vegas_inputs as vi

@@ -41,7 +41,76 @@ __global__ __launch_bounds__(kBlock) void k_issue(float* out, int iters)
     out[blockIdx.x * kBlock + threadIdx.x] = s;
 }
 
+// LDS atomic adds without return: every lane adds `iters` times into
+// workgroup memory.  PATTERN 0: lane l of wave w always hits word (or
+// double) 64 w + l, no bank conflicts; PATTERN 1: each add goes to one of
+// 1024 entries drawn by a per-lane linear congruential sequence, the way
+// the fill's histogram adds land.  All indexes stay inside the arrays.
+template <int OP, int PATTERN>
+__global__ __launch_bounds__(kBlock) void k_lds_atomic(float* out, int iters)
+{
+    __shared__ uint32_t su[1024];
+    __shared__ float sf[1024];
+    __shared__ double sd[1024];
+    for (int i = threadIdx.x; i < 1024; i += kBlock) {
+        su[i] = 0u;
+        sf[i] = 0.f;
+        sd[i] = 0.0;
+    }
+    __syncthreads();
+    uint32_t x = blockIdx.x * 7919u + threadIdx.x * 104729u + 1u;
+    const int fixed = threadIdx.x & (kBlock - 1);        // 64 w + l, < 256
+    for (int it = 0; it < iters; ++it) {
+        int idx = fixed;
+        if (PATTERN == 1) {
+            x = x * 1664525u + 1013904223u;
+            idx = (int)((x >> 16) & 1023u);
+        }
+        if (OP == 0) atomicAdd(&su[idx], 1u);
+        if (OP == 1) unsafeAtomicAdd(&sf[idx], 1.0f);
+        if (OP == 2) unsafeAtomicAdd(&sd[idx], 1.0);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = (float)su[0] + sf[0] + (float)sd[0];
+}
+
 }  // namespace
+
+// out[6 * pattern + op] = LDS atomic adds retired per cycle per CU, op 0 u32,
+// 1 f32, 2 f64; pattern 0 without bank conflicts, 1 to random entries of a
+// 1024-entry table (six values).  Returns 0 on success, -3 on a HIP error.
+extern "C" int vegas_lds_atomic_rates(double* out, double clock_ghz, int n_cu)
+{
+    const int blocks = 4096, iters = 4096;
+    float* buf = nullptr;
+    if (hipMalloc(&buf, sizeof(float) * blocks) != hipSuccess) return -3;
+    hipEvent_t a, b;
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    for (int k = 0; k < 6; ++k) {
+        float ms = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {
+            hipEventRecord(a);
+            switch (k) {
+            case 0: hipLaunchKernelGGL((k_lds_atomic<0, 0>), dim3(blocks), dim3(kBlock), 0, 0, buf, iters); break;
+            case 1: hipLaunchKernelGGL((k_lds_atomic<1, 0>), dim3(blocks), dim3(kBlock), 0, 0, buf, iters); break;
+            case 2: hipLaunchKernelGGL((k_lds_atomic<2, 0>), dim3(blocks), dim3(kBlock), 0, 0, buf, iters); break;
+            case 3: hipLaunchKernelGGL((k_lds_atomic<0, 1>), dim3(blocks), dim3(kBlock), 0, 0, buf, iters); break;
+            case 4: hipLaunchKernelGGL((k_lds_atomic<1, 1>), dim3(blocks), dim3(kBlock), 0, 0, buf, iters); break;
+            case 5: hipLaunchKernelGGL((k_lds_atomic<2, 1>), dim3(blocks), dim3(kBlock), 0, 0, buf, iters); break;
+            }
+            hipEventRecord(b);
+            hipEventSynchronize(b);
+        }
+        hipEventElapsedTime(&ms, a, b);
+        const double adds = (double)blocks * kBlock * iters;
+        out[k] = adds / (ms * 1e-3 * clock_ghz * 1e9 * n_cu);
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    hipFree(buf);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
 
 // out[op] = wave64 instructions retired per 4 cycles per SIMD for op kind
 // 0 fma_f32, 1 mul+exp2_f32, 2 mad_u64_u32+xor, 3 fma_f64, 4 bitop3,
