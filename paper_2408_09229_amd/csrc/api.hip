@@ -154,8 +154,9 @@ vegas_status geometry(const vegas_config* c, const vegas_integrand* f, Geometry*
     g->n_tiles = (int)((ne + g->tile - 1) / g->tile);
     const bool fp64 = c->precision == VEGAS_PREC_FP64;
     g->n_aux = std::max(f->family == VEGAS_GAUSS_DIAG ? (int)f->params[2] : 2 * g->D, 1);
-    g->lds_hist_ok = fill_lds_bytes(g->D, g->ng, fp64, 1, g->tile, g->n_aux) <= kLdsLimit;
-    if (!g->lds_hist_ok && fill_lds_bytes(g->D, g->ng, fp64, 0, g->tile, g->n_aux) > kLdsLimit)
+    // sized for the warped fill, which keeps the map in LDS as well
+    g->lds_hist_ok = fill_lds_bytes(g->D, g->ng, fp64, 1, g->tile, g->n_aux, 1) <= kLdsLimit;
+    if (!g->lds_hist_ok && fill_lds_bytes(g->D, g->ng, fp64, 0, g->tile, g->n_aux, 1) > kLdsLimit)
         return fail(VEGAS_EUNSUPPORTED, "map of %d x %d intervals does not fit in LDS", g->D, g->ng);
     if ((size_t)3 * (g->ng + 1) * 8 > kLdsLimit) return fail(VEGAS_EUNSUPPORTED, "n_intervals too large for the map update");
     return VEGAS_OK;
@@ -450,7 +451,8 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
         HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histC), (nb + 1) / 2, c->stream));
     }
     const FillArgs a = fill_args(c, t, c->nonfinite());
-    const size_t lds = fill_lds_bytes(c->g.D, c->g.ng, fp64, lds_hist, c->g.tile, c->g.n_aux);
+    // the warped fill keeps the map in LDS; k_fill reads it through the cache
+    const size_t lds = fill_lds_bytes(c->g.D, c->g.ng, fp64, lds_hist, c->g.tile, c->g.n_aux, c->flow_on ? 1 : 0);
     HIPCHK(c->mark());
     if (c->flow_on) {
         // the warp: y -> w = F(y) for every sample, then the fill on w
@@ -611,7 +613,7 @@ vegas_status ctx_fill_pass(vegas_ctx* c)
     // non-finite weights of this pass go to a spare counter, so the
     // iteration's own count is not touched
     const FillArgs a = fill_args(c, t, c->nonfinite() + 1);
-    const size_t lds = fill_lds_bytes(c->g.D, c->g.ng, fp64, lds_hist, c->g.tile, c->g.n_aux);
+    const size_t lds = fill_lds_bytes(c->g.D, c->g.ng, fp64, lds_hist, c->g.tile, c->g.n_aux, 0);
     HIPCHK(launch_fill(a, fp64, c->n_wg, lds, c->stream));
     return VEGAS_OK;
 }

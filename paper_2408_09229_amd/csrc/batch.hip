@@ -101,7 +101,7 @@ __device__ __noinline__ void batch_item(ItemCall c0, unsigned char* smem)
     const int ng = (int)sc.ng;
     const int tid = threadIdx.x;
     const int tile_sz = uni(in.tile);
-    const LdsPlan lp = lds_plan(D, ng, (int)sizeof(R), 1, tile_sz, sc.n_aux);
+    const LdsPlan lp = lds_plan(D, ng, (int)sizeof(R), 1, tile_sz, sc.n_aux, 1);
     const FillLds<R> L(smem, lp);
     const int nbins = D * ng;
     const R* gsrc = std::is_same<R, double>::value ? reinterpret_cast<const R*>(uni(in.grid64))
@@ -121,6 +121,7 @@ __device__ __noinline__ void batch_item(ItemCall c0, unsigned char* smem)
     double vmax = 0.0;
     unsigned long long bad = 0;
     TileIO io;
+    io.grid = nullptr;
     io.t = c.t;
     io.tile = tile_sz;
     io.per_lane = uni(in.per_lane);

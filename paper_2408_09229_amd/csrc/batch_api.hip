@@ -188,7 +188,7 @@ vegas_status batch_geometry(int32_t n, const vegas_config* cfgs, const vegas_int
         if (c.dim > kBatchMaxDim) return fail(VEGAS_EUNSUPPORTED, "problem %d: batched problems have dim <= %d", i, kBatchMaxDim);
         const bool fp64 = c.precision == VEGAS_PREC_FP64;
         const int tile_max = kFillThreads * 8;
-        if (fill_lds_bytes(gs[i].D, gs[i].ng, fp64, 1, tile_max, gs[i].n_aux) > kLdsLimit)
+        if (fill_lds_bytes(gs[i].D, gs[i].ng, fp64, 1, tile_max, gs[i].n_aux, 1) > kLdsLimit)
             return fail(VEGAS_EUNSUPPORTED, "problem %d: map and histograms of %d x %d intervals exceed LDS", i,
                         gs[i].D, gs[i].ng);
         mi = std::max(mi, c.max_iter);
@@ -386,7 +386,7 @@ vegas_status apply_layout(vegas_batch* b, const Layout& L)
         item0 += il.n_items;
         tile0 += il.n_tiles;
         blk0 += il.n_blk;
-        lds = std::max(lds, fill_lds_bytes(g.D, g.ng, b->fp64, 1, il.tile, g.n_aux));
+        lds = std::max(lds, fill_lds_bytes(g.D, g.ng, b->fp64, 1, il.tile, g.n_aux, 1));
     }
     // queue order: longest first; ties by item index, so the order is fixed
     std::vector<uint32_t> order(p.n_items);
@@ -1045,7 +1045,7 @@ vegas_status vegas_batch_get_info(const vegas_batch* b, vegas_batch_info* out)
             wg += ci.n_workgroups;
             ne += g.n_eval;
             nc += g.n_cubes;
-            lds = std::max(lds, fill_lds_bytes(g.D, g.ng, b->fp64, ci.lds_hist, g.tile, g.n_aux));
+            lds = std::max(lds, fill_lds_bytes(g.D, g.ng, b->fp64, ci.lds_hist, g.tile, g.n_aux, 0));
         }
         out->n_tiles = tiles;
         out->n_workgroups = wg;

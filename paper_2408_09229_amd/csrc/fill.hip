@@ -44,12 +44,10 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs a)
     const int D = sc.D;
     const uint32_t ng = sc.ng;
     const int tid = threadIdx.x;
-    const LdsPlan lp = lds_plan(D, (int)ng, (int)sizeof(R), a.lds_hist, a.tile, sc.n_aux);
+    const LdsPlan lp = lds_plan(D, (int)ng, (int)sizeof(R), a.lds_hist, a.tile, sc.n_aux, 0);
     const FillLds<R> L(smem, lp);
 
     const int nbins = D * (int)ng;
-    const R* gsrc = reinterpret_cast<const R*>(a.grid);
-    for (int i = tid; i < D * (int)(ng + 1); i += kFillThreads) L.gl[i] = gsrc[i];
     {
         const R* asrc = std::is_same<R, double>::value ? reinterpret_cast<const R*>(sc.aux_d)
                                                        : reinterpret_cast<const R*>(sc.aux_f);
@@ -77,6 +75,7 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs a)
     io.side = a.side;
     io.hist_H = a.hist_H;
     io.hist_C = a.hist_C;
+    io.grid = a.grid;
 
     __syncthreads();
 
@@ -260,9 +259,9 @@ hipError_t launch_final(const FinalArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
-size_t fill_lds_bytes(int D, int ng, bool fp64, int lds_hist, int tile, int n_aux)
+size_t fill_lds_bytes(int D, int ng, bool fp64, int lds_hist, int tile, int n_aux, int map_lds)
 {
-    return lds_plan(D, ng, fp64 ? 8 : 4, lds_hist, tile, n_aux).total;
+    return lds_plan(D, ng, fp64 ? 8 : 4, lds_hist, tile, n_aux, map_lds).total;
 }
 
 }  // namespace vg

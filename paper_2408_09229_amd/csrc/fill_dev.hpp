@@ -200,16 +200,20 @@ struct LdsPlan {
     uint32_t grid_off, aux_off, h_off, c_off, st_off, wave_off, cin_off, side_off, red_off, total;
 };
 
-// LDS: map [D][N_g+1] in the sample path's precision; histogram weights
-// [D][N_g] in FP64 (the FP32 LDS atomic add is an order of magnitude slower
-// than the FP64 one on gfx950) and u32 counts; the tile's cube starts;
-// per-wave carry records; the tile's side record; a reduction area.
-__host__ __device__ inline LdsPlan lds_plan(int D, int ng, int real_bytes, int lds_hist, int tile, int n_aux)
+// LDS: map [D][N_g+1] in the sample path's precision (map_lds = 1; the
+// plain fill reads the map through the vector cache instead, whose loads do
+// not queue behind the histogram atomics in the LDS pipe); histogram weights
+// [D][N_g] in FP64 (the FP32 LDS atomic add is about 25 times slower than the
+// FP64 one on gfx950) and u32 counts; the tile's cube starts; per-wave carry
+// records; the tile's side record; a reduction area.
+__host__ __device__ inline LdsPlan lds_plan(int D, int ng, int real_bytes, int lds_hist, int tile, int n_aux,
+                                            int map_lds)
 {
     LdsPlan p;
     uint32_t o = 0;
     auto al = [](uint32_t v) { return (v + 15u) & ~15u; };
-    p.grid_off = o; o = al(o + (uint32_t)(D * (ng + 1) * real_bytes));
+    p.grid_off = o;
+    if (map_lds) o = al(o + (uint32_t)(D * (ng + 1) * real_bytes));
     p.aux_off = o; o = al(o + (uint32_t)(n_aux * real_bytes));
     p.h_off = o;
     if (lds_hist) o = al(o + (uint32_t)(D * ng * 8));
@@ -236,6 +240,7 @@ struct TileIO {
     TileSide* side;               // [n_tiles]
     double* hist_H;               // global histogram (when not in LDS)
     uint32_t* hist_C;
+    const void* grid;             // the map in global memory (null: read the LDS copy)
 };
 
 // LDS views of the fill (see lds_plan).
@@ -287,6 +292,7 @@ __device__ __forceinline__ void fill_tile(int tile, const TileIO& io, const Fill
     const int wave = tid >> 6;
     const int S = io.per_lane;
     R* gl = L.gl;
+    const R* gmap = io.grid ? reinterpret_cast<const R*>(io.grid) : gl;
     double* hl = L.hl;
     uint32_t* cl = L.cl;
     uint32_t* st = L.st;
@@ -356,7 +362,7 @@ __device__ __forceinline__ void fill_tile(int tile, const TileIO& io, const Fill
                 }
                 uint32_t bins[MAXD];
                 R J, f;
-                R w = sp.template eval<false>(k, io.t, s, gl, bins, nullptr, nullptr, J, f);
+                R w = sp.template eval<false>(k, io.t, s, gmap, bins, nullptr, nullptr, J, f);
                 if (!__builtin_isfinite(w)) {
                     w = (R)0;
                     ++bad;

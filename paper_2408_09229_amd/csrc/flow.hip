@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kFillThreads) void k_fill_flow(FillArgs a, const fl
     const int D = sc.D;
     const uint32_t ng = sc.ng;
     const int tid = threadIdx.x;
-    const LdsPlan lp = lds_plan(D, (int)ng, 4, a.lds_hist, a.tile, sc.n_aux);
+    const LdsPlan lp = lds_plan(D, (int)ng, 4, a.lds_hist, a.tile, sc.n_aux, 1);
     const FillLds<float> L(smem, lp);
     const int nbins = D * (int)ng;
     const float* gsrc = reinterpret_cast<const float*>(a.grid);
@@ -262,6 +262,7 @@ __global__ __launch_bounds__(kFillThreads) void k_fill_flow(FillArgs a, const fl
     double vmax = 0.0;
     unsigned long long bad = 0;
     TileIO io;
+    io.grid = nullptr;
     io.t = a.t;
     io.tile = a.tile;
     io.per_lane = a.per_lane;

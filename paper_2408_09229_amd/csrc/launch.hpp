@@ -60,7 +60,9 @@ hipError_t launch_fill(const FillArgs& a, bool fp64, int n_wg, size_t lds, hipSt
 hipError_t launch_fixup(const FixupArgs& a, hipStream_t st);
 hipError_t launch_final(const FinalArgs& a, hipStream_t st);
 hipError_t launch_probe(const ProbeArgs& a, bool fp64, hipStream_t st);
-size_t fill_lds_bytes(int D, int ng, bool fp64, int lds_hist, int tile, int n_aux);
+// LDS bytes of a fill launch; map_lds = 1 for the kernels that keep the map
+// in LDS (the warped fill, the persistent batch), 0 for k_fill
+size_t fill_lds_bytes(int D, int ng, bool fp64, int lds_hist, int tile, int n_aux, int map_lds);
 
 hipError_t launch_prep(const PrepArgs& a, hipStream_t st);
 hipError_t launch_ordered(const OrderedArgs& a, hipStream_t st);
