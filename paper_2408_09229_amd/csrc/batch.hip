@@ -133,7 +133,7 @@ __device__ __noinline__ void batch_item(ItemCall c0, unsigned char* smem)
     io.hist_H = nullptr;
     io.hist_C = nullptr;
     for (uint32_t j = 0; j < c.n_tiles; ++j)
-        fill_tile<R, MAXD, KAHAN>((int)(c.tile0 + j), io, L, sp, totI, totV, vmax, bad);
+        fill_tile<R, MAXD, KAHAN, false>((int)(c.tile0 + j), io, L, sp, totI, totV, vmax, bad);
 
     // histograms into the item's slot
     const size_t slot = (size_t)(c.it - uni(in.item0)) * (size_t)nbins;

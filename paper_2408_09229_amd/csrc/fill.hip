@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs a)
     __syncthreads();
 
     for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x)
-        fill_tile<R, MAXD, KAHAN>(tile, io, L, sp, totI, totV, vmax, bad);
+        fill_tile<R, MAXD, KAHAN, true>(tile, io, L, sp, totI, totV, vmax, bad);
 
     if (a.lds_hist) {
         // this workgroup's histograms into its slot (reduced in slot order by

@@ -279,7 +279,19 @@ struct FillLds {
 // workgroup; ends with a barrier.
 // Path: the per-sample path (SamplePath, or the warped path of the learned
 // warp), with digits / next_digits / eval and the problem constants sc.
-template <typename R, int MAXD, bool KAHAN, typename Path>
+// The map a tile reads: GMAP reads it from global memory through the vector
+// cache (typed as a global pointer, so its loads are waited on by the vector
+// counter alone and never by the LDS atomics in flight); otherwise the copy
+// in LDS.
+template <bool GMAP, typename R>
+__device__ __forceinline__ auto tile_map(const TileIO& io, const R* gl)
+{
+    typedef const __attribute__((address_space(1))) R GlobalR;
+    if constexpr (GMAP) return (GlobalR*)(io.grid);
+    else return gl;
+}
+
+template <typename R, int MAXD, bool KAHAN, bool GMAP, typename Path>
 __device__ __forceinline__ void fill_tile(int tile, const TileIO& io, const FillLds<R>& L, Path& sp,
                                           LaneTotal<KAHAN>& totI, LaneTotal<KAHAN>& totV, double& vmax,
                                           unsigned long long& bad)
@@ -292,7 +304,7 @@ __device__ __forceinline__ void fill_tile(int tile, const TileIO& io, const Fill
     const int wave = tid >> 6;
     const int S = io.per_lane;
     R* gl = L.gl;
-    const R* gmap = io.grid ? reinterpret_cast<const R*>(io.grid) : gl;
+    const auto gmap = tile_map<GMAP>(io, gl);
     double* hl = L.hl;
     uint32_t* cl = L.cl;
     uint32_t* st = L.st;

@@ -275,7 +275,7 @@ __global__ __launch_bounds__(kFillThreads) void k_fill_flow(FillArgs a, const fl
     io.hist_C = a.hist_C;
     __syncthreads();
     for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x)
-        fill_tile<float, kFlowDim, KAHAN>(tile, io, L, sp, totI, totV, vmax, bad);
+        fill_tile<float, kFlowDim, KAHAN, false>(tile, io, L, sp, totI, totV, vmax, bad);
     if (a.lds_hist) {
         double* slotH = a.hist_H + (size_t)blockIdx.x * nbins;
         uint32_t* slotC = a.hist_C + (size_t)blockIdx.x * nbins;

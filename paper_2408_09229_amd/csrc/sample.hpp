@@ -74,9 +74,9 @@ struct SamplePath {
     // Evaluate sample k (iteration t) of the cube with digits s against the
     // grid g (row stride N_g+1).  Returns w = J f; bins and (optionally)
     // delta / x / J / f are reported through the out-parameters.
-    template <bool PROBE>
+    template <bool PROBE, typename GP>
     __device__ __forceinline__ R eval(uint32_t k, uint32_t t, const uint32_t (&s)[MAXD],
-                                      const R* __restrict__ g, uint32_t (&bins)[MAXD],
+                                      GP __restrict__ g, uint32_t (&bins)[MAXD],
                                       R* delta_out, R* x_out, R& J, R& f)
     {
         uint32_t wd[MAXD];
@@ -89,25 +89,33 @@ struct SamplePath {
                     if (4 * b + q < MAXD) wd[4 * b + q] = o.v[q];
             }
         }
-        J = (R)1;
-        fn.begin();
+        // every axis's bin and map interval first, so that the map loads are
+        // all in flight before the first of them is used
         const uint32_t row = sc.ng + 1u;
+        R lo[MAXD], hi[MAXD], dl[MAXD];
 #pragma unroll
         for (int d = 0; d < MAXD; ++d) {
             if (has(d)) {
                 const BinSplit p = bin_split(s[d], wd[d], sc.ng, sc.nst, sc.nst_magic, sc.nst_shift);
                 bins[d] = p.bin;
-                R delta;
-                if constexpr (std::is_same<R, double>::value) delta = delta_f64(p, nst2_d);
-                else delta = delta_f32(p, half_inv_nst_f);
-                const R* gd = g + d * row;
-                const R xl = gd[p.bin];
-                const R dx = gd[p.bin + 1] - xl;
-                const R x = fma(dx, delta, xl);
+                if constexpr (std::is_same<R, double>::value) dl[d] = delta_f64(p, nst2_d);
+                else dl[d] = delta_f32(p, half_inv_nst_f);
+                const auto gd = g + d * row;
+                lo[d] = gd[p.bin];
+                hi[d] = gd[p.bin + 1];
+            }
+        }
+        J = (R)1;
+        fn.begin();
+#pragma unroll
+        for (int d = 0; d < MAXD; ++d) {
+            if (has(d)) {
+                const R dx = hi[d] - lo[d];
+                const R x = fma(dx, dl[d], lo[d]);
                 J = J * (ngR * dx);
                 fn.axis(d, x);
                 if constexpr (PROBE) {
-                    delta_out[d] = delta;
+                    delta_out[d] = dl[d];
                     x_out[d] = x;
                 }
             }
