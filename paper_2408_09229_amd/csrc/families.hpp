@@ -38,6 +38,11 @@ struct Fn<R, F_GAUSS_DIAG> {
     int M;
     const R* cj;         // FP64: c_j; FP32: K c_j with K = sqrt(D / (2 s^2 ln 2))
     R K;
+    // FP32 with at most kRegTerms terms: K c_j held in registers, read once
+    // from global memory, so the per-sample work issues no LDS read (an LDS
+    // read would wait for the histogram atomics still in flight)
+    static constexpr int kRegTerms = 4;
+    float cr[kRegTerms];
     __device__ __forceinline__ void setup(const SampleConst& sc, const R* aux)
     {
         const double s = sc.prm[1];
@@ -53,6 +58,8 @@ struct Fn<R, F_GAUSS_DIAG> {
             const double L = 1.0 / (2.0 * s * s * kLn2);
             h = (float)L;
             K = (float)sqrt((double)sc.D * L);
+#pragma unroll
+            for (int q = 0; q < kRegTerms; ++q) cr[q] = q < M ? sc.aux_f[q] : 0.f;
         }
     }
     __device__ __forceinline__ void begin() { x0 = 0; a1 = 0; a2 = 0; }
@@ -80,10 +87,40 @@ struct Fn<R, F_GAUSS_DIAG> {
             }
             return A * exp(-S * h) * acc;
         } else {
-            // per term: difference, square, exp2, add (4 independent sums)
             const float Km = K * m;
+            if (M <= kRegTerms) {
+                // the association of the general loop below: one sum for
+                // M < 4, two pairs for M = 4
+                float e[kRegTerms];
+#pragma unroll
+                for (int q = 0; q < kRegTerms; ++q) {
+                    const float g = Km - cr[q];
+                    e[q] = q < M ? exp2_fast(-(g * g)) : 0.f;
+                }
+                const float acc = M == kRegTerms ? (e[0] + e[1]) + (e[2] + e[3]) : (e[0] + e[1]) + e[2];
+                return A * exp2_fast(-S * h) * acc;
+            }
+            // per term: difference, square, exp2, add (4 independent sums)
             float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
             int j = 0;
+            // eight terms a pass (two table reads, one wait), each sum still
+            // taking every fourth term in order
+            for (; j + 7 < M; j += 8) {
+                float e[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const float g = Km - cj[j + q];
+                    e[q] = exp2_fast(-(g * g));
+                }
+                acc0 += e[0];
+                acc1 += e[1];
+                acc2 += e[2];
+                acc3 += e[3];
+                acc0 += e[4];
+                acc1 += e[5];
+                acc2 += e[6];
+                acc3 += e[7];
+            }
             for (; j + 3 < M; j += 4) {
                 const float g0 = Km - cj[j];
                 const float g1 = Km - cj[j + 1];

@@ -364,9 +364,10 @@ __device__ __forceinline__ void fill_tile(int tile, const TileIO& io, const Fill
                         totV.add(vn);
                         vmax = v > vmax ? v : vmax;
                     }
-                    ++idx;
                     ++h;
-                    nxt = st[idx + 1];
+                    // from global memory: an LDS read here would be waited
+                    // on behind this lane's histogram atomics
+                    nxt = io.start[h + 1];
                     head = false;
                     n = 0;
                     cs.reset();

@@ -34,6 +34,11 @@ __global__ __launch_bounds__(kBlock) void k_issue(float* out, int iters)
             if (OP == 3) d[c] = fma(d[c], 0.999, 0.5);                                      // 1 op
             if (OP == 4) u[c] = __builtin_amdgcn_bitop3_b32(u[c], u[(c + 1) % kChains], 0x1234567u, 0x96);
             if (OP == 5) d[c] = __builtin_amdgcn_rcp(d[c] + 1.0);                            // add + rcp64
+            if (OP == 6) f[c] = __builtin_amdgcn_exp2f(-f[c]);                              // exp2 alone
+            if (OP == 7) {                                                                  // 2 exp2 : 6 fma
+                if (c % 4 == 0) f[c] = __builtin_amdgcn_exp2f(-f[c]);
+                else f[c] = fmaf(f[c], 0.999f, 0.5f);
+            }
         }
     }
     float s = 0.f;
@@ -114,18 +119,20 @@ extern "C" int vegas_lds_atomic_rates(double* out, double clock_ghz, int n_cu)
 
 // out[op] = wave64 instructions retired per 4 cycles per SIMD for op kind
 // 0 fma_f32, 1 mul+exp2_f32, 2 mad_u64_u32+xor, 3 fma_f64, 4 bitop3,
-// 5 add_f64+rcp_f64 (1.0 = one full-rate instruction every issue slot).
+// 5 add_f64+rcp_f64, 6 exp2_f32 alone, 7 exp2_f32 and fma_f32 on
+// independent chains, one exp2 to three fma (1.0 = one full-rate
+// instruction every issue slot).
 // Returns 0 on success, -3 on a HIP error.
 extern "C" int vegas_issue_rates(double* out, int n_ops, double clock_ghz, int n_simd)
 {
     const int blocks = 4096, iters = 2048;
-    const int per_step[6] = {1, 2, 2, 1, 1, 2};
+    const int per_step[8] = {1, 2, 2, 1, 1, 2, 1, 1};
     float* buf = nullptr;
     if (hipMalloc(&buf, sizeof(float) * blocks * kBlock) != hipSuccess) return -3;
     hipEvent_t a, b;
     hipEventCreate(&a);
     hipEventCreate(&b);
-    for (int op = 0; op < n_ops && op < 6; ++op) {
+    for (int op = 0; op < n_ops && op < 8; ++op) {
         for (int rep = 0; rep < 2; ++rep) {
             hipEventRecord(a);
             switch (op) {
@@ -135,6 +142,8 @@ extern "C" int vegas_issue_rates(double* out, int n_ops, double clock_ghz, int n
             case 3: hipLaunchKernelGGL(k_issue<3>, dim3(blocks), dim3(kBlock), 0, 0, buf, iters); break;
             case 4: hipLaunchKernelGGL(k_issue<4>, dim3(blocks), dim3(kBlock), 0, 0, buf, iters); break;
             case 5: hipLaunchKernelGGL(k_issue<5>, dim3(blocks), dim3(kBlock), 0, 0, buf, iters); break;
+            case 6: hipLaunchKernelGGL(k_issue<6>, dim3(blocks), dim3(kBlock), 0, 0, buf, iters); break;
+            case 7: hipLaunchKernelGGL(k_issue<7>, dim3(blocks), dim3(kBlock), 0, 0, buf, iters); break;
             }
             hipEventRecord(b);
             hipEventSynchronize(b);
