@@ -62,6 +62,12 @@ __device__ __forceinline__ void prep_problem(const PrepArgs& a, int tid, int nth
 __device__ __forceinline__ uint64_t floor_mul_div(uint64_t R, uint64_t C, uint64_t T, double rT)
 {
     const double est = (double)C * rT;
+    // est = R C / T within five roundings, so within 2^-18.6 of it (R C / T
+    // <= R < 2^32): a fraction at least 2^-16 away from both integers
+    // settles the floor without the 128-bit check
+    const double fl = floor(est);
+    const double fr = est - fl;
+    if (fr > 0x1p-16 && fr < 1.0 - 0x1p-16) return (uint64_t)fl;
     uint64_t m = (uint64_t)est;
     const unsigned __int128 rc = (unsigned __int128)R * C;
     unsigned __int128 mt = (unsigned __int128)m * T;
