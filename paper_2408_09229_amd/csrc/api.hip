@@ -146,17 +146,28 @@ vegas_status geometry(const vegas_config* c, const vegas_integrand* f, Geometry*
         g->magic = (uint32_t)((num + m - 1) / m);
         g->shift = l - 1;
     }
-    // samples per lane: long enough runs for large budgets, enough tiles to
-    // keep every CU busy for small ones
-    const uint64_t ne = g->n_eval;
-    g->per_lane = ne >= (uint64_t)256 * kLanesPerTile * 8 * 8 ? 8 : (ne >= (uint64_t)256 * kLanesPerTile * 4 * 2 ? 4 : 1);
-    g->tile = kLanesPerTile * g->per_lane;
-    g->n_tiles = (int)((ne + g->tile - 1) / g->tile);
     const bool fp64 = c->precision == VEGAS_PREC_FP64;
     g->n_aux = std::max(f->family == VEGAS_GAUSS_DIAG ? (int)f->params[2] : 2 * g->D, 1);
-    // sized for the warped fill, which keeps the map in LDS as well
-    g->lds_hist_ok = fill_lds_bytes(g->D, g->ng, fp64, 1, g->tile, g->n_aux, 1) <= kLdsLimit;
-    if (!g->lds_hist_ok && fill_lds_bytes(g->D, g->ng, fp64, 0, g->tile, g->n_aux, 1) > kLdsLimit)
+    // the warped fill (dimension kFlowDim only) keeps the map in LDS as well
+    const int map_lds = g->D == kFlowDim ? 1 : 0;
+    // samples per lane: long enough runs for large budgets (the tile's
+    // set-up, binary search and cross-lane scan are paid once per tile),
+    // enough tiles to keep every CU busy for small ones; 16 and 32 only
+    // where the tile's cube starts still fit in LDS beside the histograms
+    const uint64_t ne = g->n_eval;
+    auto fits = [&](int per_lane) {
+        return fill_lds_bytes(g->D, g->ng, fp64, 1, kLanesPerTile * per_lane, g->n_aux, map_lds) <= kLdsLimit;
+    };
+    g->per_lane = 1;
+    if (ne >= (uint64_t)256 * kLanesPerTile * 4 * 2) g->per_lane = 4;
+    if (ne >= (uint64_t)256 * kLanesPerTile * 8 * 8) g->per_lane = 8;
+    // longer runs only with at least 8 tiles per workgroup on 256 CUs
+    for (int pl = 16; pl * kLanesPerTile <= kMaxTile; pl *= 2)
+        if (ne >= (uint64_t)256 * kLanesPerTile * pl * 8 && fits(pl)) g->per_lane = pl;
+    g->tile = kLanesPerTile * g->per_lane;
+    g->n_tiles = (int)((ne + g->tile - 1) / g->tile);
+    g->lds_hist_ok = fill_lds_bytes(g->D, g->ng, fp64, 1, g->tile, g->n_aux, map_lds) <= kLdsLimit;
+    if (!g->lds_hist_ok && fill_lds_bytes(g->D, g->ng, fp64, 0, g->tile, g->n_aux, map_lds) > kLdsLimit)
         return fail(VEGAS_EUNSUPPORTED, "map of %d x %d intervals does not fit in LDS", g->D, g->ng);
     if ((size_t)3 * (g->ng + 1) * 8 > kLdsLimit) return fail(VEGAS_EUNSUPPORTED, "n_intervals too large for the map update");
     return VEGAS_OK;

@@ -219,7 +219,7 @@ __host__ __device__ inline LdsPlan lds_plan(int D, int ng, int real_bytes, int l
     if (lds_hist) o = al(o + (uint32_t)(D * ng * 8));
     p.c_off = o;
     if (lds_hist) o = al(o + (uint32_t)(D * ng * 4));
-    p.st_off = o; o = al(o + (uint32_t)((tile / 2 + 4) * 4));
+    p.st_off = o; o = al(o + (uint32_t)((tile / 2 + 4) * 2));
     p.wave_off = o; o = al(o + (uint32_t)(kWaves * sizeof(WaveRec)));
     p.cin_off = o; o = al(o + (uint32_t)(kWaves * sizeof(WaveRec)));
     p.side_off = o; o = al(o + (uint32_t)(2 * sizeof(Partial) + 16));
@@ -250,7 +250,7 @@ struct FillLds {
     R* auxl;
     double* hl;
     uint32_t* cl;
-    uint32_t* st;
+    uint16_t* st;
     WaveRec* wrec;
     WaveRec* cin;
     Partial* tside;
@@ -263,7 +263,7 @@ struct FillLds {
         auxl = reinterpret_cast<R*>(smem + lp.aux_off);
         hl = reinterpret_cast<double*>(smem + lp.h_off);
         cl = reinterpret_cast<uint32_t*>(smem + lp.c_off);
-        st = reinterpret_cast<uint32_t*>(smem + lp.st_off);
+        st = reinterpret_cast<uint16_t*>(smem + lp.st_off);
         wrec = reinterpret_cast<WaveRec*>(smem + lp.wave_off);
         cin = reinterpret_cast<WaveRec*>(smem + lp.cin_off);
         tside = reinterpret_cast<Partial*>(smem + lp.side_off);
@@ -307,7 +307,7 @@ __device__ __forceinline__ void fill_tile(int tile, const TileIO& io, const Fill
     const auto gmap = tile_map<GMAP>(io, gl);
     double* hl = L.hl;
     uint32_t* cl = L.cl;
-    uint32_t* st = L.st;
+    uint16_t* st = L.st;
     WaveRec* wrec = L.wrec;
     WaveRec* cin = L.cin;
     Partial* tside = L.tside;
@@ -318,12 +318,19 @@ __device__ __forceinline__ void fill_tile(int tile, const TileIO& io, const Fill
         const uint32_t h_nx = io.tile_first[tile + 1];
         const uint32_t h_top = min(h_nx, sc.n_cubes - 1u);
         const int nst_load = (int)(h_top - h_lo) + 2;   // starts of h_lo .. h_top+1
-        for (int i = tid; i < nst_load; i += kFillThreads) st[i] = io.start[h_lo + i];
+        // the starts relative to the tile, plus one, clamped to [0, tile + 2]:
+        // 16 bits hold them (tile <= kMaxTile), and every comparison below
+        // with a sample of the tile keeps its outcome
+        for (int i = tid; i < nst_load; i += kFillThreads) {
+            const int64_t r = (int64_t)io.start[h_lo + i] - (int64_t)t0 + 1;
+            st[i] = (uint16_t)(r < 0 ? 0 : (r > io.tile + 2 ? io.tile + 2 : r));
+        }
         if (tid == 0) *tflags = 0u;
         __syncthreads();
 
         const uint32_t k0 = t0 + (uint32_t)(tid * S);
         const uint32_t k1 = min(k0 + (uint32_t)S, t1);
+        const uint32_t kr = k0 - t0 + 1u;           // k0 in the frame of st
         const int n_active = (int)((t1 - t0 + (uint32_t)S - 1u) / (uint32_t)S);
         // per lane: the run of its first cube when that cube began earlier
         // (head), and the run of its last cube when it continues (tail)
@@ -331,16 +338,16 @@ __device__ __forceinline__ void fill_tile(int tile, const TileIO& io, const Fill
         Run hrun = run_empty(), trun = run_empty();
         uint32_t h_first = 0, h_last = 0;
         if (k0 < k1) {
-            int lo = 0, hi = nst_load - 1;          // largest idx with st[idx] <= k0
+            int lo = 0, hi = nst_load - 1;          // largest idx with start <= k0
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
-                if (st[mid] <= k0) lo = mid; else hi = mid;
+                if (st[mid] <= kr) lo = mid; else hi = mid;
             }
             int idx = lo;
             uint32_t h = h_lo + (uint32_t)idx;
             h_first = h;
-            uint32_t nxt = st[idx + 1];
-            bool head = st[idx] < k0;
+            uint32_t nxt = t0 - 1u + st[idx + 1];
+            bool head = st[idx] < kr;
             uint32_t s[MAXD];
             sp.digits(h, s);
             uint32_t n = 0;

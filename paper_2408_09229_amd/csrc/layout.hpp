@@ -8,6 +8,9 @@ namespace vg {
 constexpr int kMaxDim = 16;
 constexpr int kFillThreads = 1024;     // one persistent workgroup per CU
 constexpr int kLanesPerTile = kFillThreads;
+// largest tile: the fill keeps the tile's cube starts in LDS as 16-bit
+// offsets from the tile's first sample (plus one, clamped to tile + 2)
+constexpr int kMaxTile = 32768;
 
 // Partial moments of one hypercube's weights over a contiguous run of its
 // samples: count, mean and sum of squared deviations (Chan et al. 1983 form,
