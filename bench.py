@@ -1,16 +1,21 @@
-"""Throughput of the VEGAS+ iteration on one MI355X.
+"""Throughput and time to a target error of the VEGAS+ iteration on one MI355X.
 
-Workload: the d=8 mixture of three normalised Gaussians (s = 0.05, centres
-0.33 / 0.5 / 0.67 on the diagonal), 1024 intervals per axis, 1e8 integrand
-evaluations per iteration, FP32 sample path with FP64 per-cube and total
-accumulators.  One step = one whole iteration (fill, cube fix-up, estimate,
-allocation update, map refinement) over 1e8 synthetic samples; the inputs
-(map, allocation, parameters) are resident in HBM before timing starts.
+Default run (one JSON line): the learned warp against plain VEGAS+ on the
+d=16 correlated Gaussian (s = 0.03, rho = 0.9, 1024 intervals, 1e6
+evaluations per iteration, FP32 sample path with FP64 accumulators; the warp
+is four coupling layers with 2x64 BF16 MLPs).  Each method runs from create,
+through the same continuation warm-up, until its combined relative error
+estimate reaches 1e-4 or the caps (2000 iterations, 600 s); the line gives
+both wall times, both estimates against the closed form, and the warped
+iteration's throughput over K timed iterations after the run.  Sub-records
+give the other workloads in the same run (d=4 Gaussian product in FP64, the
+d=8 three-Gaussian mixture, the d=4 ridge, the batch of 4096 Genz
+integrals), each with its dominant kernel against the roofline (timed with
+HIP events inside the library on its stream) and the CPU oracle timed on a
+bounded sample of the same workload.
 
-Prints one JSON line: evals/s, ms per step, the fill kernel's position
-against the VALU issue roofline (timed with HIP events inside the library on
-its stream), and the CPU oracle timed on a bounded sample of the same
-workload.
+--workload NAME runs one workload alone.  Inputs (map, allocation,
+parameters) are resident in HBM before timing starts.
 """
 from __future__ import annotations
 
@@ -100,6 +105,19 @@ def profiled_traffic(workload: str):
     return rec["traffic_bytes"] if rec.get("source_hash") == fill_source_hash() else None
 
 
+def host_info():
+    """Cores and CPU model of the host the oracle is timed on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
 def cpu_baseline(w, budget_evals: int, iters: int):
     import oracle
     ww = w.with_(n_eval=budget_evals, n_iter=iters)
@@ -108,8 +126,8 @@ def cpu_baseline(w, budget_evals: int, iters: int):
                alpha=ww.alpha, beta=ww.beta)
     dt = time.perf_counter() - t0
     return {"value": budget_evals * iters / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} iterations x {budget_evals:.0e} evals of the same integrand, dim and "
-                      f"intervals (single-threaded FP64 C oracle, {dt:.1f} s)"}
+            "sample": f"{iters} iterations x {budget_evals:.2g} evals of the same integrand, dim and "
+                      f"intervals (single-threaded FP64 C oracle, {dt:.1f} s)", **host_info()}
 
 
 def cpu_baseline_batch(insts, budget_evals: int):
@@ -129,17 +147,42 @@ def cpu_baseline_batch(insts, budget_evals: int):
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
             "sample": f"one iteration of the first {n} problems of the batch ({done:.2e} evals; "
-                      f"single-threaded FP64 C oracle, {dt:.1f} s)"}
+                      f"single-threaded FP64 C oracle, {dt:.1f} s)", **host_info()}
 
 
-def run_batch(args):
+def cpu_baseline_warp(w, n_samples: int):
+    """The oracle's plain iteration on a reduced budget of the same workload,
+    and its warp (FP64 numpy forward pass plus the loss gradient through the
+    inverse chain, with BF16 emulation) on n_samples points: evals/s of each,
+    and of a warped iteration (the two costs added per sample)."""
+    import numpy as np
+    import oracle
+    from oracle import flow as fl
+    base = cpu_baseline(w, 100_000, 2)
+    rng = np.random.default_rng(0)
+    th = fl.init_params(w.dim, 0)
+    y = rng.random((n_samples, w.dim))
+    t0 = time.perf_counter()
+    wv, lj = fl.forward(th, y, emu=True)
+    coef = np.full(n_samples, 1.0 / n_samples)
+    fl.loss_grad(th, wv, coef, emu=True)
+    dt = time.perf_counter() - t0
+    per_flow = dt / n_samples
+    per_plain = 1.0 / base["value"]
+    base["warp_value"] = 1.0 / (per_flow + per_plain)
+    base["sample"] += (f"; warp: forward + loss gradient of {n_samples} samples ({dt:.1f} s, FP64 numpy with "
+                       f"BF16 emulation), warped evals/s = 1/(plain + warp seconds per sample)")
+    return base
+
+
+def run_batch(args, insts=None):
     """The batched workload: every step is one iteration of all 4096 problems."""
     import torch
     import numpy as np
     import vegas_inputs as vi
     from paper_2408_09229_amd import VegasBatch, make_config
     from tests import closed_forms as cf
-    insts = vi.genz_batch(4096, seed=0)
+    insts = insts or vi.genz_batch(4096, seed=0)
     torch.cuda.set_device(0)
     cfgs = [make_config(x.dim, vi.BATCH_N_G, x.n_eval, seed=0, instance=i, precision=vi.BATCH_PRECISION,
                         max_iter=args.warmup + args.steps + 1) for i, x in enumerate(insts)]
@@ -202,152 +245,15 @@ def run_batch(args):
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batch(insts, int(args.cpu_evals))
-    print(json.dumps(out), flush=True)
     b.close()
+    return out
 
 
-def run_warp_compare(args, w):
-    """Learned warp against plain VEGAS+ on a correlated Gaussian: the same
-    warm-up for both (for the sharp target a continuation from a wide,
-    uncorrelated Gaussian), then iterations combined until the relative
-    error estimate reaches 1e-4 or the caps.  Wall time counts from create."""
-    import numpy as np
+def run_single(args, w):
+    """One workload: W untimed iterations, then K timed ones."""
     import torch
     import vegas_inputs as vi
-    from oracle import flow as fl
     from paper_2408_09229_amd import Vegas, make_config
-    target = 1e-4
-    sharp = w.name == "corr_gauss_16d"
-    warm = vi.continuation(w, 20) if sharp else [w.params] * w.n_adapt
-    per = 2 if sharp else 1
-    cap_it, cap_s = args.cap_iters, args.cap_seconds
-    from tests import closed_forms as cf
-    exact = cf.exact(w)
-    torch.cuda.set_device(0)
-    out = {}
-    for method in ("plain", "warp"):
-        cfg = make_config(w.dim, w.n_g, w.n_eval, precision="f32", max_iter=len(warm) * per + cap_it + 16)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        v = Vegas(cfg, w.family, warm[0])
-        for p in warm:
-            v.set_params(p)
-            v.adapt(per)
-        n0 = len(warm) * per
-        if method == "warp":
-            v.attach_flow(fl.init_params(w.dim, 0).astype(np.float32), lr=args.flow_lr, train=True, judge=True)
-            v.enable_flow(True)
-        rel = math.inf
-        n = 0
-        t_int = 0.0
-        while n < cap_it and time.perf_counter() - t0 < cap_s:
-            torch.cuda.synchronize()
-            ta = time.perf_counter()
-            v.integrate(10)
-            torch.cuda.synchronize()
-            t_int += time.perf_counter() - ta
-            n += 10
-            I, s2 = v.get_iterations()
-            Ii, si = I[n0:], s2[n0:]
-            wgt = 1.0 / si
-            Ic = float(np.sum(Ii * wgt) / np.sum(wgt))
-            rel = math.sqrt(1.0 / np.sum(wgt)) / abs(Ic) if Ic != 0 else math.inf
-            if rel <= target:
-                break
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        I, s2 = v.get_iterations()
-        Ic = float(np.sum(I[n0:] / s2[n0:]) / np.sum(1.0 / s2[n0:]))
-        rec = {"iterations": n, "wall_s": wall, "reached": rel <= target, "integral": Ic, "rel_err_estimate": rel,
-               "true_rel_err": abs(Ic - exact) / exact,
-               "evals_per_s": w.n_eval * n / t_int if t_int > 0 else None,
-               "median_var_per_eval_rel": float(np.median(s2[n0:] * w.n_eval)) / Ic ** 2 if Ic else None}
-        if method == "warp":
-            on, kept, rej = v.flow_status()
-            rec["judge"] = {"warp_on_at_end": on, "kept": kept, "rejected": rej}
-        out[method] = rec
-        print(f"[bench] {method}: {rec}", file=sys.stderr, flush=True)
-        v.close()
-    line = {
-        "metric": "integrand evals/sec and wall time to 1e-4 rel. error; learned warp vs plain VEGAS+",
-        "value": out["warp"]["evals_per_s"],
-        "unit": "evals/s",
-        "n_gpus": 1,
-        "steps": out["warp"]["iterations"],
-        "warmup": len(warm) * per,
-        "ms_per_step": 1e3 * w.n_eval / out["warp"]["evals_per_s"] if out["warp"]["evals_per_s"] else None,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+bf16",
-        "data": "synthetic",
-        "config": {"workload": f"{w.name}: {WORKLOADS[w.name]}, {w.n_eval:.0e} evals/iteration; learned warp "
-                               f"4 coupling layers, 2x64 BF16 MLPs, 16 bins; lr {args.flow_lr}",
-                   "n_eval": w.n_eval, "dim": w.dim, "n_intervals": w.n_g, "target_rel_err": target,
-                   "caps": {"iterations": cap_it, "seconds": cap_s}, "parallelism": "single-gpu"},
-        "exact": exact,
-        "comparison": out,
-    }
-    print(json.dumps(line), flush=True)
-
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="gauss3_8d", choices=sorted(WORKLOADS))
-    ap.add_argument("--n-eval", type=float, default=0, help="override evals/iteration (0: the workload's)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-evals", type=float, default=1.5e7)
-    ap.add_argument("--cpu-iters", type=int, default=3)
-    ap.add_argument("--issue-rates", action="store_true",
-                    help="only measure the issue rates of the VALU instruction kinds the path uses and the "
-                         "LDS atomic add rates")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 256 MiB device copy (for scaling HBM counters)")
-    ap.add_argument("--tune-cache", default="", help="autotuner cache of the batched workload")
-    ap.add_argument("--cap-iters", type=int, default=400, help="warp comparison: iteration cap per method")
-    ap.add_argument("--cap-seconds", type=float, default=30.0, help="warp comparison: time cap per method")
-    ap.add_argument("--flow-lr", type=float, default=3e-4, help="warp comparison: Adam step of the warp")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the VEGAS+ path here "
-              "runs on a single MI355X)", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-
-    if args.issue_rates:
-        import ctypes
-        lib = ctypes.CDLL(os.path.join(ROOT, "paper_2408_09229_amd", "libvegas_issue_rates.so"))
-        out = (ctypes.c_double * 8)()
-        torch.cuda.set_device(0)
-        assert lib.vegas_issue_rates(out, 8, ctypes.c_double(2.4), 1024) == 0
-        names = ["fma_f32", "mul+exp2_f32", "mad_u64_u32+xor", "fma_f64", "bitop3", "add_f64+rcp_f64",
-                 "exp2_f32", "exp2_f32:fma_f32 1:3 independent"]
-        rates = {n: round(v, 3) for n, v in zip(names, out)}
-        lds = (ctypes.c_double * 6)()
-        assert lib.vegas_lds_atomic_rates(lds, ctypes.c_double(2.4), 256) == 0
-        lnames = ["ds_add_u32", "ds_add_f32", "ds_add_f64"]
-        rates["lds_atomic_adds_per_cu_cycle"] = {
-            "conflict_free": {n: round(lds[i], 2) for i, n in enumerate(lnames)},
-            "random_1024": {n: round(lds[3 + i], 2) for i, n in enumerate(lnames)}}
-        print(json.dumps(rates))
-        return
-
-    import vegas_inputs as vi
-    if args.workload == "genz_batch":
-        run_batch(args)
-        return
-    if args.workload in ("corr_gauss_16d", "corr_gauss_16d_mild"):
-        run_warp_compare(args, getattr(vi, args.workload)())
-        return
-    from paper_2408_09229_amd import Vegas, make_config
-
-    w = getattr(vi, args.workload)()
-    if args.n_eval:
-        w = w.with_(n_eval=int(args.n_eval))
     torch.cuda.set_device(0)
     cfg = make_config(w.dim, w.n_g, w.n_eval, alpha=w.alpha, beta=w.beta, seed=w.seed, precision=w.precision,
                       max_iter=args.warmup + args.steps + 1)
@@ -398,7 +304,13 @@ def main():
                      "kernel": "k_fill", "kernel_ms": fill_ms},
         "result": {"integral": r.integral, "sigma": math.sqrt(r.sigma2), "chi2_dof": r.chi2_dof,
                    "exact": exact, "z": (r.integral - exact) / math.sqrt(r.sigma2) if r.sigma2 > 0 else None},
+        "phases_ms_per_step": {"fill": fill_ms, "fixup_estimate": phases[1] / n_timed,
+                               "allocation": phases[2] / n_timed, "map": phases[3] / n_timed},
     }
+    if w.precision == "f64":
+        # FP64 sample path: the issue slots are FP64 instructions, which the
+        # chip issues at half the FP32 rate
+        out["roofline"]["note"] = "FP64 sample path; the issue count is the FP32 path's"
     if args.copy_calibration:
         src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")   # 256 MiB
         dst = torch.empty_like(src)
@@ -407,9 +319,234 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, int(args.cpu_evals), args.cpu_iters)
-    print(json.dumps(out), flush=True)
+        if w.name == "gauss_prod_4d":
+            out["cpu_baseline"] = cpu_baseline(w, w.n_eval, w.n_iter)     # the whole run
+        else:
+            out["cpu_baseline"] = cpu_baseline(w, int(args.cpu_evals), args.cpu_iters)
     v.close()
+    return out
+
+
+def warp_run(args, w, method: str, exact: float):
+    """One method on the correlated Gaussian: create, the continuation
+    warm-up, then iterations combined by Eq. 8-9 in chunks until the relative
+    error estimate reaches the target or the caps.  The wall time counts from
+    create.  The warp is attached at create from the library's own starting
+    weights and trains through the warm-up with the guard judge; the cost
+    judge takes over for the combined iterations."""
+    import numpy as np
+    import torch
+    import vegas_inputs as vi
+    from paper_2408_09229_amd import Vegas, make_config
+    target = args.target
+    sharp = w.name == "corr_gauss_16d"
+    warm = vi.continuation(w, args.cont_steps) if sharp else [w.params] * w.n_adapt
+    per = args.cont_iters if sharp else 1
+    cap_it, cap_s = args.cap_iters, args.cap_seconds
+    cfg = make_config(w.dim, w.n_g, w.n_eval, precision="f32",
+                      max_iter=len(warm) * per + cap_it + args.steps + args.chunk + 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    v = Vegas(cfg, w.family, warm[0])
+    if method == "warp":
+        v.attach_flow(None, lr=args.flow_lr, train=True, loss=args.flow_loss, judge="guard",
+                      steps_per_iter=args.flow_steps, control_period=16, init_seed=w.seed)
+        v.enable_flow(True)
+    for p in warm:
+        v.set_params(p)
+        v.adapt(per)
+    if method == "warp":
+        v.set_flow_config(lr=args.flow_lr, train=True, loss="variance", judge="cost",
+                          steps_per_iter=args.flow_steps, control_period=16)
+    n0 = len(warm) * per
+    n = 0
+    rel = math.inf
+    r = None
+    while n < cap_it and time.perf_counter() - t0 < cap_s:
+        v.integrate(args.chunk)
+        n += args.chunk
+        r = v.result()
+        rel = math.sqrt(r.sigma2) / abs(r.integral) if r.integral != 0 else math.inf
+        if rel <= target:
+            break
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    I_all, s2_all = v.get_iterations()
+    Ii, si = I_all[n0:], s2_all[n0:]
+    kinds = v.flow_kinds()[n0:] if method == "warp" else np.zeros(len(Ii), np.int32)
+    sel = kinds != 2
+    sig = math.sqrt(r.sigma2)
+    rec = {"iterations": n, "warmup_iterations": n0, "wall_s": wall, "reached": bool(rel <= target),
+           "integral": r.integral, "sigma": sig, "rel_err_estimate": rel,
+           "true_rel_err": abs(r.integral - exact) / exact, "z": (r.integral - exact) / sig if sig > 0 else None,
+           "resolved": bool(sig > 0 and abs(r.integral - exact) < 3.0 * sig),
+           "median_rel_var_per_eval": float(np.median(si[sel] / np.maximum(Ii[sel] ** 2, 1e-300) * w.n_eval))}
+    if method == "warp":
+        on, kept, rej = v.flow_status()
+        rec["judge"] = {"warp_on_at_end": on, "kept": kept, "rejected": rej,
+                        "control_iterations": int(np.sum(kinds == 2)), "warped_iterations": int(np.sum(kinds == 1))}
+    print(f"[bench] {method}: {json.dumps(rec)}", file=sys.stderr, flush=True)
+    return v, rec
+
+
+def run_warp_compare(args, w):
+    """Learned warp against plain VEGAS+ (time to the target error), then the
+    warped iteration's throughput over K timed iterations."""
+    import torch
+    from tests import closed_forms as cf
+    exact = cf.exact(w)
+    torch.cuda.set_device(0)
+    out = {}
+    vp, out["plain"] = warp_run(args, w, "plain", exact)
+    vp.close()
+    v, out["warp"] = warp_run(args, w, "warp", exact)
+    # throughput of the warped iteration as the run left it: W more
+    # iterations untimed, then K timed between events on the library's stream
+    v.set_flow_config(lr=args.flow_lr, train=True, loss="variance", judge="guard",
+                      steps_per_iter=args.flow_steps, control_period=16)
+    v.integrate(args.warmup)
+    torch.cuda.synchronize()
+    v.set_timing(True)
+    v.set_flow_timing(True)
+    st = v.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    v.integrate(args.steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    kinds = v.flow_kinds()[-args.steps:]
+    ft = v.flow_timing()
+    v.close()
+    # the warp's dominant kernel, the sampling pass on BF16 MFMA: 2 x (8x64 +
+    # 64x64 + 64x128) multiply-adds per layer and sample
+    flops = 2 * 4 * (8 * 64 + 64 * 64 + 64 * 128) * w.n_eval
+    samp_ms = ft["sample_ms"]
+    ach = flops / (samp_ms / 1e3) if samp_ms else None
+    pl, wp = out["plain"], out["warp"]
+    line = {
+        "metric": "integrand evals/sec and wall time to 1e-4 rel. error; learned warp vs plain VEGAS+",
+        "value": w.n_eval * args.steps / (ms / 1e3),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+bf16",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {WORKLOADS[w.name]}, {w.n_eval:.0e} evals/iteration; learned warp "
+                               f"4 coupling layers, 2x64 BF16 MLPs, 16 bins",
+                   "n_eval": w.n_eval, "dim": w.dim, "n_intervals": w.n_g, "target_rel_err": args.target,
+                   "caps": {"iterations": args.cap_iters, "seconds": args.cap_seconds},
+                   "warmup": f"continuation over {args.cont_steps} steps x {args.cont_iters} iterations",
+                   "warp": {"lr": args.flow_lr, "adam_steps_per_iteration": args.flow_steps,
+                            "warmup_loss": args.flow_loss, "control_period": 16},
+                   "parallelism": "single-gpu"},
+        "time_to_target_s": {"warp": wp["wall_s"] if wp["reached"] else None,
+                             "plain": pl["wall_s"] if pl["reached"] else None},
+        "exact": exact,
+        "comparison": out,
+        "timed_iterations": {"warped": int((kinds == 1).sum()), "control": int((kinds == 2).sum()),
+                             "plain": int((kinds == 0).sum())},
+        "roofline": {"bound": "mfma", "achieved": ach / 1e12 if ach else None, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": ach / 2.5e15 if ach else None, "traffic": None, "kernel": "k_flow_sample",
+                     "kernel_ms": samp_ms, "train_ms": ft["train_ms"]},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_warp(w, 4000)
+    return line
+
+
+def subrecords(args):
+    """The other workloads in the same run, one record each."""
+    import vegas_inputs as vi
+    subs = {}
+    for name in ("gauss_prod_4d", "gauss3_8d", "ridge_4d"):
+        w = getattr(vi, name)()
+        a = argparse.Namespace(**vars(args))
+        a.steps, a.warmup = (w.n_iter, 0) if name == "gauss_prod_4d" else (args.sub_steps, 2)
+        subs[name] = run_single(a, w)
+    a = argparse.Namespace(**vars(args))
+    a.steps, a.warmup = vi.BATCH_ITER, vi.BATCH_ADAPT
+    subs["genz_batch"] = run_batch(a)
+    return subs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="headline", choices=["headline"] + sorted(WORKLOADS))
+    ap.add_argument("--n-eval", type=float, default=0, help="override evals/iteration (0: the workload's)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sub", action="store_true", help="headline: skip the other workloads' records")
+    ap.add_argument("--sub-steps", type=int, default=20, help="timed iterations of the d=8 and ridge records")
+    ap.add_argument("--cpu-evals", type=float, default=1.5e7)
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--issue-rates", action="store_true",
+                    help="only measure the issue rates of the VALU instruction kinds the path uses and the "
+                         "LDS atomic add rates")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (for scaling HBM counters)")
+    ap.add_argument("--tune-cache", default="", help="autotuner cache of the batched workload")
+    ap.add_argument("--target", type=float, default=1e-4, help="warp comparison: relative error target")
+    ap.add_argument("--cap-iters", type=int, default=2000, help="warp comparison: iteration cap per method")
+    ap.add_argument("--cap-seconds", type=float, default=600.0, help="warp comparison: time cap per method")
+    ap.add_argument("--chunk", type=int, default=5, help="warp comparison: iterations between error checks")
+    ap.add_argument("--cont-steps", type=int, default=20, help="warp comparison: continuation steps")
+    ap.add_argument("--cont-iters", type=int, default=2, help="warp comparison: iterations per step")
+    ap.add_argument("--flow-lr", type=float, default=1e-3, help="warp comparison: Adam step of the warp")
+    ap.add_argument("--flow-steps", type=int, default=1, help="warp comparison: Adam steps per iteration")
+    ap.add_argument("--flow-loss", default="variance", choices=["variance", "kl"],
+                    help="warp comparison: training loss during the warm-up")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the VEGAS+ path here "
+              "runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if args.issue_rates:
+        import ctypes
+        lib = ctypes.CDLL(os.path.join(ROOT, "paper_2408_09229_amd", "libvegas_issue_rates.so"))
+        out = (ctypes.c_double * 8)()
+        torch.cuda.set_device(0)
+        assert lib.vegas_issue_rates(out, 8, ctypes.c_double(2.4), 1024) == 0
+        names = ["fma_f32", "mul+exp2_f32", "mad_u64_u32+xor", "fma_f64", "bitop3", "add_f64+rcp_f64",
+                 "exp2_f32", "exp2_f32:fma_f32 1:3 independent"]
+        rates = {n: round(v, 3) for n, v in zip(names, out)}
+        lds = (ctypes.c_double * 6)()
+        assert lib.vegas_lds_atomic_rates(lds, ctypes.c_double(2.4), 256) == 0
+        lnames = ["ds_add_u32", "ds_add_f32", "ds_add_f64"]
+        rates["lds_atomic_adds_per_cu_cycle"] = {
+            "conflict_free": {n: round(lds[i], 2) for i, n in enumerate(lnames)},
+            "random_1024": {n: round(lds[3 + i], 2) for i, n in enumerate(lnames)}}
+        print(json.dumps(rates))
+        return
+
+    import vegas_inputs as vi
+    if args.workload == "headline":
+        line = run_warp_compare(args, vi.corr_gauss_16d())
+        if not args.no_sub:
+            line["sub_records"] = subrecords(args)
+        print(json.dumps(line), flush=True)
+        return
+    if args.workload == "genz_batch":
+        print(json.dumps(run_batch(args)), flush=True)
+        return
+    w = getattr(vi, args.workload)()
+    if args.workload in ("corr_gauss_16d", "corr_gauss_16d_mild"):
+        print(json.dumps(run_warp_compare(args, w)), flush=True)
+        return
+    if args.n_eval:
+        w = w.with_(n_eval=int(args.n_eval))
+    print(json.dumps(run_single(args, w)), flush=True)
 
 
 if __name__ == "__main__":

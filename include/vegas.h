@@ -226,34 +226,70 @@ vegas_status vegas_get_timing(vegas_ctx* ctx, double* ms, int32_t* n_iter);
  * Restrictions: dim 16, FP32 precision, accum FP64 or KAHAN, families
  *   GAUSS_DIAG, GENZ_PPEAK, GENZ_GAUSS, GAUSS_CORR. */
 typedef struct {
-    float   lr;               /* Adam step of the warp's training */
-    int32_t train;            /* 1: one Adam step after every warped iteration */
-    int32_t loss;             /* 0: variance, c_k ~ omega_k^2; 1: KL, c_k ~ |omega_k| */
-    int32_t judge;            /* 1: judge every warped iteration against plain VEGAS+ */
+    float    lr;              /* Adam step of the warp's training */
+    int32_t  train;           /* 1: train after every kept warped iteration */
+    int32_t  loss;            /* 0: variance, c_k ~ omega_k^2; 1: KL, c_k ~ |omega_k| */
+    int32_t  judge;           /* 0: none; 1: guard; 2: guard and cost (see vegas_flow_enable) */
+    int32_t  steps_per_iter;  /* Adam steps after each kept warped iteration, 0..64 (0 = 1) */
+    int32_t  control_period;  /* judge > 0: every control_period-th iteration of the warp's
+                                 phase samples plain VEGAS+; 0 (= 16) or 2..32 */
+    uint64_t init_seed;       /* seed of the library's starting weights (params NULL at attach) */
 } vegas_flow_config;
 
 int32_t vegas_flow_n_params(void);
 /* Bytes of the warp's own device workspace for this context. */
 vegas_status vegas_flow_workspace_size(const vegas_ctx* ctx, size_t* bytes);
-/* Attach a warp with initial parameters.  params: host pointer, n_params
- * floats.  d_workspace: device memory of at least the size above,
- * 256-byte aligned; it must outlive the context.  Synchronous.  The warp
- * starts disabled. */
+/* Attach a warp.  params: host pointer to n_params floats, or NULL for the
+ * library's own starting weights: W1 and W2 uniform in +-1/sqrt(fan_in)
+ * (fan_in 8 and 64) from Philox4x32-10 keyed by cfg->init_seed, every other
+ * parameter 0, so that F starts as the identity (every bin probability
+ * 1/16, log J_F = 0).  d_workspace: device memory of at least the size
+ * above, 256-byte aligned; it must outlive the context.  Synchronous.  The
+ * warp starts disabled. */
 vegas_status vegas_flow_attach(vegas_ctx* ctx, const vegas_flow_config* cfg, const float* params,
                                void* d_workspace, size_t bytes);
-/* on = 1: the following iterations sample through the warp.  Enabling
- * takes the judge's reference from the last (up to five) plain iterations:
- * the median sigma_t^2 and the inverse-variance mean of I_t.
- * With cfg.judge set, every warped iteration t is kept or rejected.  It is
- * kept when sigma_t^2 <= 2 x the reference and |I_t - I_ref| <=
- * 5 sqrt(sigma_t^2 + sigma_ref^2).  A kept iteration's parameters become the accepted ones,
- * then one training step follows if cfg.train is set.  A rejected one
- * restores the accepted parameters and restarts Adam.  Three rejections in
- * a row switch the warp off, and plain VEGAS+ continues.  Warped and plain
- * iterations are both unbiased and combine by Eq. 8-9 as usual.  The judge
- * reads each warped iteration's estimate, so it synchronises the stream
- * once per warped iteration. */
+/* Replace the warp's configuration (lr, training, loss, judge, steps,
+ * control period) for the iterations that follow; parameters and Adam
+ * state stay.  A new judge mode starts its cost records afresh.  Host
+ * pointer; no HIP call. */
+vegas_status vegas_flow_set_config(vegas_ctx* ctx, const vegas_flow_config* cfg);
+/* on = 1: the following iterations sample through the warp; the parameters
+ * in place become the kept ones.
+ * The judge (cfg.judge > 0):
+ *  - control: every control_period-th iteration of the warp's phase samples
+ *    plain VEGAS+ (the same map and allocation, no warp), so 1/period of
+ *    the evaluations measure plain VEGAS+.  Control iterations are not
+ *    combined by Eq. 8-9: a separable importance density can miss most of a
+ *    correlated integrand's mass, and its variance estimate is then far
+ *    too small to be weighted by.
+ *  - guard, every warped iteration: rejected when its estimate or variance
+ *    is not finite or its relative variance sigma_t^2/I_t^2 exceeds 10x the
+ *    median of the last (up to) 4 kept warped iterations (of the last plain
+ *    iterations before any was kept).  A rejected iteration restores the
+ *    last kept parameters and restarts Adam; three rejections in a row
+ *    switch the warp off.
+ *  - cost (judge = 2), after each control iteration: the warp's efficiency,
+ *    the median of sigma_t^2/I_t^2 x GPU time over its last (up to) 8
+ *    warped iterations (training included), against the same over the last
+ *    (up to) 3 controls; a control whose estimate lies more than 5 sigma
+ *    from the kept warped iterations' combined estimate has missed the
+ *    integrand and counts as infinitely costly.  The warp losing two
+ *    checks in a row switches it off; plain VEGAS+ continues.
+ * Warped iterations combine by Eq. 8-9 with the plain ones run outside the
+ * warp's phase.  The judge reads each warped iteration's estimate, so it
+ * synchronises the stream once per warped iteration. */
 vegas_status vegas_flow_enable(vegas_ctx* ctx, int32_t on);
+/* Timing of the warp with HIP events on the context's stream: on = 1
+ * starts (and clears) the record; vegas_flow_get_timing synchronises and
+ * returns, summed over the recorded warped iterations, ms[0] the sampling
+ * pass (y -> w = F(y)) and ms[1] the training (gradient passes, Adam,
+ * repack), and *n_iter their count.  ms: host array of 2 doubles. */
+vegas_status vegas_flow_set_timing(vegas_ctx* ctx, int32_t on);
+vegas_status vegas_flow_get_timing(vegas_ctx* ctx, double* ms, int32_t* n_iter);
+/* Kind of every iteration run so far: 0 plain, 1 through the warp, 2 plain
+ * control of the judge.  kinds: host array of capacity cap; *n receives
+ * the iteration count.  No HIP call. */
+vegas_status vegas_flow_get_kinds(vegas_ctx* ctx, int32_t* kinds, int32_t cap, int32_t* n);
 /* The warp's state: enabled now, warped iterations kept and rejected by the
  * judge (host pointers, any may be NULL). */
 vegas_status vegas_flow_status(const vegas_ctx* ctx, int32_t* on, int32_t* accepted, int32_t* rejected);
@@ -270,6 +306,11 @@ vegas_status vegas_flow_get_samples(vegas_ctx* ctx, float* w, float* lj, float* 
  * gradient is a positive multiple of the gradient of the estimator's
  * variance. */
 vegas_status vegas_flow_grad(vegas_ctx* ctx, float* grad);
+/* Test hook, synchronous.  One Adam step of the warp's training (the step
+ * counter advances) on a given gradient instead of the computed one: host
+ * pointer grad[n_params], all finite.  Adam: beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected, step cfg.lr, in FP32. */
+vegas_status vegas_flow_adam_step(vegas_ctx* ctx, const float* grad);
 /* Test hook, synchronous, on the current device.  One BF16 matrix product
  * D = A B.  Device pointers: A [32][16], B [16][32], D [32][32], all FP32
  * row-major.  A and B are rounded to BF16 first.  It checks the lane layout

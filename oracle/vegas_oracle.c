@@ -421,11 +421,23 @@ done:
 ORC_EXPORT void orc_combine(const double* I, const double* s2, int n,
                             double* Ibar, double* s2bar, double* chi2dof)
 {
-    int nz = 0;
-    double zsum = 0.0;
-    for (int t = 0; t < n; ++t)
-        if (s2[t] == 0.0) { ++nz; zsum += I[t]; }
+    /* READING: an iteration with sigma_t^2 = 0 is exact (f constant on every
+       cube) and decides the result; an "empty" one (I_t = 0 and
+       sigma_t^2 = 0: every weight was zero, so the samples missed the
+       integrand or it underflowed) says nothing about the variance and is
+       left out whenever another iteration has a nonzero estimate. */
     if (n == 0) { *Ibar = 0.0; *s2bar = INFINITY; *chi2dof = 0.0; return; }
+    int n_empty = 0;
+    for (int t = 0; t < n; ++t)
+        if (I[t] == 0.0 && s2[t] == 0.0) ++n_empty;
+    if (n_empty == n) { *Ibar = 0.0; *s2bar = 0.0; *chi2dof = 0.0; return; }
+    int nz = 0, m = 0;
+    double zsum = 0.0;
+    for (int t = 0; t < n; ++t) {
+        if (I[t] == 0.0 && s2[t] == 0.0) continue;
+        ++m;
+        if (s2[t] == 0.0) { ++nz; zsum += I[t]; }
+    }
     if (nz > 0) {
         *Ibar = zsum / nz;
         *s2bar = 0.0;
@@ -434,18 +446,20 @@ ORC_EXPORT void orc_combine(const double* I, const double* s2, int n,
     }
     double wsum = 0.0, wisum = 0.0;
     for (int t = 0; t < n; ++t) {
+        if (s2[t] == 0.0) continue;
         wsum += 1.0 / s2[t];
         wisum += I[t] / s2[t];
     }
     double Ib = wisum / wsum;
     double chi = 0.0;
     for (int t = 0; t < n; ++t) {
+        if (s2[t] == 0.0) continue;
         double u = I[t] - Ib;
         chi += u * u / s2[t];
     }
     *Ibar = Ib;
     *s2bar = 1.0 / wsum;
-    *chi2dof = n > 1 ? chi / (n - 1) : 0.0;
+    *chi2dof = m > 1 ? chi / (m - 1) : 0.0;
 }
 
 /* ------------------------------------------------------------------------ */

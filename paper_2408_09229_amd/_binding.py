@@ -60,7 +60,8 @@ class vegas_info(C.Structure):
 
 
 class vegas_flow_config(C.Structure):
-    _fields_ = [("lr", C.c_float), ("train", C.c_int32), ("loss", C.c_int32), ("judge", C.c_int32)]
+    _fields_ = [("lr", C.c_float), ("train", C.c_int32), ("loss", C.c_int32), ("judge", C.c_int32),
+                ("steps_per_iter", C.c_int32), ("control_period", C.c_int32), ("init_seed", C.c_uint64)]
 
 
 class vegas_batch_info(C.Structure):
@@ -99,12 +100,17 @@ _DECL = {
     "vegas_flow_n_params": (C.c_int32, []),
     "vegas_flow_workspace_size": (_st, [_vp, C.POINTER(C.c_size_t)]),
     "vegas_flow_attach": (_st, [_vp, C.POINTER(vegas_flow_config), _vp, _vp, C.c_size_t]),
+    "vegas_flow_set_config": (_st, [_vp, C.POINTER(vegas_flow_config)]),
     "vegas_flow_enable": (_st, [_vp, C.c_int32]),
+    "vegas_flow_get_kinds": (_st, [_vp, _vp, C.c_int32, C.POINTER(C.c_int32)]),
+    "vegas_flow_set_timing": (_st, [_vp, C.c_int32]),
+    "vegas_flow_get_timing": (_st, [_vp, _vp, C.POINTER(C.c_int32)]),
     "vegas_flow_status": (_st, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "vegas_flow_get_params": (_st, [_vp, _vp]),
     "vegas_flow_set_params": (_st, [_vp, _vp]),
     "vegas_flow_get_samples": (_st, [_vp, _vp, _vp, _vp]),
     "vegas_flow_grad": (_st, [_vp, _vp]),
+    "vegas_flow_adam_step": (_st, [_vp, _vp]),
     "vegas_mfma_probe": (_st, [_vp, _vp, _vp]),
     "vegas_batch_workspace_size": (_st, [C.c_int32, _vp, _vp, C.c_int32, C.POINTER(C.c_size_t)]),
     "vegas_batch_create": (_st, [C.c_int32, _vp, _vp, _vp, C.c_size_t, _vp, C.c_int32, C.c_char_p,
@@ -301,19 +307,54 @@ class Vegas:
         return ms, n.value
 
     # -- learned warp -------------------------------------------------------
-    def attach_flow(self, params, lr: float = 1e-4, train: bool = False, loss: str = "variance",
-                    judge: bool = False):
-        """Attach a coupling-flow warp (initial FP32 parameters ``params``)."""
+    @staticmethod
+    def _flow_config(lr, train, loss, judge, steps_per_iter, control_period, init_seed):
+        j = {False: 0, True: 1, 0: 0, 1: 1, 2: 2, "guard": 1, "cost": 2}[judge]
+        return vegas_flow_config(lr, int(train), {"variance": 0, "kl": 1}[loss], j, steps_per_iter,
+                                 control_period, init_seed)
+
+    def attach_flow(self, params=None, lr: float = 1e-4, train: bool = False, loss: str = "variance",
+                    judge=0, steps_per_iter: int = 1, control_period: int = 16, init_seed: int = 0):
+        """Attach a coupling-flow warp: initial FP32 parameters ``params``, or
+        None for the library's own seeded starting weights (identity warp).
+        ``judge``: 0 / False none, 1 / True / "guard", 2 / "cost"."""
         import torch
         n = C.c_size_t()
         check(vegas_flow_workspace_size(self.h, C.byref(n)), "vegas_flow_workspace_size")
         self.fws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
-        p = np.ascontiguousarray(params, dtype=np.float32)
-        if p.size != vegas_flow_n_params():
-            raise ValueError("wrong number of flow parameters")
-        self.fcfg = vegas_flow_config(lr, int(train), {"variance": 0, "kl": 1}[loss], int(judge))
+        p = None
+        if params is not None:
+            p = np.ascontiguousarray(params, dtype=np.float32)
+            if p.size != vegas_flow_n_params():
+                raise ValueError("wrong number of flow parameters")
+        self.fcfg = self._flow_config(lr, train, loss, judge, steps_per_iter, control_period, init_seed)
         check(vegas_flow_attach(self.h, C.byref(self.fcfg), _dptr(p), C.c_void_p(self.fws.data_ptr()), n.value),
               "vegas_flow_attach")
+
+    def set_flow_config(self, lr: float = 1e-4, train: bool = False, loss: str = "variance", judge=0,
+                        steps_per_iter: int = 1, control_period: int = 16):
+        self.fcfg = self._flow_config(lr, train, loss, judge, steps_per_iter, control_period, self.fcfg.init_seed)
+        check(vegas_flow_set_config(self.h, C.byref(self.fcfg)), "vegas_flow_set_config")
+
+    def set_flow_timing(self, on: bool):
+        check(vegas_flow_set_timing(self.h, int(on)), "vegas_flow_set_timing")
+
+    def flow_timing(self):
+        """Per warped iteration, ms of the sampling pass and of the training."""
+        ms = np.zeros(2)
+        n = C.c_int32()
+        check(vegas_flow_get_timing(self.h, _dptr(ms), C.byref(n)), "vegas_flow_get_timing")
+        k = max(n.value, 1)
+        return {"sample_ms": ms[0] / k if n.value else None, "train_ms": ms[1] / k if n.value else None,
+                "n": n.value}
+
+    def flow_kinds(self):
+        """Per iteration: 0 plain, 1 through the warp, 2 plain control of the judge."""
+        n = C.c_int32()
+        cap = self.cfg.max_iter or 4096
+        k = np.zeros(cap, np.int32)
+        check(vegas_flow_get_kinds(self.h, _dptr(k), cap, C.byref(n)), "vegas_flow_get_kinds")
+        return k[:n.value].copy()
 
     def enable_flow(self, on: bool = True):
         check(vegas_flow_enable(self.h, int(on)), "vegas_flow_enable")
@@ -338,6 +379,11 @@ class Vegas:
         g = np.zeros(vegas_flow_n_params(), np.float32)
         check(vegas_flow_grad(self.h, _dptr(g)), "vegas_flow_grad")
         return g
+
+    def flow_adam_step(self, grad):
+        """One Adam step of the warp on a given gradient (test hook)."""
+        g = np.ascontiguousarray(grad, dtype=np.float32)
+        check(vegas_flow_adam_step(self.h, _dptr(g)), "vegas_flow_adam_step")
 
     def flow_samples(self):
         """(w [N][16], log J_F [N], omega [N]) of the last warped iteration."""

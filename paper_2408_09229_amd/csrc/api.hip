@@ -268,14 +268,38 @@ struct vegas_ctx {
     size_t f_seg = 0;                  // segment sums of the gradient reduction
     int n_cus = 1;
     bool fused = false;                // small problem: one launch after the fill
-    std::vector<uint8_t> warped;       // per iteration: 1 = sampled through the warp
-    double ref_I = 0.0, ref_s2 = INFINITY;   // plain VEGAS+ reference of the judge
+    std::vector<uint8_t> warped;       // per iteration: 0 plain, 1 through the warp, 2 plain control
+    // the judge: iterations since the warp was enabled, GPU time of each
+    // iteration while the warp is on (event pairs in a ring), the log
+    // entries already read, and its running records
+    int f_phase = 0;
+    std::vector<hipEvent_t> f_ev;      // [kJudgeRing][2]
+    std::vector<int> f_ev_iter;        // iteration held by each ring slot, -1 none
+    std::vector<double> f_ms;          // per iteration: GPU ms, NaN when unknown
+    std::vector<double> log_I, log_s2; // host copy of the iteration log
+    std::vector<double> kept_rv;       // relative variances of kept warped iterations
+    std::vector<double> warp_eff, ctrl_eff;   // relative variance x GPU ms
+    double kw_sum = 0.0, kw_w = 0.0;   // kept warped iterations of the cost phase: sum I/s2, sum 1/s2
+    bool f_timing = false;             // events around the sampling pass and the training
+    std::vector<hipEvent_t> f_tev;     // 4 per timed warped iteration
+    int strikes = 0;                   // consecutive control checks the warp lost
     int rejects = 0;                   // consecutive rejected warped iterations
-    int n_accepted = 0, n_rejected = 0;
+    int n_accepted = 0, n_rejected = 0, n_control = 0;
 
     ~vegas_ctx()
     {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        for (hipEvent_t e : f_ev) (void)hipEventDestroy(e);
+        for (hipEvent_t e : f_tev) (void)hipEventDestroy(e);
+    }
+    hipError_t fmark()
+    {
+        if (!f_timing) return hipSuccess;
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        f_tev.push_back(e);
+        return hipEventRecord(e, stream);
     }
     hipError_t mark()
     {
@@ -392,7 +416,8 @@ vegas_status run_update(vegas_ctx* c, int t, int n_slots, bool timed)
 }
 
 vegas_status flow_train_step(vegas_ctx* c);
-bool flow_judge(vegas_ctx* c, int t);
+vegas_status flow_judge(vegas_ctx* c, int t, bool* keep);
+hipError_t judge_mark(vegas_ctx* c, int t, int end);
 
 // the fill's launch record for iteration t over the current map and
 // allocation; non-finite weights are counted into *nonfinite
@@ -454,6 +479,7 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
         c->n_run = t + 1;
         c->combined.push_back(integrate ? 1 : 0);
         c->warped.push_back(0);
+        c->f_ms.push_back(NAN);
         c->have_prev = true;
         return VEGAS_OK;
     }
@@ -462,10 +488,15 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
         HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histC), (nb + 1) / 2, c->stream));
     }
     const FillArgs a = fill_args(c, t, c->nonfinite());
+    // with the judge on, every control_period-th iteration of the warp's
+    // phase samples plain VEGAS+ (the control)
+    const bool control = c->flow_on && c->fcfg.judge > 0 && (c->f_phase + 1) % c->fcfg.control_period == 0;
+    const bool warp_now = c->flow_on && !control;
+    if (c->flow_on) HIPCHK(judge_mark(c, t, 0));
     // the warped fill keeps the map in LDS; k_fill reads it through the cache
-    const size_t lds = fill_lds_bytes(c->g.D, c->g.ng, fp64, lds_hist, c->g.tile, c->g.n_aux, c->flow_on ? 1 : 0);
+    const size_t lds = fill_lds_bytes(c->g.D, c->g.ng, fp64, lds_hist, c->g.tile, c->g.n_aux, warp_now ? 1 : 0);
     HIPCHK(c->mark());
-    if (c->flow_on) {
+    if (warp_now) {
         // the warp: y -> w = F(y) for every sample, then the fill on w
         FlowSampleArgs fa;
         fa.sc = a.sc;
@@ -475,7 +506,9 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
         fa.packed = c->fws + c->f_packed;
         fa.w = reinterpret_cast<float*>(c->fws + c->f_w);
         fa.lj = reinterpret_cast<float*>(c->fws + c->f_lj);
+        HIPCHK(c->fmark());
         HIPCHK(launch_flow_sample(fa, 2 * c->n_wg, c->stream));
+        HIPCHK(c->fmark());
         HIPCHK(launch_fill_flow(a, fa.w, fa.lj, reinterpret_cast<float*>(c->fws + c->f_om), c->n_wg, lds, c->stream));
     } else {
         HIPCHK(launch_fill(a, fp64, c->n_wg, lds, c->stream));
@@ -518,20 +551,33 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
         const vegas_status s = run_update(c, t, n_slots, true);
         if (s != VEGAS_OK) return s;
     }
-    vegas_status s = VEGAS_OK;
-    const bool warped = c->flow_on;
+    const bool phase = c->flow_on;
     c->n_run = t + 1;
-    c->combined.push_back(integrate ? 1 : 0);
-    c->warped.push_back(warped ? 1 : 0);
+    // control iterations measure plain VEGAS+ for the judge and are not
+    // combined: on the workloads the warp is for, a separable density's
+    // weights can be so heavy-tailed that its own variance estimate is
+    // far too small, and Eq. 8-9 would then let it decide the result
+    c->combined.push_back(integrate && !control ? 1 : 0);
+    c->warped.push_back(warp_now ? 1 : control ? 2 : 0);
+    c->f_ms.push_back(NAN);
     c->have_prev = true;
-    if (warped) {
-        const bool keep = c->fcfg.judge ? flow_judge(c, t) : true;
-        if (!c->flow_attached) return fail(VEGAS_EDEVICE, "flow judge failed");
-        if (keep && c->flow_on && c->fcfg.train) {
-            s = flow_train_step(c);
-            if (s != VEGAS_OK) return s;
+    if (phase) c->f_phase += 1;
+    if (warp_now) {
+        bool keep = true;
+        if (c->fcfg.judge > 0) {
+            const vegas_status js = flow_judge(c, t, &keep);
+            if (js != VEGAS_OK) return js;
         }
+        HIPCHK(c->fmark());
+        if (keep && c->flow_on && c->fcfg.train) {
+            for (int st = 0; st < c->fcfg.steps_per_iter; ++st) {
+                const vegas_status s = flow_train_step(c);
+                if (s != VEGAS_OK) return s;
+            }
+        }
+        HIPCHK(c->fmark());
     }
+    if (phase) HIPCHK(judge_mark(c, t, 1));
     return VEGAS_OK;
 }
 
@@ -569,20 +615,36 @@ namespace vgh {
 
 void combine(const std::vector<double>& I, const std::vector<double>& s2, double* Ib, double* s2b, double* chi)
 {
-    // Eq. 8-9; iterations with sigma^2 = 0 are exact and decide the result
+    // Eq. 8-9.  An iteration with sigma^2 = 0 is exact and decides the
+    // result; one with I = 0 and sigma^2 = 0 had only zero weights (its
+    // samples missed the integrand, or it underflowed) and is left out
+    // whenever another iteration has a nonzero estimate.
     const size_t n = I.size();
-    int nz = 0;
-    double zs = 0.0;
-    for (size_t t = 0; t < n; ++t)
-        if (s2[t] == 0.0) {
-            ++nz;
-            zs += I[t];
-        }
     if (n == 0) {
         *Ib = 0.0;
         *s2b = INFINITY;
         *chi = 0.0;
         return;
+    }
+    auto empty = [&](size_t t) { return I[t] == 0.0 && s2[t] == 0.0; };
+    size_t n_empty = 0;
+    for (size_t t = 0; t < n; ++t) n_empty += empty(t) ? 1 : 0;
+    if (n_empty == n) {
+        *Ib = 0.0;
+        *s2b = 0.0;
+        *chi = 0.0;
+        return;
+    }
+    int nz = 0;
+    size_t m = 0;
+    double zs = 0.0;
+    for (size_t t = 0; t < n; ++t) {
+        if (empty(t)) continue;
+        ++m;
+        if (s2[t] == 0.0) {
+            ++nz;
+            zs += I[t];
+        }
     }
     if (nz > 0) {
         *Ib = zs / nz;
@@ -592,18 +654,20 @@ void combine(const std::vector<double>& I, const std::vector<double>& s2, double
     }
     double w = 0.0, wi = 0.0;
     for (size_t t = 0; t < n; ++t) {
+        if (s2[t] == 0.0) continue;
         w += 1.0 / s2[t];
         wi += I[t] / s2[t];
     }
-    const double m = wi / w;
+    const double mean = wi / w;
     double c2 = 0.0;
     for (size_t t = 0; t < n; ++t) {
-        const double u = I[t] - m;
+        if (s2[t] == 0.0) continue;
+        const double u = I[t] - mean;
         c2 += u * u / s2[t];
     }
-    *Ib = m;
+    *Ib = mean;
     *s2b = 1.0 / w;
-    *chi = n > 1 ? c2 / (double)(n - 1) : 0.0;
+    *chi = m > 1 ? c2 / (double)(m - 1) : 0.0;
 }
 
 void ctx_set_stream(vegas_ctx* c, hipStream_t s) { c->stream = s; }
@@ -1083,41 +1147,135 @@ vegas_status flow_gradient(vegas_ctx* c)
     return VEGAS_OK;
 }
 
-// The judge of a warped iteration t (its estimate against the plain VEGAS+
-// reference taken when the warp was enabled: sigma^2 at most twice the
-// reference median, estimate within 5 sigma).  Kept: the warp that sampled
-// it becomes the accepted one.  Rejected: the accepted warp comes back, the
-// optimiser restarts, and after three rejections in a row the warp is
-// switched off (plain VEGAS+ continues).  Returns whether the warp stays.
-bool flow_judge(vegas_ctx* c, int t)
+constexpr int kJudgeRing = 64;           // iterations whose GPU time can be pending
+constexpr double kJudgeGuard = 10.0;     // a warped iteration is rejected above this x the reference
+
+double rel_var(double I, double s2) { return I != 0.0 ? s2 / (I * I) : INFINITY; }
+
+double median_tail(const std::vector<double>& v, size_t m)
 {
-    double it[2];
-    if (hipMemcpy(it, c->at<double>(c->p.iter) + 2 * t, sizeof it, hipMemcpyDeviceToHost) != hipSuccess) {
-        c->flow_attached = false;
-        return false;
+    if (v.empty()) return NAN;
+    std::vector<double> t(v.end() - (ptrdiff_t)std::min(m, v.size()), v.end());
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
+}
+
+// Reads the GPU time of every finished iteration in the ring (both events
+// complete) and files its efficiency, relative variance x ms, under warped
+// or control.  Returns whether a new control efficiency arrived.
+bool judge_read_times(vegas_ctx* c, int upto)
+{
+    bool new_ctrl = false;
+    for (int slot = 0; slot < kJudgeRing; ++slot) {
+        const int it = c->f_ev_iter[slot];
+        if (it < 0 || it >= upto || it >= (int)c->log_I.size()) continue;
+        float ms = 0.f;
+        if (hipEventQuery(c->f_ev[2 * slot + 1]) != hipSuccess) continue;
+        if (hipEventElapsedTime(&ms, c->f_ev[2 * slot], c->f_ev[2 * slot + 1]) != hipSuccess) continue;
+        c->f_ev_iter[slot] = -1;
+        c->f_ms[it] = ms;
+        const double rv = rel_var(c->log_I[it], c->log_s2[it]);
+        if (c->warped[it] == 1 && std::isfinite(rv)) c->warp_eff.push_back(rv * ms);
+        if (c->warped[it] == 2) {
+            // a control whose estimate lies beyond 5 sigma of the kept warped
+            // estimate has missed the integrand's mass: plain VEGAS+ fails
+            double e = rv * ms;
+            if (c->kw_w > 0.0) {
+                const double Iw = c->kw_sum / c->kw_w;
+                if (std::fabs(c->log_I[it] - Iw) > 5.0 * std::sqrt(c->log_s2[it] + 1.0 / c->kw_w)) e = INFINITY;
+            }
+            if (!std::isfinite(rv)) e = INFINITY;
+            c->ctrl_eff.push_back(e);
+            new_ctrl = true;
+        }
     }
-    const double I = it[0], s2 = it[1];
-    // a single iteration's sigma^2 is a noisy figure: reject only what is
-    // clearly worse than plain VEGAS+ (twice its median)
-    bool ok = std::isfinite(I) && std::isfinite(s2) && s2 <= 2.0 * c->ref_s2;
-    if (ok && std::isfinite(c->ref_s2)) ok = std::fabs(I - c->ref_I) <= 5.0 * std::sqrt(s2 + c->ref_s2);
+    return new_ctrl;
+}
+
+// Event at the start (end = 0) or the end (end = 1) of iteration t while the
+// warp is on; the pair of an iteration lives in ring slot t mod kJudgeRing.
+hipError_t judge_mark(vegas_ctx* c, int t, int end)
+{
+    if (c->f_ev.empty()) {
+        c->f_ev.assign(2 * kJudgeRing, nullptr);
+        c->f_ev_iter.assign(kJudgeRing, -1);
+        for (auto& e : c->f_ev) {
+            const hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+        }
+    }
+    const int slot = t % kJudgeRing;
+    if (end == 0) c->f_ev_iter[slot] = t;
+    return hipEventRecord(c->f_ev[2 * slot + end], c->stream);
+}
+
+// The judge of warped iteration t (its estimate is read after a stream
+// synchronisation):
+//  guard: rejected when its estimate or variance is not finite, or its
+//    relative variance sigma^2/I^2 exceeds kJudgeGuard x the median of the
+//    last (up to 4) kept warped iterations (before any was kept: of the
+//    last plain iterations).  A rejected iteration restores the last kept
+//    parameters and restarts Adam; three rejections in a row switch the
+//    warp off.  Kept: its parameters become the kept ones.
+//  cost (judge = 2), after each control iteration: the warp's efficiency,
+//    the median relative variance x GPU ms of its last (up to 8) warped
+//    iterations, against the same for the last (up to 3) controls.  Not
+//    better twice in a row: the warp is switched off and plain VEGAS+
+//    continues.
+vegas_status flow_judge(vegas_ctx* c, int t, bool* keep)
+{
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int from = (int)c->log_I.size();
+    if (t + 1 > from) {
+        std::vector<double> buf(2 * (size_t)(t + 1 - from));
+        HIPCHK(hipMemcpy(buf.data(), c->at<double>(c->p.iter) + 2 * from, sizeof(double) * buf.size(),
+                         hipMemcpyDeviceToHost));
+        for (int i = 0; i < t + 1 - from; ++i) {
+            c->log_I.push_back(buf[2 * i]);
+            c->log_s2.push_back(buf[2 * i + 1]);
+        }
+    }
+    const double I = c->log_I[t], s2 = c->log_s2[t];
+    const double rv = rel_var(I, s2);
+    double ref = median_tail(c->kept_rv, 4);
+    if (!(ref >= 0.0)) {
+        std::vector<double> prv;
+        for (int i = t - 1; i >= 0 && prv.size() < 4; --i)
+            if (c->warped[i] != 1 && std::isfinite(rel_var(c->log_I[i], c->log_s2[i])))
+                prv.push_back(rel_var(c->log_I[i], c->log_s2[i]));
+        ref = median_tail(prv, 4);
+    }
+    bool ok = std::isfinite(I) && std::isfinite(s2) && std::isfinite(rv);
+    if (ok && ref >= 0.0 && std::isfinite(ref)) ok = rv <= kJudgeGuard * ref;
     float* th = reinterpret_cast<float*>(c->fws + c->f_theta);
     float* acc = reinterpret_cast<float*>(c->fws + c->f_acc);
     if (ok) {
         c->rejects = 0;
         c->n_accepted += 1;
-        (void)hipMemcpyAsync(acc, th, sizeof(float) * kFParams, hipMemcpyDeviceToDevice, c->stream);
-        return true;
+        c->kept_rv.push_back(rv);
+        if (c->fcfg.judge == 2 && s2 > 0.0) {
+            c->kw_sum += I / s2;
+            c->kw_w += 1.0 / s2;
+        }
+        HIPCHK(hipMemcpyAsync(acc, th, sizeof(float) * kFParams, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+        c->rejects += 1;
+        c->n_rejected += 1;
+        HIPCHK(hipMemcpyAsync(th, acc, sizeof(float) * kFParams, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(launch_flow_pack(th, c->fws + c->f_packed, c->stream));
+        HIPCHK(launch_reset(reinterpret_cast<unsigned long long*>(c->fws + c->f_m), kFParams / 2, c->stream));
+        HIPCHK(launch_reset(reinterpret_cast<unsigned long long*>(c->fws + c->f_v), kFParams / 2, c->stream));
+        c->f_step = 0;
+        if (c->rejects >= 3) c->flow_on = false;
     }
-    c->rejects += 1;
-    c->n_rejected += 1;
-    (void)hipMemcpyAsync(th, acc, sizeof(float) * kFParams, hipMemcpyDeviceToDevice, c->stream);
-    (void)launch_flow_pack(th, c->fws + c->f_packed, c->stream);
-    (void)launch_reset(reinterpret_cast<unsigned long long*>(c->fws + c->f_m), kFParams / 2, c->stream);
-    (void)launch_reset(reinterpret_cast<unsigned long long*>(c->fws + c->f_v), kFParams / 2, c->stream);
-    c->f_step = 0;
-    if (c->rejects >= 3) c->flow_on = false;
-    return false;
+    const bool new_ctrl = judge_read_times(c, t);
+    if (c->fcfg.judge == 2 && new_ctrl && !c->warp_eff.empty() && c->flow_on) {
+        const double ew = median_tail(c->warp_eff, 8), ep = median_tail(c->ctrl_eff, 3);
+        c->strikes = ew < ep ? 0 : c->strikes + 1;
+        if (c->strikes >= 2) c->flow_on = false;
+    }
+    *keep = ok;
+    return VEGAS_OK;
 }
 
 // one training step: gradient, Adam, BF16 repack
@@ -1130,6 +1288,21 @@ vegas_status flow_train_step(vegas_ctx* c)
     HIPCHK(launch_flow_adam(th, reinterpret_cast<const float*>(c->fws + c->f_grad), reinterpret_cast<float*>(c->fws + c->f_m),
                             reinterpret_cast<float*>(c->fws + c->f_v), c->fcfg.lr, c->f_step, c->stream));
     HIPCHK(launch_flow_pack(th, c->fws + c->f_packed, c->stream));
+    return VEGAS_OK;
+}
+
+// validated copy of a warp configuration, defaults filled in
+vegas_status flow_config_check(const vegas_flow_config* cfg, vegas_flow_config* out)
+{
+    if (!(cfg->lr >= 0.f) || !std::isfinite(cfg->lr)) return fail(VEGAS_EINVAL, "lr must be finite and >= 0");
+    if (cfg->loss != 0 && cfg->loss != 1) return fail(VEGAS_EINVAL, "loss must be 0 (variance) or 1 (KL)");
+    if (cfg->judge < 0 || cfg->judge > 2) return fail(VEGAS_EINVAL, "judge must be 0, 1 or 2");
+    if (cfg->steps_per_iter < 0 || cfg->steps_per_iter > 64) return fail(VEGAS_EINVAL, "steps_per_iter must be 0..64");
+    if (cfg->control_period != 0 && (cfg->control_period < 2 || cfg->control_period > 32))
+        return fail(VEGAS_EINVAL, "control_period must be 0 or 2..32");
+    *out = *cfg;
+    if (out->steps_per_iter == 0) out->steps_per_iter = 1;
+    if (out->control_period == 0) out->control_period = 16;
     return VEGAS_OK;
 }
 
@@ -1162,18 +1335,20 @@ vegas_status vegas_flow_workspace_size(const vegas_ctx* c, size_t* bytes)
 vegas_status vegas_flow_attach(vegas_ctx* c, const vegas_flow_config* cfg, const float* params, void* d_ws,
                                size_t bytes)
 {
-    if (!c || !cfg || !params || !d_ws) return fail(VEGAS_EINVAL, "bad arguments");
+    if (!c || !cfg || !d_ws) return fail(VEGAS_EINVAL, "bad arguments");
     vegas_status s = flow_check(c);
     if (s != VEGAS_OK) return s;
     if (((uintptr_t)d_ws & 255u) != 0) return fail(VEGAS_EINVAL, "flow workspace must be 256-byte aligned");
     const int nwg = flow_train_wg(c);
     const FlowPlan p = flow_plan(c->g.n_eval, nwg);
     if (bytes < p.total) return fail(VEGAS_ENOMEM, "flow workspace has %zu bytes, needs %zu", bytes, p.total);
-    if (!(cfg->lr >= 0.f) || !std::isfinite(cfg->lr)) return fail(VEGAS_EINVAL, "lr must be finite and >= 0");
-    if (cfg->loss != 0 && cfg->loss != 1) return fail(VEGAS_EINVAL, "loss must be 0 (variance) or 1 (KL)");
-    for (int i = 0; i < kFParams; ++i)
-        if (!std::isfinite(params[i])) return fail(VEGAS_EINVAL, "flow parameter %d is not finite", i);
-    c->fcfg = *cfg;
+    vegas_flow_config fc;
+    s = flow_config_check(cfg, &fc);
+    if (s != VEGAS_OK) return s;
+    if (params)
+        for (int i = 0; i < kFParams; ++i)
+            if (!std::isfinite(params[i])) return fail(VEGAS_EINVAL, "flow parameter %d is not finite", i);
+    c->fcfg = fc;
     c->fws = (unsigned char*)d_ws;
     c->f_theta = p.theta;
     c->f_packed = p.packed;
@@ -1194,10 +1369,35 @@ vegas_status vegas_flow_attach(vegas_ctx* c, const vegas_flow_config* cfg, const
     c->f_step = 0;
     c->flow_attached = true;
     c->flow_on = false;
-    HIPCHK(hipMemsetAsync(c->fws + p.m, 0, sizeof(float) * kFParams, c->stream));
-    HIPCHK(hipMemsetAsync(c->fws + p.v, 0, sizeof(float) * kFParams, c->stream));
-    HIPCHK(hipMemsetAsync(c->fws + p.om, 0, sizeof(float) * c->g.n_eval, c->stream));
-    return vegas_flow_set_params(c, params);
+    HIPCHK(launch_reset(reinterpret_cast<unsigned long long*>(c->fws + p.m), kFParams / 2, c->stream));
+    HIPCHK(launch_reset(reinterpret_cast<unsigned long long*>(c->fws + p.v), kFParams / 2, c->stream));
+    HIPCHK(launch_reset(reinterpret_cast<unsigned long long*>(c->fws + p.om), (int)((c->g.n_eval + 1) / 2), c->stream));
+    if (params) return vegas_flow_set_params(c, params);
+    // the library's own starting weights
+    float* th = reinterpret_cast<float*>(c->fws + c->f_theta);
+    HIPCHK(launch_flow_init(th, fc.init_seed, c->stream));
+    HIPCHK(launch_flow_pack(th, c->fws + c->f_packed, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return VEGAS_OK;
+}
+
+vegas_status vegas_flow_set_config(vegas_ctx* c, const vegas_flow_config* cfg)
+{
+    if (!c || !cfg) return fail(VEGAS_EINVAL, "bad arguments");
+    if (!c->flow_attached) return fail(VEGAS_ESTATE, "no flow attached");
+    vegas_flow_config fc;
+    const vegas_status s = flow_config_check(cfg, &fc);
+    if (s != VEGAS_OK) return s;
+    if (fc.judge != c->fcfg.judge) {
+        // a new judge mode starts its cost records afresh
+        c->warp_eff.clear();
+        c->ctrl_eff.clear();
+        c->kw_sum = c->kw_w = 0.0;
+        c->strikes = 0;
+    }
+    if (fc.control_period != c->fcfg.control_period) c->f_phase = 0;
+    c->fcfg = fc;
+    return VEGAS_OK;
 }
 
 vegas_status vegas_flow_enable(vegas_ctx* c, int32_t on)
@@ -1205,43 +1405,49 @@ vegas_status vegas_flow_enable(vegas_ctx* c, int32_t on)
     if (!c) return fail(VEGAS_EINVAL, "bad arguments");
     if (on && !c->flow_attached) return fail(VEGAS_ESTATE, "no flow attached");
     if (on && !c->flow_on) {
-        // the judge's reference: the last (up to five) plain iterations,
-        // median sigma^2 and inverse-variance mean
-        std::vector<double> I(c->n_run), s2(c->n_run);
-        if (c->n_run > 0) {
-            std::vector<double> buf(2 * (size_t)c->n_run);
-            HIPCHK(hipStreamSynchronize(c->stream));
-            HIPCHK(hipMemcpy(buf.data(), c->at<double>(c->p.iter), sizeof(double) * buf.size(), hipMemcpyDeviceToHost));
-            for (int t = 0; t < c->n_run; ++t) {
-                I[t] = buf[2 * t];
-                s2[t] = buf[2 * t + 1];
-            }
-        }
-        std::vector<double> rs2, rI;
-        for (int t = c->n_run - 1; t >= 0 && (int)rs2.size() < 5; --t)
-            if (!c->warped[t] && s2[t] > 0.0 && std::isfinite(s2[t])) {
-                rs2.push_back(s2[t]);
-                rI.push_back(I[t]);
-            }
-        if (rs2.empty()) {
-            c->ref_s2 = INFINITY;
-            c->ref_I = 0.0;
-        } else {
-            std::vector<double> sorted = rs2;
-            std::sort(sorted.begin(), sorted.end());
-            c->ref_s2 = sorted[sorted.size() / 2];
-            double w = 0.0, wi = 0.0;
-            for (size_t i = 0; i < rs2.size(); ++i) {
-                w += 1.0 / rs2[i];
-                wi += rI[i] / rs2[i];
-            }
-            c->ref_I = wi / w;
-        }
+        // the parameters now in place are the kept ones
         c->rejects = 0;
+        c->strikes = 0;
+        c->f_phase = 0;
         HIPCHK(hipMemcpyAsync(c->fws + c->f_acc, c->fws + c->f_theta, sizeof(float) * kFParams,
                               hipMemcpyDeviceToDevice, c->stream));
     }
     c->flow_on = on != 0;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_flow_set_timing(vegas_ctx* c, int32_t on)
+{
+    if (!c) return fail(VEGAS_EINVAL, "bad arguments");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (hipEvent_t e : c->f_tev) (void)hipEventDestroy(e);
+    c->f_tev.clear();
+    c->f_timing = on != 0;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_flow_get_timing(vegas_ctx* c, double* ms, int32_t* n_iter)
+{
+    if (!c || !ms) return fail(VEGAS_EINVAL, "bad arguments");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    ms[0] = ms[1] = 0.0;
+    int n = 0;
+    for (size_t i = 0; i + 4 <= c->f_tev.size(); i += 4, ++n) {
+        float a = 0.f, b = 0.f;
+        HIPCHK(hipEventElapsedTime(&a, c->f_tev[i], c->f_tev[i + 1]));
+        HIPCHK(hipEventElapsedTime(&b, c->f_tev[i + 2], c->f_tev[i + 3]));
+        ms[0] += a;
+        ms[1] += b;
+    }
+    if (n_iter) *n_iter = n;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_flow_get_kinds(vegas_ctx* c, int32_t* kinds, int32_t cap, int32_t* n)
+{
+    if (!c || !n) return fail(VEGAS_EINVAL, "bad arguments");
+    *n = c->n_run;
+    for (int t = 0; t < std::min(cap, c->n_run) && kinds; ++t) kinds[t] = c->warped[t];
     return VEGAS_OK;
 }
 
@@ -1293,6 +1499,22 @@ vegas_status vegas_flow_grad(vegas_ctx* c, float* grad)
     if (s != VEGAS_OK) return s;
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipMemcpy(grad, c->fws + c->f_grad, sizeof(float) * kFParams, hipMemcpyDeviceToHost));
+    return VEGAS_OK;
+}
+
+vegas_status vegas_flow_adam_step(vegas_ctx* c, const float* grad)
+{
+    if (!c || !grad) return fail(VEGAS_EINVAL, "bad arguments");
+    if (!c->flow_attached) return fail(VEGAS_ESTATE, "no flow attached");
+    for (int i = 0; i < kFParams; ++i)
+        if (!std::isfinite(grad[i])) return fail(VEGAS_EINVAL, "gradient entry %d is not finite", i);
+    HIPCHK(hipMemcpyAsync(c->fws + c->f_grad, grad, sizeof(float) * kFParams, hipMemcpyHostToDevice, c->stream));
+    c->f_step += 1;
+    float* th = reinterpret_cast<float*>(c->fws + c->f_theta);
+    HIPCHK(launch_flow_adam(th, reinterpret_cast<const float*>(c->fws + c->f_grad), reinterpret_cast<float*>(c->fws + c->f_m),
+                            reinterpret_cast<float*>(c->fws + c->f_v), c->fcfg.lr, c->f_step, c->stream));
+    HIPCHK(launch_flow_pack(th, c->fws + c->f_packed, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
     return VEGAS_OK;
 }
 
@@ -1380,6 +1602,10 @@ vegas_status vegas_set_state(vegas_ctx* c, const void* buf, size_t bytes)
     o += sizeof(double) * 2 * h.n_run;
     c->combined.assign(o, o + h.n_run);
     c->warped.assign(h.n_run, 0);
+    c->f_ms.assign(h.n_run, NAN);
+    c->log_I.clear();
+    c->log_s2.clear();
+    if (!c->f_ev_iter.empty()) c->f_ev_iter.assign(c->f_ev_iter.size(), -1);
     c->n_run = h.n_run;
     c->have_prev = h.have_prev != 0;
     unsigned long long bad = h.nonfinite;

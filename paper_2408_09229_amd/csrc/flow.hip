@@ -77,6 +77,30 @@ __global__ void k_flow_pack(const float* __restrict__ theta, bf16x8* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// starting weights: W1 and W2 uniform in +-1/sqrt(fan_in) (fan_in 8 and 64),
+// every other parameter 0.  The zero last layer makes every bin probability
+// exactly 1/16, so F starts as the identity.  Parameter i draws word 0 of
+// Philox4x32-10 with key = seed and counter (i, 0, 0, "FLOW"); its top 23
+// bits m give the odd multiple (2m + 1 - 2^23) 2^-23 of the unit interval's
+// half width, exact in FP32, which the bound then scales (one rounding).
+// ---------------------------------------------------------------------------
+__global__ void k_flow_init(float* __restrict__ theta, uint32_t key0, uint32_t key1)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kFParams) return;
+    const int r = i % kFLayer;
+    const float bound = r < kFB1 ? 0.35355339059327376f : (r >= kFW2 && r < kFB2) ? 0.125f : 0.f;
+    float v = 0.f;
+    if (bound != 0.f) {
+        const PhiloxKeys K = philox_keys<false>(key0, key1);
+        const W4 o = philox10((uint32_t)i, 0u, 0u, 0x464C4F57u, K);
+        const int m = (int)(o.v[0] >> 9);
+        v = (float)(2 * m + 1 - (1 << 23)) * 0x1p-23f * bound;
+    }
+    theta[i] = v;
+}
+
+// ---------------------------------------------------------------------------
 // operand layout check: D = A B for one 32x32x16 product (A 32x16 and B
 // 16x32 row-major FP32, rounded to BF16; D 32x32 FP32).  One wavefront.
 // ---------------------------------------------------------------------------
@@ -110,7 +134,7 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_sample(FlowSampleArgs a)
     const uint32_t per_round = gridDim.x * kFlowWaves;
     const uint32_t rounds = (chunks + per_round - 1u) / per_round;
     const bf16x8* pk = reinterpret_cast<const bf16x8*>(a.packed);
-    const float inv_nst = 1.f / (float)sc.nst;
+    const double den = (double)sc.nst * 0x1p33;
     for (uint32_t rd = 0; rd < rounds; ++rd) {
         // every wave runs every round (the layers synchronise the workgroup)
         const uint32_t chunk = rd * per_round + blockIdx.x * kFlowWaves + wave;
@@ -129,6 +153,9 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_sample(FlowSampleArgs a)
             dig[d] = hc - q * sc.nst;
             hc = q;
         }
+        // the stratified point y = (s 2^33 + 2r + 1) / (N_st 2^33): the
+        // numerator is exact in FP64 (s < 2^20), one FP64 division, then
+        // rounded to FP32
         float z[8];
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
@@ -136,8 +163,8 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_sample(FlowSampleArgs a)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int j = 4 * b + q;
-                const float u = ((float)o.v[q] + 0.5f) * 0x1p-32f;
-                z[j] = ((float)dig[8 * half + j] + u) * inv_nst;
+                const double num = fma((double)dig[8 * half + j], 0x1p33, 2.0 * (double)o.v[q] + 1.0);
+                z[j] = (float)(num / den);
             }
         }
         float lj = 0.f;
@@ -185,6 +212,7 @@ struct WarpedPath {
     const SampleConst& sc;
     Fn<float, FAM> fn;
     float ngR;
+    double ngD;
     const float* w;
     const float* lj;
     float* om;
@@ -195,6 +223,7 @@ struct WarpedPath {
     {
         fn.setup(c, aux);
         ngR = (float)c.ng;
+        ngD = (double)c.ng;
     }
     __device__ __forceinline__ void digits(uint32_t, uint32_t (&)[kFlowDim]) const {}
     __device__ __forceinline__ void next_digits(uint32_t (&)[kFlowDim]) const {}
@@ -217,11 +246,14 @@ struct WarpedPath {
         fn.begin();
         const uint32_t row = sc.ng + 1u;
         const int top = (int)sc.ng - 1;
+        // bin and offset of w in the map, exactly: w N_g (w FP32, N_g <=
+        // 4096) is exact in FP64, so are its floor and the remainder, which
+        // is rounded once to FP32
 #pragma unroll
         for (int d = 0; d < kFlowDim; ++d) {
-            const float u = wv[d] * ngR;
+            const double u = (double)wv[d] * ngD;
             const int bin = min((int)u, top);
-            const float delta = u - (float)bin;
+            const float delta = (float)(u - (double)bin);
             bins[d] = (uint32_t)bin;
             const float* gd = g + d * row;
             const float xl = gd[bin];
@@ -304,6 +336,13 @@ hipError_t launch_flow_pack(const float* theta, void* packed, hipStream_t st)
     return hipGetLastError();
 }
 
+hipError_t launch_flow_init(float* theta, uint64_t seed, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_flow_init, dim3((kFParams + 255) / 256), dim3(256), 0, st, theta, (uint32_t)seed,
+                       (uint32_t)(seed >> 32));
+    return hipGetLastError();
+}
+
 hipError_t launch_mfma_probe(const float* A, const float* B, float* D, hipStream_t st)
 {
     hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, st, A, B, D);
@@ -321,10 +360,14 @@ static hipError_t launch_fill_flow_fam(const FillArgs& a, const float* w, const 
                                        size_t lds, hipStream_t st)
 {
     if (a.accum == 1) {
-        hipFuncSetAttribute((const void*)k_fill_flow<FAM, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        const hipError_t e = hipFuncSetAttribute((const void*)k_fill_flow<FAM, true>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_fill_flow<FAM, true>), dim3(n_wg), dim3(kFillThreads), lds, st, a, w, lj, om);
     } else {
-        hipFuncSetAttribute((const void*)k_fill_flow<FAM, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        const hipError_t e = hipFuncSetAttribute((const void*)k_fill_flow<FAM, false>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_fill_flow<FAM, false>), dim3(n_wg), dim3(kFillThreads), lds, st, a, w, lj, om);
     }
     return hipGetLastError();

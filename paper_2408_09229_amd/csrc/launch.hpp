@@ -81,6 +81,7 @@ hipError_t launch_batch_map(const BatchArgs& a, int max_ng, hipStream_t st);
 hipError_t launch_batch_prep(const BatchArgs& a, hipStream_t st);
 
 hipError_t launch_flow_pack(const float* theta, void* packed, hipStream_t st);
+hipError_t launch_flow_init(float* theta, uint64_t seed, hipStream_t st);
 hipError_t launch_mfma_probe(const float* A, const float* B, float* D, hipStream_t st);
 hipError_t launch_flow_sample(const FlowSampleArgs& a, int n_wg, hipStream_t st);
 hipError_t launch_fill_flow(const FillArgs& a, const float* w, const float* lj, float* om, int n_wg, size_t lds,

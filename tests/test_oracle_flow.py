@@ -149,3 +149,26 @@ def test_training_lowers_variance():
     v1, m1 = var_of(th)
     assert abs(m0 - 1) < 0.1 and abs(m1 - 1) < 0.1      # unbiased both ways
     assert v1 < 0.8 * v0, (v0, v1)
+
+
+def test_adam_two_steps_by_hand():
+    """Adam (Kingma & Ba) worked by hand for one coordinate, lr 0.1.
+
+    A constant gradient g: after the bias correction the first moment is g
+    and the second g^2 at every step, so each step moves by lr g/(|g| + eps).
+    A gradient that flips sign, g then -g: m_2 = 0.9 (0.1 g) - 0.1 g = -0.01 g,
+    corrected by 1 - 0.9^2 = 0.19 to -g/19; v_2 = 0.999 (0.001 g^2) + 0.001 g^2
+    = 0.001999 g^2, corrected by 1 - 0.999^2 = 0.001999 to g^2; so the second
+    step moves by +lr/19 (for g > 0).  Without the bias correction the first
+    step would be lr 0.1 g / sqrt(0.001) g = 3.16 lr."""
+    lr, g = 0.1, 0.5
+    th = np.array([1.0])
+    m = np.zeros(1)
+    v = np.zeros(1)
+    th1, m, v = fl.adam(th, np.array([g]), m, v, 1, lr)
+    assert abs(th1[0] - (1.0 - lr * g / (g + 1e-8))) < 1e-15
+    th2, m2, v2 = fl.adam(th1, np.array([g]), m, v, 2, lr)
+    assert abs(th2[0] - (th1[0] - lr * g / (g + 1e-8))) < 1e-15
+    th2f, m2f, v2f = fl.adam(th1, np.array([-g]), m, v, 2, lr)
+    assert abs(m2f[0] - (-0.01 * g)) < 1e-15 and abs(v2f[0] - 0.001999 * g * g) < 1e-17
+    assert abs(th2f[0] - (th1[0] + lr * (g / 19.0) / (g + 1e-8))) < 1e-12

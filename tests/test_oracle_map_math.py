@@ -137,3 +137,18 @@ def test_combine_by_hand(orc):
     assert I == 2.5 and s2 == 0.25 and chi == 0.0
     I, s2, chi = orc.combine([1.0, 1.0, 4.0], [1.0, 1.0, 1.0])
     assert I == 2.0 and abs(s2 - 1 / 3) < 1e-16 and chi == (1 + 1 + 4) / 2
+
+
+def test_combine_empty_iterations(orc):
+    """An iteration whose weights were all zero (I = 0 and sigma^2 = 0) is
+    left out when another iteration saw a nonzero estimate; if every one is
+    empty the result is 0 with sigma^2 0.  By hand: weights 100 and 25 give
+    (100 * 1.0 + 25 * 1.2) / 125 = 1.04 and sigma^2 = 1/125; chi^2 over the
+    two informative iterations is (100 * 0.04^2 + 25 * 0.16^2) / 1 = 0.8."""
+    I, s2, chi = orc.combine([0.0, 1.0, 1.2], [0.0, 0.01, 0.04])
+    assert abs(I - 1.04) < 1e-15 and abs(s2 - 0.008) < 1e-17 and abs(chi - 0.8) < 1e-14
+    I, s2, chi = orc.combine([0.0, 0.0], [0.0, 0.0])
+    assert I == 0.0 and s2 == 0.0 and chi == 0.0
+    # an exact nonzero iteration still decides the result over an empty one
+    I, s2, chi = orc.combine([0.0, 2.0, 1.9], [0.0, 0.0, 0.5])
+    assert I == 2.0 and s2 == 0.0
