@@ -350,14 +350,15 @@ def warp_run(args, w, method: str, exact: float):
     v = Vegas(cfg, w.family, warm[0])
     if method == "warp":
         v.attach_flow(None, lr=args.flow_lr, train=True, loss=args.flow_loss, judge="guard",
-                      steps_per_iter=args.flow_steps, control_period=16, init_seed=w.seed)
+                      steps_per_iter=args.flow_steps, control_period=16, train_stride=args.train_stride,
+                      init_seed=w.seed)
         v.enable_flow(True)
     for p in warm:
         v.set_params(p)
         v.adapt(per)
     if method == "warp":
         v.set_flow_config(lr=args.flow_lr, train=True, loss="variance", judge="cost",
-                          steps_per_iter=args.flow_steps, control_period=16)
+                          steps_per_iter=args.flow_steps, control_period=16, train_stride=args.train_stride)
     n0 = len(warm) * per
     n = 0
     rel = math.inf
@@ -403,7 +404,7 @@ def run_warp_compare(args, w):
     # throughput of the warped iteration as the run left it: W more
     # iterations untimed, then K timed between events on the library's stream
     v.set_flow_config(lr=args.flow_lr, train=True, loss="variance", judge="guard",
-                      steps_per_iter=args.flow_steps, control_period=16)
+                      steps_per_iter=args.flow_steps, control_period=16, train_stride=args.train_stride)
     v.integrate(args.warmup)
     torch.cuda.synchronize()
     v.set_timing(True)
@@ -444,6 +445,7 @@ def run_warp_compare(args, w):
                    "caps": {"iterations": args.cap_iters, "seconds": args.cap_seconds},
                    "warmup": f"continuation over {args.cont_steps} steps x {args.cont_iters} iterations",
                    "warp": {"lr": args.flow_lr, "adam_steps_per_iteration": args.flow_steps,
+                            "train_stride": args.train_stride,
                             "warmup_loss": args.flow_loss, "control_period": 16},
                    "parallelism": "single-gpu"},
         "time_to_target_s": {"warp": wp["wall_s"] if wp["reached"] else None,
@@ -502,6 +504,8 @@ def main():
     ap.add_argument("--cont-iters", type=int, default=2, help="warp comparison: iterations per step")
     ap.add_argument("--flow-lr", type=float, default=1e-3, help="warp comparison: Adam step of the warp")
     ap.add_argument("--flow-steps", type=int, default=1, help="warp comparison: Adam steps per iteration")
+    ap.add_argument("--train-stride", type=int, default=1,
+                    help="warp comparison: a training step uses every n-th sample of the iteration")
     ap.add_argument("--flow-loss", default="variance", choices=["variance", "kl"],
                     help="warp comparison: training loss during the warm-up")
     args = ap.parse_args()

@@ -65,7 +65,10 @@ enum {
     VEGAS_LINEAR = 5,       /* A sum_d x_d                               : [A]  (Tab. 3 #2) */
     VEGAS_ROOS = 6,         /* A prod_d |4 x_d - 2|                      : [A]  (Tab. 3 #5) */
     VEGAS_CONST = 7,        /* A                                         : [A] */
-    VEGAS_COSINE = 8        /* A prod_d cos x_d                          : [A]  (Tab. 3 #3) */
+    VEGAS_COSINE = 8,       /* A prod_d cos x_d                          : [A]  (Tab. 3 #3) */
+    VEGAS_SIN_EXP = 9,      /* A (sin x_0 + exp x_1), dim >= 2           : [A]  (Tab. 3 #1) */
+    VEGAS_EXP_SQ = 10,      /* A exp(sum_d x_d^2)                        : [A]  (Tab. 3 #4) */
+    VEGAS_MOROKOFF = 11     /* A (1 + 1/D)^D prod_d x_d^(1/D), box x >= 0: [A]  (Tab. 3 #6) */
 };
 
 /* Problem parameters (Tab. 2: n_intervals, alpha, beta).  Copied at create. */
@@ -233,6 +236,8 @@ typedef struct {
     int32_t  steps_per_iter;  /* Adam steps after each kept warped iteration, 0..64 (0 = 1) */
     int32_t  control_period;  /* judge > 0: every control_period-th iteration of the warp's
                                  phase samples plain VEGAS+; 0 (= 16) or 2..32 */
+    int32_t  train_stride;    /* a training step uses every train_stride-th sample of the
+                                 iteration (offset turning with the steps); 0 (= 1) .. 1024 */
     uint64_t init_seed;       /* seed of the library's starting weights (params NULL at attach) */
 } vegas_flow_config;
 

@@ -205,12 +205,15 @@ ORC_EXPORT void orc_point(uint32_t s, uint32_t r, uint32_t n_strat, uint32_t n_g
 /*  6 ROOS        A*prod_d |4 x_d - 2|                      [A]                 */
 /*  7 CONST       A                                         [A]                 */
 /*  8 COSINE      A*prod_d cos x_d                          [A]                 */
+/*  9 SIN_EXP     A*(sin x_0 + exp x_1), D >= 2             [A]   (Tab. 3 #1)   */
+/* 10 EXP_SQ      A*exp(sum_d x_d^2)                        [A]   (Tab. 3 #4)   */
+/* 11 MOROKOFF    A*(1 + 1/D)^D prod_d x_d^(1/D), x >= 0    [A]   (Tab. 3 #6)   */
 /* All are written as the formula reads, in FP64 with libm.                    */
 /* Pinned by closed-form integrals (erf, arctan, polynomial).                  */
 /* ------------------------------------------------------------------------ */
 enum { ORC_GAUSS_DIAG = 1, ORC_GENZ_PPEAK = 2, ORC_GENZ_GAUSS = 3,
        ORC_GAUSS_CORR = 4, ORC_LINEAR = 5, ORC_ROOS = 6, ORC_CONST = 7,
-       ORC_COSINE = 8 };
+       ORC_COSINE = 8, ORC_SIN_EXP = 9, ORC_EXP_SQ = 10, ORC_MOROKOFF = 11 };
 
 ORC_EXPORT double orc_integrand(int family, int D, const double* p, const double* x)
 {
@@ -275,6 +278,19 @@ ORC_EXPORT double orc_integrand(int family, int D, const double* p, const double
     case ORC_COSINE: {
         double f = p[0];
         for (int d = 0; d < D; ++d) f *= cos(x[d]);
+        return f;
+    }
+    case ORC_SIN_EXP:
+        if (D < 2) return NAN;
+        return p[0] * (sin(x[0]) + exp(x[1]));
+    case ORC_EXP_SQ: {
+        double q = 0.0;
+        for (int d = 0; d < D; ++d) q += x[d] * x[d];
+        return p[0] * exp(q);
+    }
+    case ORC_MOROKOFF: {
+        double f = p[0] * pow(1.0 + 1.0 / D, (double)D);
+        for (int d = 0; d < D; ++d) f *= pow(x[d], 1.0 / D);
         return f;
     }
     default:

@@ -61,7 +61,8 @@ class vegas_info(C.Structure):
 
 class vegas_flow_config(C.Structure):
     _fields_ = [("lr", C.c_float), ("train", C.c_int32), ("loss", C.c_int32), ("judge", C.c_int32),
-                ("steps_per_iter", C.c_int32), ("control_period", C.c_int32), ("init_seed", C.c_uint64)]
+                ("steps_per_iter", C.c_int32), ("control_period", C.c_int32), ("train_stride", C.c_int32),
+                ("init_seed", C.c_uint64)]
 
 
 class vegas_batch_info(C.Structure):
@@ -308,13 +309,14 @@ class Vegas:
 
     # -- learned warp -------------------------------------------------------
     @staticmethod
-    def _flow_config(lr, train, loss, judge, steps_per_iter, control_period, init_seed):
+    def _flow_config(lr, train, loss, judge, steps_per_iter, control_period, train_stride, init_seed):
         j = {False: 0, True: 1, 0: 0, 1: 1, 2: 2, "guard": 1, "cost": 2}[judge]
         return vegas_flow_config(lr, int(train), {"variance": 0, "kl": 1}[loss], j, steps_per_iter,
-                                 control_period, init_seed)
+                                 control_period, train_stride, init_seed)
 
     def attach_flow(self, params=None, lr: float = 1e-4, train: bool = False, loss: str = "variance",
-                    judge=0, steps_per_iter: int = 1, control_period: int = 16, init_seed: int = 0):
+                    judge=0, steps_per_iter: int = 1, control_period: int = 16, train_stride: int = 1,
+                    init_seed: int = 0):
         """Attach a coupling-flow warp: initial FP32 parameters ``params``, or
         None for the library's own seeded starting weights (identity warp).
         ``judge``: 0 / False none, 1 / True / "guard", 2 / "cost"."""
@@ -327,13 +329,15 @@ class Vegas:
             p = np.ascontiguousarray(params, dtype=np.float32)
             if p.size != vegas_flow_n_params():
                 raise ValueError("wrong number of flow parameters")
-        self.fcfg = self._flow_config(lr, train, loss, judge, steps_per_iter, control_period, init_seed)
+        self.fcfg = self._flow_config(lr, train, loss, judge, steps_per_iter, control_period, train_stride,
+                                      init_seed)
         check(vegas_flow_attach(self.h, C.byref(self.fcfg), _dptr(p), C.c_void_p(self.fws.data_ptr()), n.value),
               "vegas_flow_attach")
 
     def set_flow_config(self, lr: float = 1e-4, train: bool = False, loss: str = "variance", judge=0,
-                        steps_per_iter: int = 1, control_period: int = 16):
-        self.fcfg = self._flow_config(lr, train, loss, judge, steps_per_iter, control_period, self.fcfg.init_seed)
+                        steps_per_iter: int = 1, control_period: int = 16, train_stride: int = 1):
+        self.fcfg = self._flow_config(lr, train, loss, judge, steps_per_iter, control_period, train_stride,
+                                      self.fcfg.init_seed)
         check(vegas_flow_set_config(self.h, C.byref(self.fcfg)), "vegas_flow_set_config")
 
     def set_flow_timing(self, on: bool):

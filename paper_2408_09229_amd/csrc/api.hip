@@ -66,7 +66,10 @@ int family_params(int fam, int D, const vegas_integrand* f)
     case VEGAS_LINEAR:
     case VEGAS_ROOS:
     case VEGAS_CONST:
-    case VEGAS_COSINE: return 1;
+    case VEGAS_COSINE:
+    case VEGAS_SIN_EXP:
+    case VEGAS_EXP_SQ:
+    case VEGAS_MOROKOFF: return 1;
     default: return -1;
     }
 }
@@ -105,6 +108,10 @@ vegas_status geometry(const vegas_config* c, const vegas_integrand* f, Geometry*
         if (!std::isfinite(lo) || !std::isfinite(hi) || !(lo < hi)) return fail(VEGAS_EINVAL, "bad box on axis %d", d);
     }
     if (f->family == VEGAS_GAUSS_DIAG && !(f->params[1] > 0.0)) return fail(VEGAS_EINVAL, "GAUSS_DIAG needs s > 0");
+    if (f->family == VEGAS_SIN_EXP && c->dim < 2) return fail(VEGAS_EINVAL, "SIN_EXP needs dim >= 2");
+    if (f->family == VEGAS_MOROKOFF)
+        for (int d = 0; d < c->dim; ++d)
+            if (f->lo && !(f->lo[d] >= 0.0)) return fail(VEGAS_EINVAL, "MOROKOFF needs a box in x >= 0");
     if (f->family == VEGAS_GAUSS_CORR) {
         const double s = f->params[1], rho = f->params[2];
         if (!(s > 0.0) || !(rho < 1.0) || !(1.0 + (c->dim - 1) * rho > 0.0))
@@ -1120,10 +1127,13 @@ int flow_train_wg(const vegas_ctx* c)
     return std::max(1, std::min(c->n_cus, chunks));
 }
 
-FlowTrainArgs flow_train_args(vegas_ctx* c)
+// the training samples are off, off + stride, ... of the iteration's samples
+FlowTrainArgs flow_train_args(vegas_ctx* c, uint32_t stride, uint32_t off)
 {
     FlowTrainArgs a;
-    a.n = c->g.n_eval;
+    a.n = (c->g.n_eval - off + stride - 1) / stride;
+    a.stride = stride;
+    a.off = off;
     a.layer = 0;
     a.theta = reinterpret_cast<const float*>(c->fws + c->f_theta);
     a.packed = c->fws + c->f_packed;
@@ -1139,9 +1149,10 @@ FlowTrainArgs flow_train_args(vegas_ctx* c)
 }
 
 // gradient of the warp's loss on the last warped iteration's samples
-vegas_status flow_gradient(vegas_ctx* c)
+// off, off + stride, ...
+vegas_status flow_gradient(vegas_ctx* c, uint32_t stride, uint32_t off)
 {
-    HIPCHK(launch_flow_gradient(flow_train_args(c), c->f_nwg, reinterpret_cast<float*>(c->fws + c->f_G0),
+    HIPCHK(launch_flow_gradient(flow_train_args(c, stride, off), c->f_nwg, reinterpret_cast<float*>(c->fws + c->f_G0),
                                 reinterpret_cast<float*>(c->fws + c->f_G1), reinterpret_cast<float*>(c->fws + c->f_grad),
                                 reinterpret_cast<float*>(c->fws + c->f_seg), c->stream));
     return VEGAS_OK;
@@ -1281,7 +1292,9 @@ vegas_status flow_judge(vegas_ctx* c, int t, bool* keep)
 // one training step: gradient, Adam, BF16 repack
 vegas_status flow_train_step(vegas_ctx* c)
 {
-    vegas_status s = flow_gradient(c);
+    // a strided subset of the samples, its offset turning with the steps
+    const uint32_t stride = (uint32_t)std::min<int64_t>(c->fcfg.train_stride, c->g.n_eval);
+    vegas_status s = flow_gradient(c, stride, (uint32_t)(c->f_step % stride));
     if (s != VEGAS_OK) return s;
     c->f_step += 1;
     float* th = reinterpret_cast<float*>(c->fws + c->f_theta);
@@ -1300,8 +1313,10 @@ vegas_status flow_config_check(const vegas_flow_config* cfg, vegas_flow_config* 
     if (cfg->steps_per_iter < 0 || cfg->steps_per_iter > 64) return fail(VEGAS_EINVAL, "steps_per_iter must be 0..64");
     if (cfg->control_period != 0 && (cfg->control_period < 2 || cfg->control_period > 32))
         return fail(VEGAS_EINVAL, "control_period must be 0 or 2..32");
+    if (cfg->train_stride < 0 || cfg->train_stride > 1024) return fail(VEGAS_EINVAL, "train_stride must be 0..1024");
     *out = *cfg;
     if (out->steps_per_iter == 0) out->steps_per_iter = 1;
+    if (out->train_stride == 0) out->train_stride = 1;
     if (out->control_period == 0) out->control_period = 16;
     return VEGAS_OK;
 }
@@ -1495,7 +1510,7 @@ vegas_status vegas_flow_grad(vegas_ctx* c, float* grad)
 {
     if (!c || !grad) return fail(VEGAS_EINVAL, "bad arguments");
     if (!c->flow_attached) return fail(VEGAS_ESTATE, "no flow attached");
-    const vegas_status s = flow_gradient(c);
+    const vegas_status s = flow_gradient(c, 1, 0);
     if (s != VEGAS_OK) return s;
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipMemcpy(grad, c->fws + c->f_grad, sizeof(float) * kFParams, hipMemcpyDeviceToHost));

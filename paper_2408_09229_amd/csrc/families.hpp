@@ -19,7 +19,8 @@
 namespace vg {
 
 enum : int { F_GAUSS_DIAG = 1, F_GENZ_PPEAK = 2, F_GENZ_GAUSS = 3, F_GAUSS_CORR = 4,
-             F_LINEAR = 5, F_ROOS = 6, F_CONST = 7, F_COSINE = 8 };
+             F_LINEAR = 5, F_ROOS = 6, F_CONST = 7, F_COSINE = 8, F_SIN_EXP = 9, F_EXP_SQ = 10,
+             F_MOROKOFF = 11 };
 
 constexpr double kLn2 = 0.69314718055994530942;
 
@@ -258,6 +259,72 @@ struct Fn<R, F_CONST> {
     __device__ __forceinline__ void begin() {}
     __device__ __forceinline__ void axis(int, R) {}
     __device__ __forceinline__ R finish() const { return A; }
+};
+
+// Tab. 3 #1: A (sin x_0 + exp x_1); the other axes do not enter
+template <typename R>
+struct Fn<R, F_SIN_EXP> {
+    R A, a, b;
+    __device__ __forceinline__ void setup(const SampleConst& sc, const R*) { A = (R)sc.prm[0]; }
+    __device__ __forceinline__ void begin() { a = 0; b = 0; }
+    __device__ __forceinline__ void axis(int d, R x)
+    {
+        if constexpr (std::is_same<R, double>::value) {
+            if (d == 0) a = sin(x);
+            else if (d == 1) b = exp(x);
+        } else {
+            if (d == 0) a = sinf(x);
+            else if (d == 1) b = exp2_fast(x * 1.44269504088896341f);
+        }
+    }
+    __device__ __forceinline__ R finish() const { return A * (a + b); }
+};
+
+// Tab. 3 #4: A exp(sum_d x_d^2)
+template <typename R>
+struct Fn<R, F_EXP_SQ> {
+    R A, q;
+    __device__ __forceinline__ void setup(const SampleConst& sc, const R*) { A = (R)sc.prm[0]; }
+    __device__ __forceinline__ void begin() { q = 0; }
+    __device__ __forceinline__ void axis(int, R x)
+    {
+        if constexpr (std::is_same<R, double>::value) q = q + x * x;
+        else q = fmaf(x, x, q);
+    }
+    __device__ __forceinline__ R finish() const
+    {
+        if constexpr (std::is_same<R, double>::value) return A * exp(q);
+        else return A * exp2_fast(q * 1.44269504088896341f);
+    }
+};
+
+// Tab. 3 #6 (Morokoff & Caflisch): A (1 + 1/D)^D prod_d x_d^(1/D).  FP64
+// factor by factor with pow; FP32 as 2^(sum_d log2 x_d / D) on the
+// hardware log2 and exp2.
+template <typename R>
+struct Fn<R, F_MOROKOFF> {
+    R c, e, p;
+    __device__ __forceinline__ void setup(const SampleConst& sc, const R*)
+    {
+        const double D = (double)sc.D;
+        c = (R)(sc.prm[0] * pow(1.0 + 1.0 / D, D));
+        e = (R)(1.0 / D);
+    }
+    __device__ __forceinline__ void begin()
+    {
+        if constexpr (std::is_same<R, double>::value) p = c;
+        else p = 0.f;
+    }
+    __device__ __forceinline__ void axis(int, R x)
+    {
+        if constexpr (std::is_same<R, double>::value) p = p * pow(x, e);
+        else p = p + __builtin_amdgcn_logf(x);
+    }
+    __device__ __forceinline__ R finish() const
+    {
+        if constexpr (std::is_same<R, double>::value) return p;
+        else return c * exp2_fast(p * e);
+    }
 };
 
 template <typename R>

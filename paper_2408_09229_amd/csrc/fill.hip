@@ -223,6 +223,9 @@ static hipError_t launch_probe_fam(const ProbeArgs& a, hipStream_t st)
     case F_ROOS: return CALL<R, F_ROOS>(__VA_ARGS__);                          \
     case F_CONST: return CALL<R, F_CONST>(__VA_ARGS__);                        \
     case F_COSINE: return CALL<R, F_COSINE>(__VA_ARGS__);                      \
+    case F_SIN_EXP: return CALL<R, F_SIN_EXP>(__VA_ARGS__);                    \
+    case F_EXP_SQ: return CALL<R, F_EXP_SQ>(__VA_ARGS__);                      \
+    case F_MOROKOFF: return CALL<R, F_MOROKOFF>(__VA_ARGS__);                  \
     default: return hipErrorInvalidValue;                                      \
     }
 

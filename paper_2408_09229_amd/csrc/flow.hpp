@@ -76,17 +76,18 @@ struct FlowSampleArgs {
 // (l = 0, 1, 2, 3) turns the upstream gradient g = dL/du_{l-1} into
 // dL/du_l and the layer's parameter gradient.
 struct FlowTrainArgs {
-    uint32_t n;                   // samples
+    uint32_t n;                   // training samples: j = 0 .. n-1 is sample off + j stride
+    uint32_t stride, off;
     int32_t layer;                // backward pass: layer index
     const float* theta;
     const void* packed;
-    const float* w;               // [N][16]
-    const float* om;              // [N] sample weights
+    const float* w;               // [N_ev][16], read at the training samples
+    const float* om;              // [N_ev] sample weights, read at the training samples
     const double* sumsq;          // sum of |om|^gamma
     int32_t gamma;                // 2: variance loss, 1: KL loss
-    float* U;                     // [3][N][16]: u_0, u_1, u_2
-    const float* g_in;            // [N][16] upstream gradient (null: zero)
-    float* g_out;                 // [N][16]
+    float* U;                     // [3][n][16]: u_0, u_1, u_2 of the training samples
+    const float* g_in;            // [n][16] upstream gradient (null: zero)
+    float* g_out;                 // [n][16]
     float* part;                  // [n_wg][kFLayer] per-workgroup gradient
 };
 

@@ -31,12 +31,13 @@ constexpr int kSumBlocks = 256;
 
 // sum of |omega|^gamma, gamma = 2 (variance loss) or 1 (KL loss): block
 // partials (strided samples), then the partials in block order
-__global__ __launch_bounds__(kSumThreads) void k_flow_sumsq(const float* om, uint32_t n, int gamma, double* part)
+__global__ __launch_bounds__(kSumThreads) void k_flow_sumsq(const float* om, uint32_t n, uint32_t stride, uint32_t off,
+                                                            int gamma, double* part)
 {
     __shared__ double red[kSumThreads];
     double s = 0.0;
     for (uint32_t i = blockIdx.x * kSumThreads + threadIdx.x; i < n; i += kSumThreads * kSumBlocks) {
-        const double v = fabs((double)om[i]);
+        const double v = fabs((double)om[(size_t)off + (size_t)i * stride]);
         s += gamma == 2 ? v * v : v;
     }
     red[threadIdx.x] = s;
@@ -81,7 +82,8 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_inverse(FlowTrainArgs a)
         const uint32_t k = live ? min(chunk * 32u + (uint32_t)n32, N - 1u) : 0u;
         const bool valid = live && chunk * 32u + (uint32_t)n32 < N;
         float z[8];
-        const float4* wi = reinterpret_cast<const float4*>(a.w + (size_t)k * kFlowDim + 8 * half);
+        const size_t src = (size_t)a.off + (size_t)k * a.stride;
+        const float4* wi = reinterpret_cast<const float4*>(a.w + src * kFlowDim + 8 * half);
         const float4 w0 = wi[0], w1 = wi[1];
         z[0] = w0.x; z[1] = w0.y; z[2] = w0.z; z[3] = w0.w;
         z[4] = w1.x; z[5] = w1.y; z[6] = w1.z; z[7] = w1.w;
@@ -144,7 +146,10 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_grad(FlowTrainArgs a)
     const uint32_t N = a.n;
     const float* P = a.theta + (size_t)l * kFLayer;
     const bf16x8* pk = reinterpret_cast<const bf16x8*>(a.packed) + (size_t)l * kPLayer;
-    const float* uin = l == kFlowLayers - 1 ? a.w : a.U + (size_t)l * N * kFlowDim;
+    // the last layer reads w itself at the training samples, the others
+    // the compact inverse-pass outputs
+    const bool from_w = l == kFlowLayers - 1;
+    const float* uin = from_w ? a.w : a.U + (size_t)l * N * kFlowDim;
     const double ss = *a.sumsq;
     const float inv_ss = ss > 0.0 ? (float)(1.0 / ss) : 0.f;
     const uint32_t chunks = (N + 31u) / 32u;
@@ -159,7 +164,8 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_grad(FlowTrainArgs a)
         const bool valid = live && chunk * 32u + (uint32_t)n32 < N;
         float u[8], g[8];
         {
-            const float4* ui = reinterpret_cast<const float4*>(uin + (size_t)k * kFlowDim + 8 * half);
+            const size_t row = from_w ? (size_t)a.off + (size_t)k * a.stride : (size_t)k;
+            const float4* ui = reinterpret_cast<const float4*>(uin + row * kFlowDim + 8 * half);
             const float4 u0 = ui[0], u1 = ui[1];
             u[0] = u0.x; u[1] = u0.y; u[2] = u0.z; u[3] = u0.w;
             u[4] = u1.x; u[5] = u1.y; u[6] = u1.z; u[7] = u1.w;
@@ -173,7 +179,7 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_grad(FlowTrainArgs a)
 #pragma unroll
             for (int j = 0; j < 8; ++j) g[j] = 0.f;
         }
-        const float omk = valid ? fabsf(a.om[k]) : 0.f;
+        const float omk = valid ? fabsf(a.om[(size_t)a.off + (size_t)k * a.stride]) : 0.f;
         const float coef = (a.gamma == 2 ? omk * omk : omk) * inv_ss;
 
         // ---- recompute the conditioner of this layer -----------------------
@@ -428,7 +434,8 @@ hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, 
                                 float* seg, hipStream_t st)
 {
     double* ss = const_cast<double*>(base.sumsq);
-    hipLaunchKernelGGL(k_flow_sumsq, dim3(kSumBlocks), dim3(kSumThreads), 0, st, base.om, base.n, base.gamma, ss);
+    hipLaunchKernelGGL(k_flow_sumsq, dim3(kSumBlocks), dim3(kSumThreads), 0, st, base.om, base.n, base.stride,
+                       base.off, base.gamma, ss);
     hipLaunchKernelGGL(k_flow_sumsq_final, dim3(1), dim3(kSumThreads), 0, st, ss);
     // the inverse pass holds 80 KB of LDS: two workgroups per CU
     hipLaunchKernelGGL(k_flow_inverse, dim3(2 * n_wg), dim3(kFlowThreads), 0, st, base);

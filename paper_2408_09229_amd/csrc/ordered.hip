@@ -168,6 +168,9 @@ hipError_t launch_ordered(const OrderedArgs& a, hipStream_t st)
     case F_ROOS: e = launch_ord_eval_fam<F_ROOS>(a, st); break;
     case F_CONST: e = launch_ord_eval_fam<F_CONST>(a, st); break;
     case F_COSINE: e = launch_ord_eval_fam<F_COSINE>(a, st); break;
+    case F_SIN_EXP: e = launch_ord_eval_fam<F_SIN_EXP>(a, st); break;
+    case F_EXP_SQ: e = launch_ord_eval_fam<F_EXP_SQ>(a, st); break;
+    case F_MOROKOFF: e = launch_ord_eval_fam<F_MOROKOFF>(a, st); break;
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;

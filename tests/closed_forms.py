@@ -85,6 +85,21 @@ def cosine(params, dim) -> float:
     return float(params[0] * mp.sin(1) ** dim)
 
 
+def sin_exp(params, dim) -> float:
+    """A (sin x_0 + exp x_1) on [0,1]^D: A ((1 - cos 1) + (e - 1))."""
+    return float(params[0] * ((1 - mp.cos(1)) + (mp.e - 1)))
+
+
+def exp_sq(params, dim) -> float:
+    """A prod_d int_0^1 exp(x^2) dx = A (sqrt(pi)/2 erfi(1))^D."""
+    return float(params[0] * (mp.sqrt(mp.pi) / 2 * mp.erfi(1)) ** dim)
+
+
+def morokoff(params, dim) -> float:
+    """A (1 + 1/D)^D prod_d int_0^1 x^(1/D) dx = A (1 + 1/D)^D (1/(1 + 1/D))^D = A."""
+    return float(params[0])
+
+
 def exact(w: vi.Workload) -> float:
     f = w.family
     if f == vi.GAUSS_DIAG:
@@ -103,6 +118,12 @@ def exact(w: vi.Workload) -> float:
         return const(w.params, w.dim, w.lo, w.hi)
     if f == vi.COSINE:
         return cosine(w.params, w.dim)
+    if f == vi.SIN_EXP:
+        return sin_exp(w.params, w.dim)
+    if f == vi.EXP_SQ:
+        return exp_sq(w.params, w.dim)
+    if f == vi.MOROKOFF:
+        return morokoff(w.params, w.dim)
     if f == vi.GAUSS_CORR:
         return 1.0   # normalised density; mass outside [0,1]^16 is below 1e-60
     raise ValueError(f)

@@ -58,7 +58,7 @@ PROBE_CASES = [
                 n_eval=12 ** 4 * 3, n_iter=1, n_strat=12),
     vi.gauss3_8d().with_(name="gauss3_8d_f64", n_eval=50_000, n_g=64, precision="f64"),
     vi.Workload("corr16", 16, vi.GAUSS_CORR, np.array([0.5, 0.03, 0.9]), n_g=32, n_eval=300_000, n_iter=1),
-]
+] + [w.with_(n_eval=min(w.n_eval, 60_000)) for w in vi.tab3_cases()]
 
 
 @pytest.mark.parametrize("w", PROBE_CASES, ids=lambda w: w.name)
@@ -99,7 +99,12 @@ ITER_CASES = vi.small_cases() + [
                 n_iter=1),
     vi.Workload("cosine_big_cubes", 2, vi.COSINE, np.array([1.0]), n_g=32, n_eval=400_000, n_iter=1,
                 n_strat=3),
-]
+    # 16 x 1024 intervals: the histograms do not fit in LDS beside the fill's
+    # other tables, so they are global FP64 / u32 atomics (the path of the
+    # d=16 benchmark workload)
+    vi.Workload("corr16_ng1024", 16, vi.GAUSS_CORR, np.array([0.5, 0.2, 0.3]), n_g=1024, n_eval=200_003,
+                n_iter=1),
+] + vi.tab3_cases()
 
 
 @pytest.mark.parametrize("w", ITER_CASES, ids=lambda w: w.name)

@@ -24,6 +24,8 @@ def _quad1(orc, fam, params):
     (vi.ROOS, np.array([2.0]), 2.0),
     (vi.CONST, np.array([4.25]), 4.25),
     (vi.COSINE, np.array([1.0]), math.sin(1.0)),
+    (vi.EXP_SQ, np.array([1.5]), None),
+    (vi.MOROKOFF, np.array([0.75]), 0.75),
 ])
 def test_family_1d_integral(orc, fam, params, exact):
     w = vi.Workload("t", 1, fam, params, n_g=1, n_eval=1, n_iter=1)
@@ -83,3 +85,51 @@ def test_gauss_corr_closed_form_against_direct_sampling():
     s = 0.2
     prod = cf.gauss_diag(np.array([1.0, s, 1.0, 0.5]), 6) / (2 * np.pi * s * s) ** 3
     assert abs(cf.gauss_corr(np.array([0.5, s, 0.0]), 6) - prod) < 1e-12
+
+
+def _quad2(orc, fam, params):
+    return integrate.dblquad(lambda b, a: orc.integrand(fam, [a, b], params), 0.0, 1.0, 0.0, 1.0,
+                             epsabs=1e-13, epsrel=1e-11)[0]
+
+
+@pytest.mark.parametrize("fam,params", [
+    (vi.SIN_EXP, np.array([1.25])),
+    (vi.EXP_SQ, np.array([0.5])),
+    (vi.MOROKOFF, np.array([2.0])),
+])
+def test_family_2d_integral(orc, fam, params):
+    """Tab. 3 #1, #4, #6 in two dimensions against their closed forms
+    (sin + exp: e - cos 1; exp of the squared norm: the erfi product;
+    Morokoff-Caflisch: A, since (1 + 1/2)^2 (int_0^1 sqrt x dx)^2 = 1)."""
+    w = vi.Workload("t", 2, fam, params, n_g=1, n_eval=1, n_iter=1)
+    want = cf.exact(w)
+    assert abs(_quad2(orc, fam, params) - want) <= 1e-9 * abs(want)
+
+
+def test_sin_exp_uses_the_first_two_axes(orc):
+    """sin + exp reads x_0 and x_1 only: in 3-d the third axis changes
+    nothing, and the two terms swap roles with the axes."""
+    p = np.array([1.0])
+    for x in ([0.2, 0.7, 0.1], [0.9, 0.05, 0.6]):
+        a = orc.integrand(vi.SIN_EXP, x, p)
+        assert a == orc.integrand(vi.SIN_EXP, [x[0], x[1], 0.99], p)
+        assert abs(a - (math.sin(x[0]) + math.exp(x[1]))) <= 1e-15 * a
+
+
+def test_morokoff_3d_mean_is_one(orc):
+    """Morokoff-Caflisch in 3-d by a tensor Gauss-Jacobi rule exact for the
+    x^(1/3) weights: the integral is A = 1 (closed form)."""
+    from scipy.special import roots_jacobi
+    # int_0^1 x^(1/3) g(x) dx with weight x^(1/3): Jacobi on [-1,1] with
+    # beta = 1/3 after x = (1 + t)/2
+    t, wt = roots_jacobi(8, 0.0, 1.0 / 3.0)
+    xs = (1 + t) / 2
+    ws = wt / 2 ** (1 + 1 / 3)
+    tot = 0.0
+    for i, a in enumerate(xs):
+        for j, b in enumerate(xs):
+            for k, c in enumerate(xs):
+                # the rule integrates the x^(1/3) factors; divide them out of f
+                tot += ws[i] * ws[j] * ws[k] * orc.integrand(vi.MOROKOFF, [a, b, c], np.array([1.0])) / \
+                    (a * b * c) ** (1 / 3)
+    assert abs(tot - 1.0) < 1e-12

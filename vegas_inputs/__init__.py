@@ -18,6 +18,9 @@ id    name         f(x)                                                  params
 6     ROOS         A * prod_d |4 x_d - 2|                                [A]
 7     CONST        A                                                     [A]
 8     COSINE       A * prod_d cos(x_d)                                   [A]
+9     SIN_EXP      A * (sin(x_0) + exp(x_1)), D >= 2                     [A]
+10    EXP_SQ       A * exp(sum_d x_d^2)                                  [A]
+11    MOROKOFF     A * (1 + 1/D)^D prod_d x_d^(1/D), box in x >= 0       [A]
 ====  ===========  ====================================================  ==========================
 
 The paper's test integrands are Tab. 3 (Sec. 4.1); the five benchmark
@@ -32,10 +35,10 @@ from typing import List
 
 import numpy as np
 
-GAUSS_DIAG, GENZ_PPEAK, GENZ_GAUSS, GAUSS_CORR, LINEAR, ROOS, CONST, COSINE = range(1, 9)
+GAUSS_DIAG, GENZ_PPEAK, GENZ_GAUSS, GAUSS_CORR, LINEAR, ROOS, CONST, COSINE, SIN_EXP, EXP_SQ, MOROKOFF = range(1, 12)
 FAMILY_NAMES = {GAUSS_DIAG: "gauss_diag", GENZ_PPEAK: "genz_ppeak", GENZ_GAUSS: "genz_gauss",
                 GAUSS_CORR: "gauss_corr", LINEAR: "linear", ROOS: "roos", CONST: "const",
-                COSINE: "cosine"}
+                COSINE: "cosine", SIN_EXP: "sin_exp", EXP_SQ: "exp_sq", MOROKOFF: "morokoff"}
 
 
 @dataclass
@@ -204,4 +207,16 @@ def closed_form_cases() -> List[Workload]:
         Workload("ppeak3", 3, GENZ_PPEAK, np.array([1.0, 6.0, 9.0, 12.0, 0.3, 0.6, 0.45]), n_g=32,
                  n_eval=50_003, n_iter=5),
         Workload("roos5", 5, ROOS, np.array([1.0]), n_g=8, n_eval=30_001, n_iter=5),
+    ] + tab3_cases()
+
+
+def tab3_cases() -> List[Workload]:
+    """The paper's Tab. 3 integrands #1, #4, #6 at their dimensions (2, 10,
+    8) on small budgets VEGAS+ resolves (checked across seeds on the
+    oracle): sine + exponential, exponential of the squared norm,
+    Morokoff & Caflisch."""
+    return [
+        Workload("sin_exp2", 2, SIN_EXP, np.array([1.0]), n_g=32, n_eval=20_011, n_iter=5),
+        Workload("exp_sq10", 10, EXP_SQ, np.array([1.0]), n_g=32, n_eval=200_003, n_iter=5),
+        Workload("morokoff8", 8, MOROKOFF, np.array([1.0]), n_g=32, n_eval=100_003, n_iter=5),
     ]
