@@ -118,16 +118,25 @@ def host_info():
     return {"nproc": os.cpu_count(), "cpu_model": model}
 
 
-def cpu_baseline(w, budget_evals: int, iters: int):
+def cpu_baseline(w, budget_evals: int, iters: int, target_s: float = 15.0):
+    """The oracle on the same integrand, dimension and intervals: `iters`
+    iterations of at most `budget_evals` evaluations, cut so that the whole
+    sample takes about target_s seconds (a one-iteration probe at 2e4
+    evaluations sets the rate)."""
     import oracle
-    ww = w.with_(n_eval=budget_evals, n_iter=iters)
+    probe = min(budget_evals, 20_000)
+    t0 = time.perf_counter()
+    oracle.run(w.dim, w.n_g, probe, w.family, w.params, n_iter=1, seed=w.seed, alpha=w.alpha, beta=w.beta)
+    per_eval = (time.perf_counter() - t0) / probe
+    n = int(min(budget_evals, max(probe, target_s / iters / per_eval)))
+    ww = w.with_(n_eval=n, n_iter=iters)
     t0 = time.perf_counter()
     oracle.run(ww.dim, ww.n_g, ww.n_eval, ww.family, ww.params, n_iter=ww.n_iter, seed=ww.seed,
                alpha=ww.alpha, beta=ww.beta)
     dt = time.perf_counter() - t0
-    return {"value": budget_evals * iters / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} iterations x {budget_evals:.2g} evals of the same integrand, dim and "
-                      f"intervals (single-threaded FP64 C oracle, {dt:.1f} s)", **host_info()}
+    return {"value": n * iters / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} iterations x {n:,} evals of the same integrand, dim and intervals "
+                      f"(single-threaded FP64 C oracle, {dt:.1f} s)", **host_info()}
 
 
 def cpu_baseline_batch(insts, budget_evals: int):

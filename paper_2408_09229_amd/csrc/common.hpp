@@ -5,7 +5,9 @@
 // the map damping and the allocation power, and the built-in integrand
 // families (Tab. 3 and the benchmark workloads).
 #pragma once
+#ifndef __HIPCC_RTC__   // hipRTC provides the HIP device runtime itself
 #include <hip/hip_runtime.h>
+#endif
 #include <stdint.h>
 
 #include "layout.hpp"

@@ -11,7 +11,9 @@
 // FP32 variants use the hardware exp2 and fold constants so that the
 // per-term work is a few VALU operations.
 #pragma once
+#ifndef __HIPCC_RTC__   // hipRTC provides the HIP device runtime itself
 #include <hip/hip_runtime.h>
+#endif
 #include <type_traits>
 
 #include "layout.hpp"

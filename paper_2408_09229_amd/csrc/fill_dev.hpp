@@ -2,7 +2,9 @@
 // their merges, per-lane accumulators, the LDS plan, and one tile of the
 // fill.  Shared by the single-problem and the batched fill kernels.
 #pragma once
+#ifndef __HIPCC_RTC__   // hipRTC provides the HIP device runtime itself
 #include <hip/hip_runtime.h>
+#endif
 #include <stdint.h>
 #include <type_traits>
 
@@ -661,6 +663,78 @@ __device__ __forceinline__ void wave_atomic_max(unsigned long long b, unsigned l
         b = y > b ? y : b;
     }
     if ((threadIdx.x & 63) == 0 && b) atomicMax(p, b);
+}
+
+// The whole fill of one workgroup (Alg. 2): the integrand's table and the
+// histograms into LDS, the workgroup's tiles (static round-robin), its
+// histogram slot and its fixed-order partial sums.  The body of the built-in
+// fill kernels and of a runtime-compiled integrand's fill kernel; smem is
+// the kernel's dynamic LDS.
+template <typename R, int FAM, int MAXD, bool KAHAN, bool EXACT>
+__device__ __forceinline__ void fill_body(const FillArgs& a, unsigned char* smem)
+{
+    const SampleConst& sc = a.sc;
+    const int D = sc.D;
+    const uint32_t ng = sc.ng;
+    const int tid = threadIdx.x;
+    const LdsPlan lp = lds_plan(D, (int)ng, (int)sizeof(R), a.lds_hist, a.tile, sc.n_aux, 0);
+    const FillLds<R> L(smem, lp);
+
+    const int nbins = D * (int)ng;
+    {
+        const R* asrc = std::is_same<R, double>::value ? reinterpret_cast<const R*>(sc.aux_d)
+                                                       : reinterpret_cast<const R*>(sc.aux_f);
+        for (int i = tid; i < sc.n_aux; i += kFillThreads) L.auxl[i] = asrc[i];
+    }
+    if (a.lds_hist) {
+        for (int i = tid; i < nbins; i += kFillThreads) {
+            L.hl[i] = 0.0;
+            L.cl[i] = 0u;
+        }
+    }
+
+    SamplePath<R, FAM, MAXD, EXACT> sp(sc, L.auxl);
+    LaneTotal<KAHAN> totI, totV;
+    double vmax = 0.0;
+    unsigned long long bad = 0;
+    TileIO io;
+    io.t = a.t;
+    io.tile = a.tile;
+    io.per_lane = a.per_lane;
+    io.lds_hist = a.lds_hist;
+    io.start = a.start;
+    io.tile_first = a.tile_first;
+    io.v_out = a.v_out;
+    io.side = a.side;
+    io.hist_H = a.hist_H;
+    io.hist_C = a.hist_C;
+    io.grid = a.grid;
+
+    __syncthreads();
+
+    for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x)
+        fill_tile<R, MAXD, KAHAN, true>(tile, io, L, sp, totI, totV, vmax, bad);
+
+    if (a.lds_hist) {
+        // this workgroup's histograms into its slot (reduced in slot order by
+        // the map kernel)
+        double* slotH = a.hist_H + (size_t)blockIdx.x * nbins;
+        uint32_t* slotC = a.hist_C + (size_t)blockIdx.x * nbins;
+        for (int i = tid; i < nbins; i += kFillThreads) {
+            slotH[i] = L.hl[i];
+            slotC[i] = L.cl[i];
+        }
+    }
+
+    // ---- fixed-order workgroup reduction of the lane partials -------------
+    double sI, sV, mx;
+    wg_reduce_totals(totI.value(), totV.value(), vmax, L.red, sI, sV, mx);
+    if (tid == 0) {
+        a.wg_part[2 * blockIdx.x] = sI;
+        a.wg_part[2 * blockIdx.x + 1] = sV;
+        atomicMax(a.vmax, (unsigned long long)__double_as_longlong(mx));
+    }
+    if (bad) atomicAdd(a.nonfinite, bad);
 }
 
 }  // namespace vg

@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 #include "flow.hpp"
 #include "flow_dev.hpp"
 #include "launch.hpp"
@@ -150,8 +152,10 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_grad(FlowTrainArgs a)
     // the compact inverse-pass outputs
     const bool from_w = l == kFlowLayers - 1;
     const float* uin = from_w ? a.w : a.U + (size_t)l * N * kFlowDim;
+    // c_k = |omega_k|^gamma / sum |omega|^gamma in double: tiny weights
+    // (an integrand that underflows almost everywhere) put 1/sum beyond FP32
     const double ss = *a.sumsq;
-    const float inv_ss = ss > 0.0 ? (float)(1.0 / ss) : 0.f;
+    const double inv_ss = ss > 0.0 && ss < INFINITY ? 1.0 / ss : 0.0;
     const uint32_t chunks = (N + 31u) / 32u;
     const uint32_t per_round = gridDim.x * kFlowWaves;
     const uint32_t rounds = (chunks + per_round - 1u) / per_round;
@@ -180,7 +184,8 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_grad(FlowTrainArgs a)
             for (int j = 0; j < 8; ++j) g[j] = 0.f;
         }
         const float omk = valid ? fabsf(a.om[(size_t)a.off + (size_t)k * a.stride]) : 0.f;
-        const float coef = (a.gamma == 2 ? omk * omk : omk) * inv_ss;
+        const double omd = (double)omk;
+        const float coef = (float)((a.gamma == 2 ? omd * omd : omd) * inv_ss);
 
         // ---- recompute the conditioner of this layer -----------------------
         flow_mlp(l, u, P, pk, S.h1[wave], S.o[wave], S.h2[wave], S.x[wave]);
@@ -454,8 +459,10 @@ hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, 
 
 hipError_t launch_flow_adam(float* theta, const float* grad, float* m, float* v, float lr, int step, hipStream_t st)
 {
-    const float c1 = 1.f / (1.f - powf(0.9f, (float)step));
-    const float c2 = 1.f / (1.f - powf(0.999f, (float)step));
+    // bias corrections in double: 1 - 0.999^t in FP32 (from the FP32 constant
+    // 0.999f) is off by 1.3e-5 relative at t = 1
+    const float c1 = (float)(1.0 / (1.0 - std::pow(0.9, (double)step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(0.999, (double)step)));
     hipLaunchKernelGGL(k_flow_adam, dim3((kFParams + 255) / 256), dim3(256), 0, st, theta, grad, m, v, lr, c1, c2);
     return hipGetLastError();
 }

@@ -2,7 +2,9 @@
 // the probe: stratum digits of a cube, Philox words, fixed-point point and
 // bin, map and Jacobian, integrand.
 #pragma once
+#ifndef __HIPCC_RTC__   // hipRTC provides the HIP device runtime itself
 #include <hip/hip_runtime.h>
+#endif
 #include <stdint.h>
 #include <type_traits>
 
