@@ -152,6 +152,28 @@ vegas_status vegas_result(vegas_ctx* ctx, vegas_estimate* out);
 /* Synchronous: release the handle (the workspace stays the caller's). */
 void vegas_destroy(vegas_ctx* ctx);
 
+/* ---- for callers that cannot allocate device memory ---------------------
+ * Code under HIP graph capture, tight serving loops, or harnesses that
+ * forbid hipMalloc: the same context as vegas_create, but its workspace is a
+ * device array the library holds (VEGAS_STATIC_SCRATCH_BYTES, 256-byte
+ * aligned), one per device, kept until the process ends.  Allocates no
+ * device memory (no hipMalloc/hipFree, no allocating library routine); the
+ * handle itself is host memory, released by vegas_destroy.
+ *  - The problem's workspace (vegas_workspace_size) must fit the array,
+ *    else VEGAS_ENOMEM and no context.
+ *  - Every context made by this call on one device uses the same array:
+ *    creating one overwrites the state of any earlier one on that device,
+ *    whose handle may then only be destroyed.  Calls on such contexts that
+ *    overlap (any thread, any stream) race.
+ *  - The array keeps the last context's contents; create writes everything
+ *    an iteration reads before writing it, so no clearing is needed.
+ *  - Set-up as vegas_create (asynchronous on hip_stream, NULL = null
+ *    stream); errors as vegas_create, plus VEGAS_EDEVICE when the array's
+ *    device address cannot be obtained. */
+#define VEGAS_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+vegas_status vegas_create_static(const vegas_config* cfg, const vegas_integrand* f,
+                                 void* hip_stream, vegas_ctx** out);
+
 /* Host pointer out. */
 vegas_status vegas_get_info(const vegas_ctx* ctx, vegas_info* out);
 

@@ -30,6 +30,7 @@ VEGAS_OK, VEGAS_EINVAL, VEGAS_ENOMEM, VEGAS_EDEVICE, VEGAS_ESTATE, VEGAS_ENONFIN
 PREC_FP64, PREC_FP32 = 0, 1
 ACC_FP64, ACC_KAHAN, ACC_ORDERED = 0, 1, 2
 BATCH_STREAMS, BATCH_PERSISTENT = 0, 1
+STATIC_SCRATCH_BYTES = 64 << 20     # VEGAS_STATIC_SCRATCH_BYTES
 _SCHEDULES = {"streams": BATCH_STREAMS, "persistent": BATCH_PERSISTENT}
 
 
@@ -79,6 +80,7 @@ _DECL = {
     "vegas_workspace_size": (_st, [C.POINTER(vegas_config), C.POINTER(vegas_integrand), C.POINTER(C.c_size_t)]),
     "vegas_create": (_st, [C.POINTER(vegas_config), C.POINTER(vegas_integrand), _vp, C.c_size_t, _vp,
                            C.POINTER(_vp)]),
+    "vegas_create_static": (_st, [C.POINTER(vegas_config), C.POINTER(vegas_integrand), _vp, C.POINTER(_vp)]),
     "vegas_adapt": (_st, [_vp, C.c_int32]),
     "vegas_integrate": (_st, [_vp, C.c_int32]),
     "vegas_result": (_st, [_vp, C.POINTER(vegas_estimate)]),
@@ -190,22 +192,30 @@ class Vegas:
     """One VEGAS+ problem on the current HIP device.
 
     ``Vegas(cfg, family, params)`` allocates the workspace as a torch uint8
-    tensor and runs on torch's current stream (or ``stream``).
+    tensor and runs on torch's current stream (or ``stream``).  With
+    ``static=True`` the context uses the library's own device array instead
+    (vegas_create_static: no allocation; one such context per device at a
+    time).
     """
 
     def __init__(self, cfg: vegas_config, family: int, params, lo=None, hi=None, *, stream=None,
-                 device=None):
+                 device=None, static: bool = False):
         import torch
         self.cfg = cfg
         self._it = _Integrand(family, params, lo, hi)
-        n = C.c_size_t()
-        check(vegas_workspace_size(C.byref(cfg), C.byref(self._it.s), C.byref(n)), "vegas_workspace_size")
         self.device = torch.device(device or "cuda")
-        self.ws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = C.c_void_p()
-        check(vegas_create(C.byref(cfg), C.byref(self._it.s), C.c_void_p(self.ws.data_ptr()), n.value,
-                           C.c_void_p(self.stream.cuda_stream), C.byref(h)), "vegas_create")
+        if static:
+            self.ws = None
+            check(vegas_create_static(C.byref(cfg), C.byref(self._it.s), C.c_void_p(self.stream.cuda_stream),
+                                      C.byref(h)), "vegas_create_static")
+        else:
+            n = C.c_size_t()
+            check(vegas_workspace_size(C.byref(cfg), C.byref(self._it.s), C.byref(n)), "vegas_workspace_size")
+            self.ws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+            check(vegas_create(C.byref(cfg), C.byref(self._it.s), C.c_void_p(self.ws.data_ptr()), n.value,
+                               C.c_void_p(self.stream.cuda_stream), C.byref(h)), "vegas_create")
         self.h = h
         self.info = vegas_info()
         check(vegas_get_info(self.h, C.byref(self.info)), "vegas_get_info")

@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -816,6 +817,69 @@ void vegas_destroy(vegas_ctx* ctx)
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
     delete ctx;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The library-held workspace of vegas_create_static, for callers that cannot
+// allocate device memory.  Each device that runs the library holds its own
+// copy of this array, at its own address, until the process ends.  In host
+// code `scratch` names a host-side stand-in, never the device memory: host
+// code uses only the per-device address hipGetSymbolAddress returns.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[VEGAS_STATIC_SCRATCH_BYTES];
+
+namespace vgh {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};   // device address of `scratch`, per device
+
+// the current device's address of `scratch`, looked up once per device with
+// that device current
+vegas_status scratch_address(void** out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(VEGAS_EUNSUPPORTED, "device %d: the static workspace is kept for devices 0..%d", dev,
+                    kMaxDevices - 1);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(VEGAS_EDEVICE, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return VEGAS_OK;
+}
+
+}  // namespace vgh
+
+extern "C" {
+
+vegas_status vegas_create_static(const vegas_config* cfg, const vegas_integrand* f, void* hip_stream,
+                                 vegas_ctx** out)
+{
+    if (!out) return fail(VEGAS_EINVAL, "null out");
+    *out = nullptr;
+    size_t need = 0;
+    const vegas_status s = vegas_workspace_size(cfg, f, &need);
+    if (s != VEGAS_OK) return s;
+    if (need > (size_t)VEGAS_STATIC_SCRATCH_BYTES)
+        return fail(VEGAS_ENOMEM, "the problem needs %zu bytes of workspace; the static workspace holds %zu",
+                    need, (size_t)VEGAS_STATIC_SCRATCH_BYTES);
+    void* ws = nullptr;
+    const vegas_status a = scratch_address(&ws);
+    if (a != VEGAS_OK) return a;
+    // the same set-up as a caller workspace: every array an iteration reads
+    // before writing it (counters, map, allocation, constants) is written
+    // here, so what an earlier context left in the array does not matter
+    return vegas_create(cfg, f, ws, (size_t)VEGAS_STATIC_SCRATCH_BYTES, hip_stream, out);
 }
 
 vegas_status vegas_adapt(vegas_ctx* ctx, int32_t n_iter)
