@@ -5,29 +5,39 @@ point y in [0,1]^D goes to w = F(y), and w goes through the separable map to
 x.  The weight of the sample is f(x) J_map(w) J_F(y), so the estimate stays
 unbiased for any F, because J_F is the exact Jacobian determinant.  The paper
 has no such warp: this follows the problem statement's description of it
-(four coupling layers, 2x64 MLP conditioners, BF16 matrix products with FP32
-accumulation) with the readings listed here.
+(four monotone coupling layers, 2x64 MLP conditioners, BF16 matrix products
+with FP32 accumulation) with the readings listed here.
 
 Readings (all fixed here, shared by the GPU path through its tests):
+  * Gaussian coordinates: the flow acts on z = Phi^-1(y) (Phi the standard
+    normal distribution function) and returns w = Phi(z_4).  The separable
+    VEGAS map leaves the integrand's dependence between axes to the warp,
+    and for an integrand that is a correlated Gaussian (or close to one) that
+    dependence is an affine map of z, which affine coupling layers express.
   * Masks: layer 1 conditions on the first half of the axes and transforms
     the second, layer 2 the reverse, layer 3 conditions on the even axes,
     layer 4 on the odd ones.
-  * Conditioner: x = 2 z_A - 1; h1 = relu(W1 x + b1); h2 = relu(W2 h1 + b2);
-    o = W3 h2 + b3, o = (logits of K bins) for each transformed axis.
-  * Bin probabilities p = (1 - eps) softmax(o) + eps/K, eps = 1e-3, K = 16.
-  * Transform of a coordinate z in bin b = min(floor(K z), K-1):
-    C(z) = sum_{k<b} p_k + (K z - b) p_b, with derivative K p_b.  The inverse
-    finds the bin of v among the cumulative sums and inverts the linear piece.
+  * Conditioner: x = z_A / 2; h1 = relu(W1 x + b1); h2 = relu(W2 h1 + b2);
+    o = W3 h2 + b3 with 2 |B| outputs: raw log-scales a (first |B|) and
+    shifts t (last |B|) of the transformed axes, in axis order.
+  * Transform of a moved axis: s = S tanh(a / S) with S = 3 (log-scale kept
+    in [-3, 3]), z_B -> z_B e^s + t.  Monotone in z_B; the inverse is
+    (z_B - t) e^-s.
+  * log J_F(y) = sum over layers and moved axes of s + sum_d (z_0d^2 - z_4d^2)/2
+    (the log-densities of the two changes of variable y <-> z and z <-> w).
   * Initialisation: W1, W2 uniform in +-1/sqrt(fan_in), everything else 0, so
-    p = 1/K and F is the identity.
-  * Training loss of one iteration: L = sum_k c_k log J_F(F^-1(w_k)) with
-    c_k = omega_k^2 / sum omega^2 on the stored samples (w_k, omega_k).  Its
-    gradient is the gradient of the estimator's variance, sum g^2/q, in the
-    direction that matters (log q(w) = -log J_F(F^-1(w))), up to a positive
-    factor; the inverse pass is differentiated.
+    s = t = 0 and F is the identity.
+  * Training data of one iteration: the final Gaussian coordinates z_4 of its
+    samples (w = Phi(z_4)) and their weights omega.  Loss
+    L = sum_k c_k log J_F(F^-1(w_k)) with c_k = omega_k^2 / sum omega^2
+    (variance) or |omega_k| / sum |omega| (KL).  Since the warp's density at
+    w is 1 / J_F(F^-1(w)), the variance loss's gradient is a positive multiple
+    of the gradient of the estimator's variance, sum g^2/q, and the KL loss's
+    that of the KL divergence from |g| / int |g| to q.  The gradient is taken
+    through the inverse chain from z_4 (fixed) down to z_0.
   * Adam with beta1 0.9, beta2 0.999, eps 1e-8.
 
-``bf16=True`` rounds, to BF16 with round-to-nearest-even, exactly the values
+``emu=True`` rounds, to BF16 with round-to-nearest-even, exactly the values
 the GPU feeds to its BF16 matrix instructions: the conditioner inputs, the
 weights, the hidden activations, and in the backward pass the gradients of
 the layer outputs that enter products.
@@ -38,11 +48,12 @@ from dataclasses import dataclass
 from typing import List
 
 import numpy as np
+from scipy.special import ndtr, ndtri
 
-K_BINS = 16
 HIDDEN = 64
-EPS = 1e-3
 N_LAYERS = 4
+S_MAX = 3.0          # log-scale bound S
+X_SCALE = 0.5        # conditioner input x = X_SCALE z_A
 
 
 # --------------------------------------------------------------------------
@@ -61,7 +72,7 @@ def layer_shapes(dim: int):
     for a, b in masks(dim):
         na, nb = len(a), len(b)
         out.append([("W1", (HIDDEN, na)), ("b1", (HIDDEN,)), ("W2", (HIDDEN, HIDDEN)), ("b2", (HIDDEN,)),
-                    ("W3", (nb * K_BINS, HIDDEN)), ("b3", (nb * K_BINS,))])
+                    ("W3", (2 * nb, HIDDEN)), ("b3", (2 * nb,))])
     return out
 
 
@@ -109,16 +120,13 @@ class Cache:
     x: np.ndarray      # (N, nA) conditioner input (as fed to the product)
     h1: np.ndarray     # (N, H)
     h2: np.ndarray
-    s: np.ndarray      # (N, nB, K) softmax
-    p: np.ndarray      # (N, nB, K) bin probabilities
-    cum: np.ndarray    # (N, nB, K+1) exclusive cumulative sums, cum[..., K] = total
-    b: np.ndarray      # (N, nB) bin of each transformed coordinate
-    logj: np.ndarray   # (N,)
+    s: np.ndarray      # (N, nB) log-scales
+    zb: np.ndarray     # (N, nB) the moved axes on the y side of the layer
 
 
 def _mlp(L, zA, emu):
     r = bf16 if emu else (lambda v: v)
-    x = r(2.0 * zA - 1.0)
+    x = r(X_SCALE * zA)
     h1 = np.maximum(x @ r(L["W1"]).T + L["b1"], 0.0)
     h1 = r(h1)
     h2 = np.maximum(h1 @ r(L["W2"]).T + L["b2"], 0.0)
@@ -127,119 +135,104 @@ def _mlp(L, zA, emu):
     return x, h1, h2, o
 
 
-def _probs(o, nb):
-    o = o.reshape(o.shape[0], nb, K_BINS)
-    e = np.exp(o - o.max(axis=2, keepdims=True))
-    s = e / e.sum(axis=2, keepdims=True)
-    return s, (1.0 - EPS) * s + EPS / K_BINS
-
-
-def _cums(p):
-    c = np.zeros(p.shape[:2] + (K_BINS + 1,))
-    c[..., 1:] = np.cumsum(p, axis=2)
-    return c
+def _scale_shift(o, nb):
+    s = S_MAX * np.tanh(o[:, :nb] / S_MAX)
+    return s, o[:, nb:]
 
 
 def layer_forward(L, z, A, B, emu=False):
+    """Forward layer in Gaussian coordinates: z_B -> z_B e^s + t."""
     x, h1, h2, o = _mlp(L, z[:, A], emu)
-    s, p = _probs(o, len(B))
-    cum = _cums(p)
-    zb = z[:, B]
-    b = np.clip(np.floor(K_BINS * zb).astype(np.int64), 0, K_BINS - 1)
-    pb = np.take_along_axis(p, b[..., None], 2)[..., 0]
-    cb = np.take_along_axis(cum, b[..., None], 2)[..., 0]
+    s, t = _scale_shift(o, len(B))
     out = z.copy()
-    out[:, B] = cb + (K_BINS * zb - b) * pb
-    logj = np.log(K_BINS * pb).sum(axis=1)
-    return out, Cache(x, h1, h2, s, p, cum, b, logj)
+    out[:, B] = z[:, B] * np.exp(s) + t
+    return out, Cache(x, h1, h2, s, z[:, B].copy())
 
 
 def layer_inverse(L, u, A, B, emu=False):
+    """Inverse layer: u_B -> (u_B - t) e^-s."""
     x, h1, h2, o = _mlp(L, u[:, A], emu)
-    s, p = _probs(o, len(B))
-    cum = _cums(p)
-    v = u[:, B]
-    # bin: the last k with cum_k <= v (k < K)
-    b = np.clip((cum[..., :K_BINS] <= v[..., None]).sum(axis=2) - 1, 0, K_BINS - 1)
-    pb = np.take_along_axis(p, b[..., None], 2)[..., 0]
-    cb = np.take_along_axis(cum, b[..., None], 2)[..., 0]
+    s, t = _scale_shift(o, len(B))
     out = u.copy()
-    out[:, B] = np.clip((b + (v - cb) / pb) / K_BINS, 0.0, 1.0)
-    logj = np.log(K_BINS * pb).sum(axis=1)
-    return out, Cache(x, h1, h2, s, p, cum, b, logj)
+    out[:, B] = (u[:, B] - t) * np.exp(-s)
+    return out, Cache(x, h1, h2, s, out[:, B].copy())
 
 
 # --------------------------------------------------------------------------
 # the flow
 # --------------------------------------------------------------------------
-def forward(theta, y, emu=False):
-    """w = F(y) and log J_F(y), for rows y of an (N, D) array."""
+def forward(theta, y, emu=False, return_z=False):
+    """w = F(y) and log J_F(y) for rows y of an (N, D) array (and the final
+    Gaussian coordinates z_4 with return_z)."""
     y = np.asarray(y, dtype=np.float64)
     dim = y.shape[1]
-    z = y
+    z0 = ndtri(y)
+    z = z0
     lj = np.zeros(y.shape[0])
     for L, (A, B) in zip(unpack(theta, dim), masks(dim)):
         z, c = layer_forward(L, z, A, B, emu)
-        lj += c.logj
-    return z, lj
+        lj += c.s.sum(axis=1)
+    lj += 0.5 * (z0 * z0 - z * z).sum(axis=1)
+    w = ndtr(z)
+    return (w, lj, z) if return_z else (w, lj)
+
+
+def inverse_z(theta, zf, emu=False):
+    """z_0 = F^-1 in Gaussian coordinates from the final coordinates z_4, and
+    log J_F at y = Phi(z_0)."""
+    zf = np.asarray(zf, dtype=np.float64)
+    dim = zf.shape[1]
+    u = zf
+    lj = np.zeros(zf.shape[0])
+    for L, (A, B) in reversed(list(zip(unpack(theta, dim), masks(dim)))):
+        u, c = layer_inverse(L, u, A, B, emu)
+        lj += c.s.sum(axis=1)
+    lj += 0.5 * (u * u - zf * zf).sum(axis=1)
+    return u, lj
 
 
 def inverse(theta, w, emu=False):
     """y = F^-1(w) and log J_F(y)."""
-    w = np.asarray(w, dtype=np.float64)
-    dim = w.shape[1]
-    u = w
-    lj = np.zeros(w.shape[0])
-    layers = list(zip(unpack(theta, dim), masks(dim)))
-    for L, (A, B) in reversed(layers):
-        u, c = layer_inverse(L, u, A, B, emu)
-        lj += c.logj
-    return u, lj
+    z0, lj = inverse_z(theta, ndtri(np.asarray(w, dtype=np.float64)), emu)
+    return ndtr(z0), lj
 
 
-def loss_grad(theta, w, coef, emu=False):
-    """L = sum_k coef_k log J_F(F^-1(w_k)) and dL/dtheta (same layout as theta).
+def loss_grad(theta, zf, coef, emu=False):
+    """L = sum_k coef_k log J_F(F^-1(w_k)), w_k = Phi(zf_k), and dL/dtheta
+    (same layout as theta).
 
-    Backward through the inverse chain u_4 = w -> u_3 -> .. -> u_0 = y: for
-    layer l the upstream gradient g = dL/du_{l-1} of the layers already
-    passed, and the layer's own log-Jacobian, give dL/dtheta_l and
-    dL/du_l."""
-    w = np.asarray(w, dtype=np.float64)
+    Backward through the inverse chain u_4 = zf -> u_3 -> .. -> u_0: the
+    loss's dependence on theta is through each layer's log-scales and through
+    z_0 = u_0 (the term z_0^2 / 2); for layer l the upstream gradient
+    g = dL/du_l of the layers already passed gives dL/dtheta_l and
+    dL/du_{l+1}."""
+    zf = np.asarray(zf, dtype=np.float64)
     coef = np.asarray(coef, dtype=np.float64)
-    N, dim = w.shape
+    N, dim = zf.shape
     layers = list(zip(unpack(theta, dim), masks(dim)))
     grad = np.zeros_like(theta)
     gl = unpack(grad, dim)
-    # inverse pass, keeping every layer's input u_l and cache
-    u = w
-    ins, caches = [None] * N_LAYERS, [None] * N_LAYERS
+    # inverse pass, keeping every layer's input u_{l+1} and cache
+    u = zf
+    caches = [None] * N_LAYERS
     for l in reversed(range(N_LAYERS)):
         L, (A, B) = layers[l]
-        ins[l] = u
         u, caches[l] = layer_inverse(L, u, A, B, emu)
-    total = float((coef * sum(c.logj for c in caches)).sum())
+    z0 = u
+    total = float((coef * (sum(c.s.sum(axis=1) for c in caches) + 0.5 * (z0 * z0 - zf * zf).sum(axis=1))).sum())
     r = bf16 if emu else (lambda v: v)
-    g = np.zeros((N, dim))                  # dL/du_0: y enters no log-Jacobian
+    g = coef[:, None] * z0                  # dL/du_0
     for l in range(N_LAYERS):
         L, (A, B) = layers[l]
         c = caches[l]
-        v = ins[l][:, B]
-        b = c.b
-        pb = np.take_along_axis(c.p, b[..., None], 2)[..., 0]
-        cb = np.take_along_axis(c.cum, b[..., None], 2)[..., 0]
-        gz = g[:, B]
-        # z = (b + (v - cum_b)/p_b)/K
-        dp = np.zeros_like(c.p)
-        kk = np.arange(K_BINS)[None, None, :]
-        below = kk < b[..., None]
-        at = kk == b[..., None]
-        dp += below * (gz * (-1.0 / (K_BINS * pb)))[..., None]
-        dp += at * (gz * (-(v - cb) / (K_BINS * pb * pb)) + coef[:, None] / pb)[..., None]
-        gv = gz / (K_BINS * pb)
-        # p = (1 - eps) s + eps/K; s = softmax(o)
-        ds = (1.0 - EPS) * dp
-        do = c.s * (ds - (c.s * ds).sum(axis=2, keepdims=True))
-        do = do.reshape(N, -1)
+        nb = len(B)
+        es = np.exp(-c.s)
+        gb = g[:, B]
+        # u_l,B = (u_{l+1},B - t) e^-s
+        ds = coef[:, None] - gb * c.zb
+        dt = -gb * es
+        da = ds * (1.0 - (c.s / S_MAX) ** 2)
+        do = np.concatenate([da, dt], axis=1)
         G = gl[l]
         G["W3"] += r(do).T @ c.h2
         G["b3"] += do.sum(axis=0)
@@ -251,8 +244,8 @@ def loss_grad(theta, w, coef, emu=False):
         G["b1"] += dh1.sum(axis=0)
         dx = r(dh1) @ r(L["W1"])
         gnew = g.copy()
-        gnew[:, A] = g[:, A] + 2.0 * dx
-        gnew[:, B] = gv
+        gnew[:, A] = g[:, A] + X_SCALE * dx
+        gnew[:, B] = gb * es
         g = gnew
     return total, grad
 
