@@ -172,9 +172,9 @@ def cpu_baseline_warp(w, n_samples: int):
     th = fl.init_params(w.dim, 0)
     y = rng.random((n_samples, w.dim))
     t0 = time.perf_counter()
-    wv, lj = fl.forward(th, y, emu=True)
+    wv, lj, zf = fl.forward(th, y, emu=True, return_z=True)
     coef = np.full(n_samples, 1.0 / n_samples)
-    fl.loss_grad(th, wv, coef, emu=True)
+    fl.loss_grad(th, zf, coef, emu=True)
     dt = time.perf_counter() - t0
     per_flow = dt / n_samples
     per_plain = 1.0 / base["value"]

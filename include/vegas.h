@@ -68,7 +68,8 @@ enum {
     VEGAS_COSINE = 8,       /* A prod_d cos x_d                          : [A]  (Tab. 3 #3) */
     VEGAS_SIN_EXP = 9,      /* A (sin x_0 + exp x_1), dim >= 2           : [A]  (Tab. 3 #1) */
     VEGAS_EXP_SQ = 10,      /* A exp(sum_d x_d^2)                        : [A]  (Tab. 3 #4) */
-    VEGAS_MOROKOFF = 11     /* A (1 + 1/D)^D prod_d x_d^(1/D), box x >= 0: [A]  (Tab. 3 #6) */
+    VEGAS_MOROKOFF = 11,    /* A (1 + 1/D)^D prod_d x_d^(1/D), box x >= 0: [A]  (Tab. 3 #6) */
+    VEGAS_USER = 12         /* compiled at run time (vegas_user_compile): any params, 0..4096 */
 };
 
 /* Problem parameters (Tab. 2: n_intervals, alpha, beta).  Copied at create. */
@@ -152,6 +153,36 @@ vegas_status vegas_result(vegas_ctx* ctx, vegas_estimate* out);
 /* Synchronous: release the handle (the workspace stays the caller's). */
 void vegas_destroy(vegas_ctx* ctx);
 
+/* ---- integrands compiled at run time (hipRTC) -------------------------
+ * The counterpart of the paper's user-supplied integrand compiled for the
+ * GPU at run time (Sec. 3.6).  source (host string) defines the device
+ * function vegas_user_f, taking (const vegas_real* x, int dim,
+ * const double* params) and returning vegas_real,
+ * where vegas_real is double for precision VEGAS_PREC_FP64 and float for
+ * VEGAS_PREC_FP32, x holds the point in the box (dim values) and params the
+ * context's n_params parameters (device memory, FP64).  It may define other
+ * device functions and constants, and use the HIP device math functions.
+ * The fill kernel (the built-ins' tile body, specialised to dim) is compiled
+ * for the current device with hipRTC, with the library's own flags.
+ * Errors: VEGAS_EINVAL for bad arguments or source that does not compile
+ * (the compiler's log is in vegas_last_error()); VEGAS_EDEVICE when loading
+ * fails.  *out is a host handle, valid on that device, released by
+ * vegas_user_destroy (after every context that uses it). */
+typedef struct vegas_user_fn vegas_user_fn;
+vegas_status vegas_user_compile(const char* source, int32_t dim, int32_t precision,
+                                vegas_user_fn** out);
+/* Compile only, for gfx950, and discard the code: checks a source without a
+ * device (no HIP call).  Errors as vegas_user_compile. */
+vegas_status vegas_user_check(const char* source, int32_t dim, int32_t precision);
+void vegas_user_destroy(vegas_user_fn* fn);
+/* As vegas_create, for f->family == VEGAS_USER (0..4096 parameters; params
+ * may be NULL when there are none): the fill runs fn, whose dim and
+ * precision must equal cfg's.  Accumulation FP64 or KAHAN (not ORDERED);
+ * the sample probe and the learned warp do not take user integrands
+ * (VEGAS_EUNSUPPORTED).  fn must outlive the context. */
+vegas_status vegas_create_user(const vegas_config* cfg, const vegas_integrand* f, const vegas_user_fn* fn,
+                               void* d_workspace, size_t bytes, void* hip_stream, vegas_ctx** out);
+
 /* ---- for callers that cannot allocate device memory ---------------------
  * Code under HIP graph capture, tight serving loops, or harnesses that
  * forbid hipMalloc: the same context as vegas_create, but its workspace is a
@@ -178,6 +209,12 @@ vegas_status vegas_create_static(const vegas_config* cfg, const vegas_integrand*
 vegas_status vegas_get_info(const vegas_ctx* ctx, vegas_info* out);
 
 /* ---- inspection / injection hooks (all synchronous, host pointers) ----- */
+/* Switch the map refinement and the sample reallocation on or off (1 / 0)
+ * for the iterations that follow, as cfg.adapt_map and cfg.adapt_strat do
+ * at create (the usual last phase of a VEGAS run keeps the grid fixed).
+ * No HIP call. */
+vegas_status vegas_set_adapt(vegas_ctx* ctx, int32_t adapt_map, int32_t adapt_strat);
+
 /* Map grid, FP64, layout [D][N_g+1] row-major. */
 vegas_status vegas_get_map(vegas_ctx* ctx, double* grid);
 vegas_status vegas_set_map(vegas_ctx* ctx, const double* grid);
@@ -239,14 +276,16 @@ vegas_status vegas_get_timing(vegas_ctx* ctx, double* ms, int32_t* n_iter);
  * A sample weighs f(x) J_map(w) J_F(y).  J_F is the exact Jacobian
  * determinant, so every estimate stays unbiased.  The map and allocation
  * adapt to the warped samples exactly as before.
- * F: four coupling layers on [0,1]^16.  Layer l keeps the axes A_l
- *   ({0..7}, {8..15}, the even axes, the odd axes) and moves the other 8.
- *   A move is the piecewise-linear CDF of 16 bin probabilities
- *   p = (1 - 1e-3) softmax(o) + 1e-3/16.  The logits o come from an MLP of
- *   x = 2 z_A - 1: 8 -> 64 -> 64 -> 128 with ReLU.  The matrix products run on
- *   BF16 MFMA with FP32 accumulation.
+ * F: four affine coupling layers in Gaussian coordinates.  z_0 = Phi^-1(y)
+ *   (Phi the standard normal distribution function), z_4 after the layers,
+ *   w = Phi(z_4).  Layer l keeps the axes A_l ({0..7}, {8..15}, the even
+ *   axes, the odd axes) and moves the other 8: z_B -> z_B e^s + t with
+ *   s = 3 tanh(a/3).  (a, t) come from an MLP of x = z_A / 2:
+ *   8 -> 64 -> 64 -> 16 with ReLU (outputs a_0..a_7, t_0..t_7).  The matrix
+ *   products run on BF16 MFMA with FP32 accumulation.
+ *   log J_F(y) = sum s + sum_d (z_0d^2 - z_4d^2)/2, exact.
  * Parameters: vegas_flow_n_params() floats, layer by layer
- *   W1[64][8], b1[64], W2[64][64], b2[64], W3[128][64], b3[128] (row-major
+ *   W1[64][8], b1[64], W2[64][64], b2[64], W3[16][64], b3[16] (row-major
  *   [out][in]).  A zero W3 and b3 make F the identity.
  * Restrictions: dim 16, FP32 precision, accum FP64 or KAHAN, families
  *   GAUSS_DIAG, GENZ_PPEAK, GENZ_GAUSS, GAUSS_CORR. */
@@ -269,8 +308,8 @@ vegas_status vegas_flow_workspace_size(const vegas_ctx* ctx, size_t* bytes);
 /* Attach a warp.  params: host pointer to n_params floats, or NULL for the
  * library's own starting weights: W1 and W2 uniform in +-1/sqrt(fan_in)
  * (fan_in 8 and 64) from Philox4x32-10 keyed by cfg->init_seed, every other
- * parameter 0, so that F starts as the identity (every bin probability
- * 1/16, log J_F = 0).  d_workspace: device memory of at least the size
+ * parameter 0, so that F starts as the identity (s = t = 0,
+ * log J_F = 0).  d_workspace: device memory of at least the size
  * above, 256-byte aligned; it must outlive the context.  Synchronous.  The
  * warp starts disabled. */
 vegas_status vegas_flow_attach(vegas_ctx* ctx, const vegas_flow_config* cfg, const float* params,
@@ -324,8 +363,9 @@ vegas_status vegas_flow_status(const vegas_ctx* ctx, int32_t* on, int32_t* accep
 vegas_status vegas_flow_get_params(vegas_ctx* ctx, float* params);
 vegas_status vegas_flow_set_params(vegas_ctx* ctx, const float* params);
 /* Test hook, synchronous.  The last warped iteration's samples: w [N][16],
- * log J_F [N] and weight omega [N] (FP32, host pointers; any may be NULL). */
-vegas_status vegas_flow_get_samples(vegas_ctx* ctx, float* w, float* lj, float* omega);
+ * log J_F [N], weight omega [N] and the final Gaussian coordinates z_4
+ * [N][16] (FP32, host pointers; any may be NULL). */
+vegas_status vegas_flow_get_samples(vegas_ctx* ctx, float* w, float* lj, float* omega, float* z);
 /* Test hook, synchronous.  Gradient of the warp's training loss on the last
  * warped iteration's samples (no parameter update), host pointer
  * grad[n_params].  Loss: sum_k c_k log J_F(F^-1(w_k)) with c_k as set by

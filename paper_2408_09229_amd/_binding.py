@@ -81,6 +81,11 @@ _DECL = {
     "vegas_create": (_st, [C.POINTER(vegas_config), C.POINTER(vegas_integrand), _vp, C.c_size_t, _vp,
                            C.POINTER(_vp)]),
     "vegas_create_static": (_st, [C.POINTER(vegas_config), C.POINTER(vegas_integrand), _vp, C.POINTER(_vp)]),
+    "vegas_create_user": (_st, [C.POINTER(vegas_config), C.POINTER(vegas_integrand), _vp, _vp, C.c_size_t, _vp,
+                                C.POINTER(_vp)]),
+    "vegas_user_compile": (_st, [C.c_char_p, C.c_int32, C.c_int32, C.POINTER(_vp)]),
+    "vegas_user_check": (_st, [C.c_char_p, C.c_int32, C.c_int32]),
+    "vegas_user_destroy": (None, [_vp]),
     "vegas_adapt": (_st, [_vp, C.c_int32]),
     "vegas_integrate": (_st, [_vp, C.c_int32]),
     "vegas_result": (_st, [_vp, C.POINTER(vegas_estimate)]),
@@ -89,6 +94,7 @@ _DECL = {
     "vegas_get_map": (_st, [_vp, _vp]),
     "vegas_set_map": (_st, [_vp, _vp]),
     "vegas_set_params": (_st, [_vp, _vp]),
+    "vegas_set_adapt": (_st, [_vp, C.c_int32, C.c_int32]),
     "vegas_get_nh": (_st, [_vp, _vp]),
     "vegas_set_nh": (_st, [_vp, _vp]),
     "vegas_get_accumulators": (_st, [_vp, _vp, _vp, _vp]),
@@ -111,7 +117,7 @@ _DECL = {
     "vegas_flow_status": (_st, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "vegas_flow_get_params": (_st, [_vp, _vp]),
     "vegas_flow_set_params": (_st, [_vp, _vp]),
-    "vegas_flow_get_samples": (_st, [_vp, _vp, _vp, _vp]),
+    "vegas_flow_get_samples": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "vegas_flow_grad": (_st, [_vp, _vp]),
     "vegas_flow_adam_step": (_st, [_vp, _vp]),
     "vegas_mfma_probe": (_st, [_vp, _vp, _vp]),
@@ -188,6 +194,37 @@ def workspace_size(cfg: vegas_config, family, params, lo=None, hi=None) -> int:
     return n.value
 
 
+class UserIntegrand:
+    """An integrand compiled at run time (hipRTC) from device source that
+    defines ``__device__ vegas_real vegas_user_f(const vegas_real* x, int dim,
+    const double* params)`` (vegas_real: double for "f64", float for "f32")."""
+
+    def __init__(self, source: str, dim: int, precision: str = "f64"):
+        h = C.c_void_p()
+        check(vegas_user_compile(source.encode(), dim, PREC_FP64 if precision == "f64" else PREC_FP32, C.byref(h)),
+              "vegas_user_compile")
+        self.h = h
+        self.dim = dim
+
+    @staticmethod
+    def check(source: str, dim: int, precision: str = "f64"):
+        """Compile for gfx950 without a device (raises VegasError with the
+        compiler's log on failure)."""
+        check(vegas_user_check(source.encode(), dim, PREC_FP64 if precision == "f64" else PREC_FP32),
+              "vegas_user_check")
+
+    def close(self):
+        if getattr(self, "h", None):
+            vegas_user_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+VEGAS_USER = 12
+
+
 class Vegas:
     """One VEGAS+ problem on the current HIP device.
 
@@ -199,9 +236,12 @@ class Vegas:
     """
 
     def __init__(self, cfg: vegas_config, family: int, params, lo=None, hi=None, *, stream=None,
-                 device=None, static: bool = False):
+                 device=None, static: bool = False, user: "UserIntegrand" = None):
         import torch
         self.cfg = cfg
+        self.user = user          # kept alive with the context
+        if user is not None:
+            family = VEGAS_USER
         self._it = _Integrand(family, params, lo, hi)
         self.device = torch.device(device or "cuda")
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -214,8 +254,12 @@ class Vegas:
             n = C.c_size_t()
             check(vegas_workspace_size(C.byref(cfg), C.byref(self._it.s), C.byref(n)), "vegas_workspace_size")
             self.ws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
-            check(vegas_create(C.byref(cfg), C.byref(self._it.s), C.c_void_p(self.ws.data_ptr()), n.value,
-                               C.c_void_p(self.stream.cuda_stream), C.byref(h)), "vegas_create")
+            if user is not None:
+                check(vegas_create_user(C.byref(cfg), C.byref(self._it.s), user.h, C.c_void_p(self.ws.data_ptr()),
+                                        n.value, C.c_void_p(self.stream.cuda_stream), C.byref(h)), "vegas_create_user")
+            else:
+                check(vegas_create(C.byref(cfg), C.byref(self._it.s), C.c_void_p(self.ws.data_ptr()), n.value,
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(h)), "vegas_create")
         self.h = h
         self.info = vegas_info()
         check(vegas_get_info(self.h, C.byref(self.info)), "vegas_get_info")
@@ -261,6 +305,9 @@ class Vegas:
     def set_map(self, g):
         g = np.ascontiguousarray(g, dtype=np.float64)
         check(vegas_set_map(self.h, _dptr(g)), "vegas_set_map")
+
+    def set_adapt(self, adapt_map: bool = True, adapt_strat: bool = True):
+        check(vegas_set_adapt(self.h, int(adapt_map), int(adapt_strat)), "vegas_set_adapt")
 
     def set_params(self, params):
         p = np.ascontiguousarray(params, dtype=np.float64)
@@ -399,14 +446,16 @@ class Vegas:
         g = np.ascontiguousarray(grad, dtype=np.float32)
         check(vegas_flow_adam_step(self.h, _dptr(g)), "vegas_flow_adam_step")
 
-    def flow_samples(self):
-        """(w [N][16], log J_F [N], omega [N]) of the last warped iteration."""
+    def flow_samples(self, with_z: bool = False):
+        """(w [N][16], log J_F [N], omega [N]) of the last warped iteration,
+        and the final Gaussian coordinates z_4 [N][16] with with_z."""
         n = self.cfg.n_eval
         w = np.zeros((n, 16), np.float32)
         lj = np.zeros(n, np.float32)
         om = np.zeros(n, np.float32)
-        check(vegas_flow_get_samples(self.h, _dptr(w), _dptr(lj), _dptr(om)), "vegas_flow_get_samples")
-        return w, lj, om
+        z = np.zeros((n, 16), np.float32) if with_z else None
+        check(vegas_flow_get_samples(self.h, _dptr(w), _dptr(lj), _dptr(om), _dptr(z)), "vegas_flow_get_samples")
+        return (w, lj, om, z) if with_z else (w, lj, om)
 
     def probe(self, t: int, k0: int, n: int):
         """Per-sample path for samples k0..k0+n-1 of iteration t (torch tensors)."""

@@ -71,6 +71,8 @@ int family_params(int fam, int D, const vegas_integrand* f)
     case VEGAS_SIN_EXP:
     case VEGAS_EXP_SQ:
     case VEGAS_MOROKOFF: return 1;
+    case VEGAS_USER:
+        return f->n_params >= 0 && f->n_params <= 4096 && (f->n_params == 0 || f->params) ? f->n_params : -1;
     default: return -1;
     }
 }
@@ -190,7 +192,7 @@ namespace {
 // Workspace carving: offsets of every device array (256-byte aligned).
 struct Plan {
     size_t prm, lo, hi, aux_d, aux_f, grid64, grid32, start[2], tfirst[2], v, qbuf, wg_part, side, fix_part,
-        histH, histC, partH, partC, Hsum, Csum, counters, bsum, boff, iter, ord_w, ord_bins, ord_m, total;
+        histH, histC, histCw, partH, partC, Hsum, Csum, counters, bsum, boff, iter, ord_w, ord_bins, ord_m, total;
 };
 
 Plan plan(const Geometry& g, int max_iter, bool ordered)
@@ -226,6 +228,8 @@ Plan plan(const Geometry& g, int max_iter, bool ordered)
     const size_t slots = g.lds_hist_ok ? (size_t)std::min(kMaxWG, g.n_tiles) : 1;
     p.histH = take(sizeof(double) * nb * slots);
     p.histC = take(sizeof(uint32_t) * nb * slots);
+    // the learned warp's iterations (dimension 16): FP64 count weights
+    p.histCw = g.D == kFlowDim ? take(sizeof(double) * nb) : 0;
     p.partH = take(sizeof(double) * nb * kHistParts);
     p.partC = take(sizeof(uint32_t) * nb * kHistParts);
     p.Hsum = take(sizeof(double) * nb);
@@ -260,6 +264,8 @@ struct vegas_ctx {
     std::vector<uint8_t> combined;     // per iteration: 1 = integrate
     int slots_last;                    // histogram slots written by the last fill
     bool have_prev;                    // previous estimate valid (FP32 histogram scale)
+    bool hist_weighted = false;        // the last fill wrote importance-weighted histograms (warp)
+    const vegas_user_fn* user = nullptr;   // integrand compiled at run time (family VEGAS_USER)
     bool timing;
     std::vector<hipEvent_t> events;    // 5 per timed iteration
 
@@ -268,7 +274,7 @@ struct vegas_ctx {
     bool flow_on = false;
     vegas_flow_config fcfg{};
     unsigned char* fws = nullptr;
-    size_t f_theta = 0, f_packed = 0, f_w = 0, f_lj = 0, f_om = 0, f_U = 0, f_G0 = 0, f_G1 = 0, f_part = 0,
+    size_t f_theta = 0, f_packed = 0, f_w = 0, f_z = 0, f_lj = 0, f_om = 0, f_U = 0, f_G0 = 0, f_G1 = 0, f_part = 0,
            f_grad = 0, f_m = 0, f_v = 0, f_sumsq = 0;
     int f_nwg = 0;                     // workgroups of the training passes
     int f_step = 0;                    // Adam steps taken
@@ -386,6 +392,7 @@ MapArgs map_args(vegas_ctx* c, int n_slots)
     m.alpha = c->cfg.adapt_map ? c->cfg.alpha : 0.0;
     m.hist_H = c->at<double>(c->p.histH);
     m.hist_C = c->at<uint32_t>(c->p.histC);
+    m.hist_Cw = c->hist_weighted ? c->at<double>(c->p.histCw) : nullptr;
     m.grid64 = c->at<double>(c->p.grid64);
     m.grid32 = c->at<float>(c->p.grid32);
     m.Hsum = c->at<double>(c->p.Hsum);
@@ -448,6 +455,7 @@ FillArgs fill_args(vegas_ctx* c, int t, unsigned long long* nonfinite)
     a.side = c->at<TileSide>(c->p.side);
     a.hist_H = c->at<double>(c->p.histH);
     a.hist_C = c->at<uint32_t>(c->p.histC);
+    a.hist_Cw = nullptr;
     a.vmax = c->vmax(t);
     a.nonfinite = nonfinite;
     return a;
@@ -458,12 +466,11 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
     if (c->n_run >= c->max_iter) return fail(VEGAS_ESTATE, "iteration log full (max_iter = %d)", c->max_iter);
     const int t = c->n_run;
     const bool fp64 = c->cfg.precision == VEGAS_PREC_FP64;
-    // LDS-privatised histograms unless LDS cannot hold them
-    const int lds_hist = c->g.lds_hist_ok ? 1 : 0;
     const int nb = c->g.D * c->g.ng;
     HIPCHK(launch_reset(c->vmax(t), 1, c->stream));
     HIPCHK(launch_reset(c->qmax(t), 1, c->stream));
     if (c->cfg.accum == VEGAS_ACC_ORDERED) {
+        c->hist_weighted = false;
         OrderedArgs o;
         o.sc = sample_const(c);
         o.t = (uint32_t)t;
@@ -491,15 +498,22 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
         c->have_prev = true;
         return VEGAS_OK;
     }
-    if (!lds_hist) {
-        HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histH), nb, c->stream));
-        HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histC), (nb + 1) / 2, c->stream));
-    }
-    const FillArgs a = fill_args(c, t, c->nonfinite());
     // with the judge on, every control_period-th iteration of the warp's
     // phase samples plain VEGAS+ (the control)
     const bool control = c->flow_on && c->fcfg.judge > 0 && (c->f_phase + 1) % c->fcfg.control_period == 0;
     const bool warp_now = c->flow_on && !control;
+    // the warped fill's histograms are importance-weighted FP64 sums in
+    // global memory (one slot)
+    const int lds_hist = warp_now ? 0 : (c->g.lds_hist_ok ? 1 : 0);
+    if (!lds_hist) {
+        HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histH), nb, c->stream));
+        if (warp_now) HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histCw), nb, c->stream));
+        else HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histC), (nb + 1) / 2, c->stream));
+    }
+    FillArgs a = fill_args(c, t, c->nonfinite());
+    a.lds_hist = lds_hist;
+    if (warp_now) a.hist_Cw = c->at<double>(c->p.histCw);
+    c->hist_weighted = warp_now;
     if (c->flow_on) HIPCHK(judge_mark(c, t, 0));
     // the warped fill keeps the map in LDS; k_fill reads it through the cache
     const size_t lds = fill_lds_bytes(c->g.D, c->g.ng, fp64, lds_hist, c->g.tile, c->g.n_aux, warp_now ? 1 : 0);
@@ -513,11 +527,14 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
         fa.theta = reinterpret_cast<const float*>(c->fws + c->f_theta);
         fa.packed = c->fws + c->f_packed;
         fa.w = reinterpret_cast<float*>(c->fws + c->f_w);
+        fa.z = reinterpret_cast<float*>(c->fws + c->f_z);
         fa.lj = reinterpret_cast<float*>(c->fws + c->f_lj);
         HIPCHK(c->fmark());
         HIPCHK(launch_flow_sample(fa, 2 * c->n_wg, c->stream));
         HIPCHK(c->fmark());
         HIPCHK(launch_fill_flow(a, fa.w, fa.lj, reinterpret_cast<float*>(c->fws + c->f_om), c->n_wg, lds, c->stream));
+    } else if (c->user) {
+        HIPCHK(launch_user_fill(c->user, a, c->n_wg, lds, c->stream));
     } else {
         HIPCHK(launch_fill(a, fp64, c->n_wg, lds, c->stream));
     }
@@ -682,7 +699,7 @@ void ctx_set_stream(vegas_ctx* c, hipStream_t s) { c->stream = s; }
 
 vegas_status ctx_fill_pass(vegas_ctx* c)
 {
-    if (c->flow_on || c->cfg.accum == VEGAS_ACC_ORDERED)
+    if (c->flow_on || c->user || c->cfg.accum == VEGAS_ACC_ORDERED)
         return fail(VEGAS_EUNSUPPORTED, "a bare fill pass is for the plain FP64 / Kahan iteration");
     const int t = c->n_run;
     const bool fp64 = c->cfg.precision == VEGAS_PREC_FP64;
@@ -731,14 +748,29 @@ vegas_status vegas_workspace_size(const vegas_config* cfg, const vegas_integrand
     return VEGAS_OK;
 }
 
-vegas_status vegas_create(const vegas_config* cfg, const vegas_integrand* f, void* d_workspace, size_t bytes,
-                          void* hip_stream, vegas_ctx** out)
+}  // extern "C"
+
+namespace vgh {
+
+// a context on the caller's workspace; user: the compiled integrand of
+// family VEGAS_USER (else null)
+vegas_status create_ctx(const vegas_config* cfg, const vegas_integrand* f, const vegas_user_fn* user,
+                        void* d_workspace, size_t bytes, void* hip_stream, vegas_ctx** out)
 {
     if (!out) return fail(VEGAS_EINVAL, "null out");
     *out = nullptr;
     Geometry g;
     vegas_status s = geometry(cfg, f, &g);
     if (s != VEGAS_OK) return s;
+    if ((f->family == VEGAS_USER) != (user != nullptr))
+        return fail(VEGAS_EINVAL, "family VEGAS_USER goes with a compiled integrand (vegas_create_user)");
+    if (user) {
+        if (user_fn_dim(user) != cfg->dim || user_fn_precision(user) != cfg->precision)
+            return fail(VEGAS_EINVAL, "the compiled integrand is for dim %d precision %d, the config has %d and %d",
+                        user_fn_dim(user), user_fn_precision(user), cfg->dim, cfg->precision);
+        if (cfg->accum == VEGAS_ACC_ORDERED)
+            return fail(VEGAS_EUNSUPPORTED, "ORDERED accumulation does not take compiled integrands");
+    }
     const int max_iter = cfg->max_iter > 0 ? cfg->max_iter : 4096;
     const Plan p = plan(g, max_iter, cfg->accum == VEGAS_ACC_ORDERED);
     if (!d_workspace) return fail(VEGAS_EINVAL, "null workspace");
@@ -752,6 +784,7 @@ vegas_status vegas_create(const vegas_config* cfg, const vegas_integrand* f, voi
     c->cfg.max_iter = max_iter;
     c->g = g;
     c->p = p;
+    c->user = user;
     c->params.assign(f->params, f->params + g.n_params);
     c->lo.resize(g.D);
     c->hi.resize(g.D);
@@ -810,6 +843,25 @@ vegas_status vegas_create(const vegas_config* cfg, const vegas_integrand* f, voi
 #undef HIPCHK_C
     *out = c;
     return VEGAS_OK;
+}
+
+}  // namespace vgh
+
+extern "C" {
+
+vegas_status vegas_create(const vegas_config* cfg, const vegas_integrand* f, void* d_workspace, size_t bytes,
+                          void* hip_stream, vegas_ctx** out)
+{
+    return create_ctx(cfg, f, nullptr, d_workspace, bytes, hip_stream, out);
+}
+
+vegas_status vegas_create_user(const vegas_config* cfg, const vegas_integrand* f, const vegas_user_fn* fn,
+                               void* d_workspace, size_t bytes, void* hip_stream, vegas_ctx** out)
+{
+    if (out) *out = nullptr;
+    if (!fn) return fail(VEGAS_EINVAL, "null compiled integrand");
+    if (!f || f->family != VEGAS_USER) return fail(VEGAS_EINVAL, "vegas_create_user takes family VEGAS_USER");
+    return create_ctx(cfg, f, fn, d_workspace, bytes, hip_stream, out);
 }
 
 void vegas_destroy(vegas_ctx* ctx)
@@ -1022,6 +1074,15 @@ vegas_status vegas_set_params(vegas_ctx* c, const double* params)
     return VEGAS_OK;
 }
 
+vegas_status vegas_set_adapt(vegas_ctx* c, int32_t adapt_map, int32_t adapt_strat)
+{
+    if (!c || (adapt_map != 0 && adapt_map != 1) || (adapt_strat != 0 && adapt_strat != 1))
+        return fail(VEGAS_EINVAL, "bad arguments");
+    c->cfg.adapt_map = adapt_map;
+    c->cfg.adapt_strat = adapt_strat;
+    return VEGAS_OK;
+}
+
 vegas_status vegas_get_nh(vegas_ctx* c, uint32_t* nh)
 {
     if (!c || !nh) return fail(VEGAS_EINVAL, "bad arguments");
@@ -1071,6 +1132,7 @@ vegas_status vegas_set_accumulators(vegas_ctx* c, const double* H, const double*
     std::memcpy(&bits, &vmax, sizeof bits);
     const unsigned long long zero = 0;
     const int t = c->n_run;
+    c->hist_weighted = false;
     HIPCHK(hipMemcpy(c->at<double>(c->p.histH), H, sizeof(double) * nb, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->at<uint32_t>(c->p.histC), cu.data(), sizeof(uint32_t) * nb, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->at<double>(c->p.v), v, sizeof(double) * c->g.n_cubes, hipMemcpyHostToDevice));
@@ -1124,6 +1186,7 @@ vegas_status vegas_sample_probe(vegas_ctx* c, uint32_t t, uint64_t k0, int64_t n
                                 uint32_t* d_bins, double* d_delta, double* d_x, double* d_jac, double* d_f)
 {
     if (!c || n < 0) return fail(VEGAS_EINVAL, "bad arguments");
+    if (c->user) return fail(VEGAS_EUNSUPPORTED, "the sample probe does not take compiled integrands");
     if (n == 0) return VEGAS_OK;
     if (k0 + (uint64_t)n > c->g.n_eval) return fail(VEGAS_EINVAL, "sample range beyond n_eval");
     const bool fp64 = c->cfg.precision == VEGAS_PREC_FP64;
@@ -1153,7 +1216,7 @@ vegas_status vegas_sample_probe(vegas_ctx* c, uint32_t t, uint64_t k0, int64_t n
 namespace {
 
 struct FlowPlan {
-    size_t theta, packed, w, lj, om, U, G0, G1, part, seg, grad, m, v, sumsq, acc, total;
+    size_t theta, packed, w, z, lj, om, U, G0, G1, part, seg, grad, m, v, sumsq, acc, total;
 };
 
 FlowPlan flow_plan(uint32_t n_eval, int n_wg)
@@ -1168,6 +1231,7 @@ FlowPlan flow_plan(uint32_t n_eval, int n_wg)
     p.theta = take(sizeof(float) * kFParams);
     p.packed = take((size_t)16 * kFlowLayers * kPLayer);
     p.w = take(sizeof(float) * kFlowDim * (size_t)n_eval);
+    p.z = take(sizeof(float) * kFlowDim * (size_t)n_eval);
     p.lj = take(sizeof(float) * (size_t)n_eval);
     p.om = take(sizeof(float) * (size_t)n_eval);
     p.U = take(sizeof(float) * 3 * kFlowDim * (size_t)n_eval);
@@ -1201,7 +1265,7 @@ FlowTrainArgs flow_train_args(vegas_ctx* c, uint32_t stride, uint32_t off)
     a.layer = 0;
     a.theta = reinterpret_cast<const float*>(c->fws + c->f_theta);
     a.packed = c->fws + c->f_packed;
-    a.w = reinterpret_cast<const float*>(c->fws + c->f_w);
+    a.zf = reinterpret_cast<const float*>(c->fws + c->f_z);
     a.om = reinterpret_cast<const float*>(c->fws + c->f_om);
     a.sumsq = reinterpret_cast<const double*>(c->fws + c->f_sumsq);
     a.gamma = c->fcfg.loss == 1 ? 1 : 2;
@@ -1432,6 +1496,7 @@ vegas_status vegas_flow_attach(vegas_ctx* c, const vegas_flow_config* cfg, const
     c->f_theta = p.theta;
     c->f_packed = p.packed;
     c->f_w = p.w;
+    c->f_z = p.z;
     c->f_lj = p.lj;
     c->f_om = p.om;
     c->f_U = p.U;
@@ -1558,7 +1623,7 @@ vegas_status vegas_flow_get_params(vegas_ctx* c, float* params)
     return VEGAS_OK;
 }
 
-vegas_status vegas_flow_get_samples(vegas_ctx* c, float* w, float* lj, float* om)
+vegas_status vegas_flow_get_samples(vegas_ctx* c, float* w, float* lj, float* om, float* z)
 {
     if (!c) return fail(VEGAS_EINVAL, "bad arguments");
     if (!c->flow_attached) return fail(VEGAS_ESTATE, "no flow attached");
@@ -1567,6 +1632,7 @@ vegas_status vegas_flow_get_samples(vegas_ctx* c, float* w, float* lj, float* om
     if (w) HIPCHK(hipMemcpy(w, c->fws + c->f_w, sizeof(float) * kFlowDim * n, hipMemcpyDeviceToHost));
     if (lj) HIPCHK(hipMemcpy(lj, c->fws + c->f_lj, sizeof(float) * n, hipMemcpyDeviceToHost));
     if (om) HIPCHK(hipMemcpy(om, c->fws + c->f_om, sizeof(float) * n, hipMemcpyDeviceToHost));
+    if (z) HIPCHK(hipMemcpy(z, c->fws + c->f_z, sizeof(float) * kFlowDim * n, hipMemcpyDeviceToHost));
     return VEGAS_OK;
 }
 

@@ -132,6 +132,7 @@ __device__ __noinline__ void batch_item(ItemCall c0, unsigned char* smem)
     io.side = c.side + uni(in.tile0);
     io.hist_H = nullptr;
     io.hist_C = nullptr;
+    io.hist_Cw = nullptr;
     for (uint32_t j = 0; j < c.n_tiles; ++j)
         fill_tile<R, MAXD, KAHAN, false>((int)(c.tile0 + j), io, L, sp, totI, totV, vmax, bad);
 

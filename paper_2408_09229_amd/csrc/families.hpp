@@ -22,7 +22,7 @@ namespace vg {
 
 enum : int { F_GAUSS_DIAG = 1, F_GENZ_PPEAK = 2, F_GENZ_GAUSS = 3, F_GAUSS_CORR = 4,
              F_LINEAR = 5, F_ROOS = 6, F_CONST = 7, F_COSINE = 8, F_SIN_EXP = 9, F_EXP_SQ = 10,
-             F_MOROKOFF = 11 };
+             F_MOROKOFF = 11, F_USER = 12 };
 
 constexpr double kLn2 = 0.69314718055994530942;
 

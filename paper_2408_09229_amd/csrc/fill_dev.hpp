@@ -242,6 +242,7 @@ struct TileIO {
     TileSide* side;               // [n_tiles]
     double* hist_H;               // global histogram (when not in LDS)
     uint32_t* hist_C;
+    double* hist_Cw;              // paths with weighted histograms: FP64 count weights
     const void* grid;             // the map in global memory (null: read the LDS copy)
 };
 
@@ -391,7 +392,21 @@ __device__ __forceinline__ void fill_tile(int tile, const TileIO& io, const Fill
                 }
                 const double wd = (double)w;
                 const double w2 = wd * wd;
-                if (io.lds_hist) {
+                if constexpr (Path::kWeightedHist) {
+                    // the warped path's samples have density q = 1/J_F in w:
+                    // the map's bin averages of w^2 over uniform points are
+                    // sum (w^2 / J_F) / sum J_F (global memory)
+                    const double jf = sp.last_jf();
+                    if (jf > 0.0 && __builtin_isfinite(jf)) {
+                        const double h = w2 / jf;
+#pragma unroll
+                        for (int d = 0; d < MAXD; ++d) {
+                            const uint32_t bi = (uint32_t)d * ng + bins[d];
+                            unsafeAtomicAdd(io.hist_H + bi, h);
+                            unsafeAtomicAdd(io.hist_Cw + bi, jf);
+                        }
+                    }
+                } else if (io.lds_hist) {
 #pragma unroll
                     for (int d = 0; d < MAXD; ++d) {
                         if (Path::kExact || d < D) {
@@ -708,6 +723,7 @@ __device__ __forceinline__ void fill_body(const FillArgs& a, unsigned char* smem
     io.side = a.side;
     io.hist_H = a.hist_H;
     io.hist_C = a.hist_C;
+    io.hist_Cw = nullptr;
     io.grid = a.grid;
 
     __syncthreads();

@@ -1,12 +1,13 @@
 // The learned warp on gfx950: packing of the BF16 MFMA operands, the
-// sampling pass (stratified y -> w = F(y), log J_F), and the fill of an
-// iteration through the warp (weight f(map(w)) J_map(w) J_F(y)).
+// sampling pass (stratified y -> z_0 = Phi^-1(y) -> four affine coupling
+// layers -> w = Phi(z_4), log J_F), and the fill of an iteration through the
+// warp (weight f(map(w)) J_map(w) J_F(y)).
 //
 // One wavefront evaluates the flow for 32 samples at a time.  Its matrix
 // products are v_mfma_f32_32x32x16_bf16 with the samples as rows; a layer's
 // hidden activations go through LDS to change from the product's output
-// layout to the next product's input layout, and the bin logits go through
-// LDS to the lanes that move each sample's axes.
+// layout to the next product's input layout, and the conditioner outputs go
+// through LDS to the lanes that move each sample's axes.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -49,16 +50,15 @@ __global__ void k_flow_pack(const float* __restrict__ theta, bf16x8* __restrict_
         const int nt = r >> 8, ks = (r >> 6) & 3;
         const int n = nt * 32 + n32;
         for (int j = 0; j < 8; ++j) v[j] = W2[n * kFlowHidden + ks * 16 + kb + j];
-    } else if (r < kPR3) {                // F3[nt][ks]: B[k][n] = W3[n][k]
+    } else if (r < kPR3) {                // F3[ks]: B[k][n = output] = W3[n][k], n < 16
         r -= kPF3;
-        const int nt = r >> 8, ks = (r >> 6) & 3;
-        const int n = nt * 32 + n32;
-        for (int j = 0; j < 8; ++j) v[j] = W3[n * kFlowHidden + ks * 16 + kb + j];
-    } else if (r < kPR2) {                // R3[nt][ks]: B[k = o][n = h] = W3[o][h]
+        const int ks = r >> 6;
+        for (int j = 0; j < 8; ++j) v[j] = n32 < kFlowOut ? W3[n32 * kFlowHidden + ks * 16 + kb + j] : 0.f;
+    } else if (r < kPR2) {                // R3[nt]: B[k = o][n = h] = W3[o][h]
         r -= kPR3;
-        const int nt = r >> 9, ks = (r >> 6) & 7;
+        const int nt = r >> 6;
         const int n = nt * 32 + n32;
-        for (int j = 0; j < 8; ++j) v[j] = W3[(ks * 16 + kb + j) * kFlowHidden + n];
+        for (int j = 0; j < 8; ++j) v[j] = W3[(kb + j) * kFlowHidden + n];
     } else if (r < kPR1) {                // R2[nt][ks]: B[k = n2][n = n1] = W2[n2][n1]
         r -= kPR2;
         const int nt = r >> 8, ks = (r >> 6) & 3;
@@ -78,8 +78,8 @@ __global__ void k_flow_pack(const float* __restrict__ theta, bf16x8* __restrict_
 
 // ---------------------------------------------------------------------------
 // starting weights: W1 and W2 uniform in +-1/sqrt(fan_in) (fan_in 8 and 64),
-// every other parameter 0.  The zero last layer makes every bin probability
-// exactly 1/16, so F starts as the identity.  Parameter i draws word 0 of
+// every other parameter 0.  The zero last layer makes every log-scale and
+// shift exactly 0, so F starts as the identity.  Parameter i draws word 0 of
 // Philox4x32-10 with key = seed and counter (i, 0, 0, "FLOW"); its top 23
 // bits m give the odd multiple (2m + 1 - 2^23) 2^-23 of the unit interval's
 // half width, exact in FP32, which the bound then scales (one rounding).
@@ -153,10 +153,10 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_sample(FlowSampleArgs a)
             dig[d] = hc - q * sc.nst;
             hc = q;
         }
-        // the stratified point y = (s 2^33 + 2r + 1) / (N_st 2^33): the
-        // numerator is exact in FP64 (s < 2^20), one FP64 division, then
-        // rounded to FP32
-        float z[8];
+        // the stratified point y = (s 2^33 + 2r + 1) / (N_st 2^33) and
+        // z_0 = Phi^-1(y): numerator and den - numerator are exact in FP64
+        // (s < 2^20), so min(y, 1 - y) is one FP64 division, rounded to FP32
+        float z0[8], z[8];
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             const W4 o = philox10(k, 0u, a.t, sc.ctr3 | (uint32_t)(2 * half + b), keys);
@@ -164,7 +164,10 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_sample(FlowSampleArgs a)
             for (int q = 0; q < 4; ++q) {
                 const int j = 4 * b + q;
                 const double num = fma((double)dig[8 * half + j], 0x1p33, 2.0 * (double)o.v[q] + 1.0);
-                z[j] = (float)(num / den);
+                const bool upper = 2.0 * num > den;
+                const float m = (float)((upper ? den - num : num) / den);
+                z0[j] = flow_phi_inv(m, upper);
+                z[j] = z0[j];
             }
         }
         float lj = 0.f;
@@ -175,26 +178,27 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_sample(FlowSampleArgs a)
             for (int j = 0; j < 8; ++j) {
                 const int c = 8 * half + j;
                 if (flow_in_a(l, c)) continue;
-                float p[kFlowBins];
-                flow_probs(S.o[wave] + n32 * (kFlowHalf * kFlowBins) + flow_pos(l, c) * kFlowBins, p);
-                const float zk = z[j] * (float)kFlowBins;
-                const int bin = min((int)zk, kFlowBins - 1);
-                float cum = 0.f, pb = p[0];
-#pragma unroll
-                for (int q = 0; q < kFlowBins; ++q) {
-                    if (q < bin) cum += p[q];
-                    if (q == bin) pb = p[q];
-                }
-                z[j] = fminf(fmaxf(fmaf(zk - (float)bin, pb, cum), 0.f), 1.f);
-                lj += logf((float)kFlowBins * pb);
+                const float* ob = S.o[wave] + n32 * kFlowOut + flow_pos(l, c);
+                const float s = flow_scale(ob[0]);
+                z[j] = fmaf(z[j], expf(s), ob[kFlowHalf]);
+                lj += s;
             }
             __syncthreads();
+        }
+        float wv[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            lj += 0.5f * (z0[j] - z[j]) * (z0[j] + z[j]);
+            wv[j] = flow_phi(z[j]);
         }
         lj += __shfl_xor(lj, 32, 64);
         if (live && chunk * 32u + (uint32_t)n32 < N) {
             float4* wo = reinterpret_cast<float4*>(a.w + (size_t)k * kFlowDim + 8 * half);
-            wo[0] = make_float4(z[0], z[1], z[2], z[3]);
-            wo[1] = make_float4(z[4], z[5], z[6], z[7]);
+            wo[0] = make_float4(wv[0], wv[1], wv[2], wv[3]);
+            wo[1] = make_float4(wv[4], wv[5], wv[6], wv[7]);
+            float4* zo = reinterpret_cast<float4*>(a.z + (size_t)k * kFlowDim + 8 * half);
+            zo[0] = make_float4(z[0], z[1], z[2], z[3]);
+            zo[1] = make_float4(z[4], z[5], z[6], z[7]);
             if (half == 0) a.lj[k] = lj;
         }
     }
@@ -205,10 +209,13 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_sample(FlowSampleArgs a)
 // ---------------------------------------------------------------------------
 // Sample path of the warped fill: the point is w_k from the sampling pass
 // (FP32), its map bin floor(w N_g), and the weight carries J_F = exp(lj_k).
-// The stratum digits are not needed (the sampling pass used them).
+// The stratum digits are not needed (the sampling pass used them).  The
+// map's histograms weigh the sample by 1/J_F (see fill_tile).
 template <int FAM>
 struct WarpedPath {
     static constexpr bool kExact = true;       // D = 16 always
+    static constexpr bool kWeightedHist = true;
+    float jf = 1.f;                            // J_F of the last sample evaluated
     const SampleConst& sc;
     Fn<float, FAM> fn;
     float ngR;
@@ -225,6 +232,7 @@ struct WarpedPath {
         ngR = (float)c.ng;
         ngD = (double)c.ng;
     }
+    __device__ __forceinline__ double last_jf() const { return (double)jf; }
     __device__ __forceinline__ void digits(uint32_t, uint32_t (&)[kFlowDim]) const {}
     __device__ __forceinline__ void next_digits(uint32_t (&)[kFlowDim]) const {}
 
@@ -262,7 +270,8 @@ struct WarpedPath {
             fn.axis(d, fmaf(dx, delta, xl));
         }
         f = fn.finish();
-        J = J * expf(lj[k]);
+        jf = expf(lj[k]);
+        J = J * jf;
         const float wt = J * f;
         om[k] = __builtin_isfinite(wt) ? wt : 0.f;
         return wt;
@@ -305,6 +314,7 @@ __global__ __launch_bounds__(kFillThreads) void k_fill_flow(FillArgs a, const fl
     io.side = a.side;
     io.hist_H = a.hist_H;
     io.hist_C = a.hist_C;
+    io.hist_Cw = a.hist_Cw;
     __syncthreads();
     for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x)
         fill_tile<float, kFlowDim, KAHAN, false>(tile, io, L, sp, totI, totV, vmax, bad);

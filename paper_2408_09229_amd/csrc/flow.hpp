@@ -2,13 +2,14 @@
 // (stratified y -> w = F(y) -> x = map(w)); shapes, parameter layout and the
 // launch records of its kernels.
 //
-// Four coupling layers.  Layer l keeps the axes A_l and moves the others
-// (B_l): A = {0..7}, {8..15}, even axes, odd axes.  The conditioner of a
-// layer is an MLP 8 -> 64 -> 64 -> 8 x 16 with ReLU, fed x = 2 z_A - 1; its
-// 16 outputs per moved axis are bin logits, p = (1 - eps) softmax + eps/16,
-// and the axis moves by the piecewise-linear CDF of p (derivative 16 p_b in
-// bin b), so log J_F is a sum of logs and exact.  Matrix products run on
-// BF16 MFMA with FP32 accumulation; everything else is FP32.
+// The flow works in Gaussian coordinates: z_0 = Phi^-1(y), four affine
+// coupling layers, w = Phi(z_4).  Layer l keeps the axes A_l and moves the
+// others (B_l): A = {0..7}, {8..15}, even axes, odd axes.  The conditioner of
+// a layer is an MLP 8 -> 64 -> 64 -> 16 with ReLU, fed x = z_A / 2; its 16
+// outputs are the raw log-scales a (8) and the shifts t (8) of the moved
+// axes, s = 3 tanh(a / 3) and z_B -> z_B e^s + t.  log J_F = sum s +
+// sum_d (z_0d^2 - z_4d^2) / 2, exact.  Matrix products run on BF16 MFMA with
+// FP32 accumulation; everything else is FP32.
 #pragma once
 #include <stdint.h>
 
@@ -18,19 +19,20 @@ namespace vg {
 
 constexpr int kFlowDim = 16;
 constexpr int kFlowHidden = 64;
-constexpr int kFlowBins = 16;
 constexpr int kFlowLayers = 4;
 constexpr int kFlowHalf = 8;                   // |A| = |B|
-constexpr float kFlowEps = 1e-3f;
+constexpr int kFlowOut = 2 * kFlowHalf;        // log-scales, then shifts
+constexpr float kFlowSMax = 3.f;               // |s| < 3
+constexpr float kFlowXScale = 0.5f;            // conditioner input z_A / 2
 
 // per-layer parameter offsets (floats; row-major W[out][in])
 constexpr int kFW1 = 0;                                    // [64][8]
 constexpr int kFB1 = kFW1 + kFlowHidden * kFlowHalf;       // [64]
 constexpr int kFW2 = kFB1 + kFlowHidden;                   // [64][64]
 constexpr int kFB2 = kFW2 + kFlowHidden * kFlowHidden;     // [64]
-constexpr int kFW3 = kFB2 + kFlowHidden;                   // [128][64]
-constexpr int kFB3 = kFW3 + kFlowHalf * kFlowBins * kFlowHidden;   // [128]
-constexpr int kFLayer = kFB3 + kFlowHalf * kFlowBins;      // 13056
+constexpr int kFW3 = kFB2 + kFlowHidden;                   // [16][64]
+constexpr int kFB3 = kFW3 + kFlowOut * kFlowHidden;        // [16]
+constexpr int kFLayer = kFB3 + kFlowOut;                   // 5776
 constexpr int kFParams = kFlowLayers * kFLayer;
 
 // Packed BF16 operands of one layer, one 8-value entry per (tile, k-step,
@@ -38,17 +40,17 @@ constexpr int kFParams = kFlowLayers * kFLayer;
 // B[8 (l/32) + j][l % 32], j < 8):
 //   F1: x (k = axis, 16 with the B axes zeroed) . W1^T      [2 n-tiles]
 //   F2: h1 . W2^T                                          [2 n-tiles][4 k]
-//   F3: h2 . W3^T                                          [4 n-tiles][4 k]
-//   R3: dO . W3     (backward)                             [2 n-tiles][8 k]
+//   F3: h2 . W3^T (n = output, 16 of 32 used)              [1 n-tile][4 k]
+//   R3: dO . W3     (backward; k = output)                 [2 n-tiles][1 k]
 //   R2: dA2 . W2                                           [2 n-tiles][4 k]
 //   R1: dA1 . W1 (n = axis, 16 of 32 used)                 [1 n-tile][4 k]
 constexpr int kPF1 = 0;
 constexpr int kPF2 = kPF1 + 2 * 64;
 constexpr int kPF3 = kPF2 + 2 * 4 * 64;
-constexpr int kPR3 = kPF3 + 4 * 4 * 64;
-constexpr int kPR2 = kPR3 + 2 * 8 * 64;
+constexpr int kPR3 = kPF3 + 4 * 64;
+constexpr int kPR2 = kPR3 + 2 * 64;
 constexpr int kPR1 = kPR2 + 2 * 4 * 64;
-constexpr int kPLayer = kPR1 + 4 * 64;           // 3456 entries of 16 bytes
+constexpr int kPLayer = kPR1 + 4 * 64;           // 1792 entries of 16 bytes
 
 // axis c is conditioning (in A) in layer l
 __host__ __device__ inline bool flow_in_a(int l, int c)
@@ -64,30 +66,31 @@ struct FlowSampleArgs {
     const uint32_t* start;        // [N_c+1]
     const float* theta;           // FP32 parameters (biases are read from here)
     const void* packed;           // [4][kPLayer] x 16 bytes of BF16
-    float* w;                     // [N][16] out
+    float* w;                     // [N][16] out: w = Phi(z_4)
+    float* z;                     // [N][16] out: z_4 (the training data)
     float* lj;                    // [N] out: log J_F
 };
 
 // Training records.  The loss of an iteration is
 // L = sum_k c_k log J_F(F^-1(w_k)), c_k = |omega_k|^gamma / sum |omega|^gamma,
-// and its
-// gradient is taken through the inverse chain u_3 = w -> u_2 -> u_1 -> u_0:
-// the inverse pass stores u_0..u_2, then one backward pass per layer
-// (l = 0, 1, 2, 3) turns the upstream gradient g = dL/du_{l-1} into
-// dL/du_l and the layer's parameter gradient.
+// and its gradient is taken through the inverse chain u_4 = z_4 -> u_3 ->
+// u_2 -> u_1 -> u_0 (Gaussian coordinates): the inverse pass stores u_1..u_3
+// and the upstream gradient dL/du_0 = c z_0, then one backward pass per
+// layer (l = 0, 1, 2, 3) turns g = dL/du_l into dL/du_{l+1} and the layer's
+// parameter gradient.
 struct FlowTrainArgs {
     uint32_t n;                   // training samples: j = 0 .. n-1 is sample off + j stride
     uint32_t stride, off;
     int32_t layer;                // backward pass: layer index
     const float* theta;
     const void* packed;
-    const float* w;               // [N_ev][16], read at the training samples
+    const float* zf;              // [N_ev][16] z_4, read at the training samples
     const float* om;              // [N_ev] sample weights, read at the training samples
     const double* sumsq;          // sum of |om|^gamma
     int32_t gamma;                // 2: variance loss, 1: KL loss
-    float* U;                     // [3][n][16]: u_0, u_1, u_2 of the training samples
-    const float* g_in;            // [n][16] upstream gradient (null: zero)
-    float* g_out;                 // [n][16]
+    float* U;                     // [3][n][16]: u_1, u_2, u_3 of the training samples
+    const float* g_in;            // [n][16] upstream gradient dL/du_layer
+    float* g_out;                 // [n][16] dL/du_{layer+1}
     float* part;                  // [n_wg][kFLayer] per-workgroup gradient
 };
 

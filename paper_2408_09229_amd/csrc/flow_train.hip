@@ -4,17 +4,21 @@
 // |omega|^gamma.  gamma = 2: its gradient is a positive multiple of the
 // gradient of the estimator's variance (the warp's density at w is
 // 1 / J_F(F^-1(w))); gamma = 1: of the KL divergence from the normalised
-// |f| to the warp's density, whose sample gradient has lighter tails.  The gradient goes through
-// the inverse chain u_3 = w -> u_2 -> u_1 -> u_0:
+// |f| to the warp's density, whose sample gradient has lighter tails.  The
+// gradient goes through the inverse chain in Gaussian coordinates,
+// u_4 = z_4 -> u_3 -> u_2 -> u_1 -> u_0, where log J_F depends on the
+// parameters through each layer's log-scales and through u_0 (the term
+// u_0^2 / 2):
 //   k_flow_sumsq    sum of |omega|^gamma (block partials, then in order)
-//   k_flow_inverse  u_2, u_1, u_0 of every sample (MLP on MFMA)
-//   k_flow_grad     one coupling layer l = 0..3 in turn: from the upstream
-//                   g = dL/du_{l-1}, the layer's log-Jacobian and inverse
-//                   transform give dL/dlogits; the MLP backward runs on MFMA
-//                   (dO W3, dA2 W2, dA1 W1); the weight gradients dW =
-//                   sum_samples delta^T activation are MFMA products over the
-//                   workgroup's 128 samples, each wave owning some output
-//                   tiles, accumulated across the workgroup's chunks
+//   k_flow_inverse  u_3, u_2, u_1 of every training sample (MLP on MFMA) and
+//                   the upstream gradient dL/du_0 = c u_0
+//   k_flow_grad     one coupling layer l = 0..3 in turn: from g = dL/du_l,
+//                   the layer's log-scales and inverse transform give
+//                   dL/d(a, t); the MLP backward runs on MFMA (dO W3, dA2 W2,
+//                   dA1 W1); the weight gradients dW = sum_samples delta^T
+//                   activation are MFMA products over the workgroup's 128
+//                   samples, each wave owning some output tiles,
+//                   accumulated across the workgroup's chunks
 //   k_flow_reduce   per-workgroup gradients summed in a fixed order
 //   k_flow_adam     Adam on the FP32 parameters (then the BF16 repack)
 #include <hip/hip_runtime.h>
@@ -66,6 +70,30 @@ __global__ __launch_bounds__(kSumThreads) void k_flow_sumsq_final(double* part)
 // ---------------------------------------------------------------------------
 // inverse pass
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void load8(const float* p, float (&v)[8])
+{
+    const float4* q = reinterpret_cast<const float4*>(p);
+    const float4 a = q[0], b = q[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+__device__ __forceinline__ void store8(float* p, const float (&v)[8])
+{
+    float4* q = reinterpret_cast<float4*>(p);
+    q[0] = make_float4(v[0], v[1], v[2], v[3]);
+    q[1] = make_float4(v[4], v[5], v[6], v[7]);
+}
+
+// c_k of a training sample in double, rounded to FP32: tiny weights (an
+// integrand that underflows almost everywhere) put 1/sum beyond FP32
+__device__ __forceinline__ float train_coef(const FlowTrainArgs& a, uint32_t k, bool valid)
+{
+    const double ss = *a.sumsq;
+    const double inv_ss = ss > 0.0 && ss < INFINITY ? 1.0 / ss : 0.0;
+    const double om = valid ? fabs((double)a.om[(size_t)a.off + (size_t)k * a.stride]) : 0.0;
+    return (float)((a.gamma == 2 ? om * om : om) * inv_ss);
+}
+
 __global__ __launch_bounds__(kFlowThreads) void k_flow_inverse(FlowTrainArgs a)
 {
     __shared__ FlowLds S;
@@ -84,39 +112,27 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_inverse(FlowTrainArgs a)
         const uint32_t k = live ? min(chunk * 32u + (uint32_t)n32, N - 1u) : 0u;
         const bool valid = live && chunk * 32u + (uint32_t)n32 < N;
         float z[8];
-        const size_t src = (size_t)a.off + (size_t)k * a.stride;
-        const float4* wi = reinterpret_cast<const float4*>(a.w + src * kFlowDim + 8 * half);
-        const float4 w0 = wi[0], w1 = wi[1];
-        z[0] = w0.x; z[1] = w0.y; z[2] = w0.z; z[3] = w0.w;
-        z[4] = w1.x; z[5] = w1.y; z[6] = w1.z; z[7] = w1.w;
+        load8(a.zf + ((size_t)a.off + (size_t)k * a.stride) * kFlowDim + 8 * half, z);
         for (int l = kFlowLayers - 1; l >= 0; --l) {
             flow_mlp(l, z, a.theta + (size_t)l * kFLayer, pk + (size_t)l * kPLayer, S.h[wave], S.o[wave]);
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int c = 8 * half + j;
                 if (flow_in_a(l, c)) continue;
-                float p[kFlowBins];
-                flow_probs(S.o[wave] + n32 * (kFlowHalf * kFlowBins) + flow_pos(l, c) * kFlowBins, p);
-                const float v = z[j];
-                int b = 0;
-                float cb = 0.f, pb = p[0], cum = 0.f;
-#pragma unroll
-                for (int q = 0; q < kFlowBins; ++q) {
-                    if (cum <= v) {
-                        b = q;
-                        cb = cum;
-                        pb = p[q];
-                    }
-                    cum += p[q];
-                }
-                z[j] = fminf(fmaxf(((float)b + (v - cb) / pb) * (1.f / kFlowBins), 0.f), 1.f);
+                const float* ob = S.o[wave] + n32 * kFlowOut + flow_pos(l, c);
+                const float s = flow_scale(ob[0]);
+                z[j] = (z[j] - ob[kFlowHalf]) * expf(-s);
             }
             __syncthreads();
-            if (l > 0 && valid) {
-                float4* uo = reinterpret_cast<float4*>(a.U + ((size_t)(l - 1) * N + k) * kFlowDim + 8 * half);
-                uo[0] = make_float4(z[0], z[1], z[2], z[3]);
-                uo[1] = make_float4(z[4], z[5], z[6], z[7]);
-            }
+            if (l > 0 && valid) store8(a.U + ((size_t)(l - 1) * N + k) * kFlowDim + 8 * half, z);
+        }
+        // dL/du_0 = c u_0 (the term u_0^2 / 2 of log J_F)
+        if (valid) {
+            const float c = train_coef(a, k, true);
+            float g[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) g[j] = c * z[j];
+            store8(a.g_out + (size_t)k * kFlowDim + 8 * half, g);
         }
     }
 }
@@ -125,7 +141,7 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_inverse(FlowTrainArgs a)
 // backward pass of one coupling layer
 // ---------------------------------------------------------------------------
 struct __align__(16) FlowGradLds {
-    float o[kFlowWaves][32 * kFlowHalf * kFlowBins];    // logits, then dL/dlogits (FP32)
+    float o[kFlowWaves][32 * kFlowOut];                // conditioner outputs, then dL/d(a, t) (FP32)
     __bf16 h1[kFlowWaves][32 * kFlowHidden];
     __bf16 h2[kFlowWaves][32 * kFlowHidden];
     __bf16 da2[kFlowWaves][32 * kFlowHidden];
@@ -148,18 +164,15 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_grad(FlowTrainArgs a)
     const uint32_t N = a.n;
     const float* P = a.theta + (size_t)l * kFLayer;
     const bf16x8* pk = reinterpret_cast<const bf16x8*>(a.packed) + (size_t)l * kPLayer;
-    // the last layer reads w itself at the training samples, the others
-    // the compact inverse-pass outputs
-    const bool from_w = l == kFlowLayers - 1;
-    const float* uin = from_w ? a.w : a.U + (size_t)l * N * kFlowDim;
-    // c_k = |omega_k|^gamma / sum |omega|^gamma in double: tiny weights
-    // (an integrand that underflows almost everywhere) put 1/sum beyond FP32
-    const double ss = *a.sumsq;
-    const double inv_ss = ss > 0.0 && ss < INFINITY ? 1.0 / ss : 0.0;
+    // the layer's input in the inverse direction, u_{l+1}: z_4 itself for
+    // the last layer (at the training samples), else the inverse pass's
+    // compact output
+    const bool from_z = l == kFlowLayers - 1;
+    const float* uin = from_z ? a.zf : a.U + (size_t)l * N * kFlowDim;
     const uint32_t chunks = (N + 31u) / 32u;
     const uint32_t per_round = gridDim.x * kFlowWaves;
     const uint32_t rounds = (chunks + per_round - 1u) / per_round;
-    f32x16 acc3[2] = {}, acc2 = {}, acc1 = {};
+    f32x16 acc3 = {}, acc2 = {}, acc1 = {};
     float db3 = 0.f, db2[2] = {0.f, 0.f}, db1[2] = {0.f, 0.f};
     for (uint32_t rd = 0; rd < rounds; ++rd) {
         const uint32_t chunk = rd * per_round + blockIdx.x * kFlowWaves + wave;
@@ -167,79 +180,49 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_grad(FlowTrainArgs a)
         const uint32_t k = live ? min(chunk * 32u + (uint32_t)n32, N - 1u) : 0u;
         const bool valid = live && chunk * 32u + (uint32_t)n32 < N;
         float u[8], g[8];
-        {
-            const size_t row = from_w ? (size_t)a.off + (size_t)k * a.stride : (size_t)k;
-            const float4* ui = reinterpret_cast<const float4*>(uin + row * kFlowDim + 8 * half);
-            const float4 u0 = ui[0], u1 = ui[1];
-            u[0] = u0.x; u[1] = u0.y; u[2] = u0.z; u[3] = u0.w;
-            u[4] = u1.x; u[5] = u1.y; u[6] = u1.z; u[7] = u1.w;
-        }
-        if (a.g_in && valid) {
-            const float4* gi = reinterpret_cast<const float4*>(a.g_in + (size_t)k * kFlowDim + 8 * half);
-            const float4 g0 = gi[0], g1 = gi[1];
-            g[0] = g0.x; g[1] = g0.y; g[2] = g0.z; g[3] = g0.w;
-            g[4] = g1.x; g[5] = g1.y; g[6] = g1.z; g[7] = g1.w;
+        load8(uin + (from_z ? (size_t)a.off + (size_t)k * a.stride : (size_t)k) * kFlowDim + 8 * half, u);
+        if (valid) {
+            load8(a.g_in + (size_t)k * kFlowDim + 8 * half, g);
         } else {
 #pragma unroll
             for (int j = 0; j < 8; ++j) g[j] = 0.f;
         }
-        const float omk = valid ? fabsf(a.om[(size_t)a.off + (size_t)k * a.stride]) : 0.f;
-        const double omd = (double)omk;
-        const float coef = (float)((a.gamma == 2 ? omd * omd : omd) * inv_ss);
+        const float coef = train_coef(a, k, valid);
 
         // ---- recompute the conditioner of this layer -----------------------
         flow_mlp(l, u, P, pk, S.h1[wave], S.o[wave], S.h2[wave], S.x[wave]);
 
-        // ---- log-Jacobian and inverse transform: dL/dlogits ---------------
+        // ---- inverse transform and log-scale: dL/d(a, t) -------------------
+        // u_l,B = (u_{l+1},B - t) e^-s: dL/ds = c - g_B u_l,B (the log-scale
+        // is a term of log J_F), dL/dt = -g_B e^-s, dL/du_{l+1},B = g_B e^-s;
+        // s = S tanh(a/S), ds/da = 1 - (s/S)^2
         float gn[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int c = 8 * half + j;
             gn[j] = g[j];
             if (flow_in_a(l, c)) continue;
-            float* lg = S.o[wave] + n32 * (kFlowHalf * kFlowBins) + flow_pos(l, c) * kFlowBins;
-            float sm[kFlowBins], p[kFlowBins];
-            flow_softmax(lg, sm, p);
-            const float v = u[j];
-            int b = 0;
-            float cb = 0.f, pb = p[0], cum = 0.f;
-#pragma unroll
-            for (int q = 0; q < kFlowBins; ++q) {
-                if (cum <= v) {
-                    b = q;
-                    cb = cum;
-                    pb = p[q];
-                }
-                cum += p[q];
-            }
-            const float gz = g[j];
-            const float ipb = 1.f / pb;
-            const float below = -gz * ipb * (1.f / kFlowBins);
-            const float atb = -gz * (v - cb) * ipb * ipb * (1.f / kFlowBins) + coef * ipb;
-            float dp[kFlowBins], dot = 0.f;
-#pragma unroll
-            for (int q = 0; q < kFlowBins; ++q) {
-                dp[q] = (1.f - kFlowEps) * (q < b ? below : (q == b ? atb : 0.f));
-                dot = fmaf(sm[q], dp[q], dot);
-            }
-#pragma unroll
-            for (int q = 0; q < kFlowBins; ++q) lg[q] = sm[q] * (dp[q] - dot);
-            gn[j] = gz * ipb * (1.f / kFlowBins);
+            float* ob = S.o[wave] + n32 * kFlowOut + flow_pos(l, c);
+            const float s = flow_scale(ob[0]);
+            const float es = expf(-s);
+            const float ub = (u[j] - ob[kFlowHalf]) * es;
+            const float ds = valid ? coef - g[j] * ub : 0.f;
+            const float rs = s * (1.f / kFlowSMax);
+            ob[0] = ds * (1.f - rs * rs);
+            ob[kFlowHalf] = -g[j] * es;
+            gn[j] = g[j] * es;
         }
         __syncthreads();
 
         // ---- dH2 = dO W3; dA2 = dH2 (h2 > 0) -------------------------------
         {
             f32x16 t[2] = {};
-            const float* orow = S.o[wave] + n32 * (kFlowHalf * kFlowBins) + 8 * half;
+            const float* orow = S.o[wave] + n32 * kFlowOut + 8 * half;
+            bf16x8 av;
 #pragma unroll
-            for (int ks = 0; ks < 8; ++ks) {
-                bf16x8 av;
+            for (int j = 0; j < 8; ++j) av[j] = (__bf16)orow[j];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) av[j] = (__bf16)orow[ks * 16 + j];
-#pragma unroll
-                for (int nt = 0; nt < 2; ++nt) t[nt] = mfma(av, pk[kPR3 + (nt * 8 + ks) * 64 + lane], t[nt]);
-            }
+            for (int nt = 0; nt < 2; ++nt) t[nt] = mfma(av, pk[kPR3 + nt * 64 + lane], t[nt]);
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt) {
 #pragma unroll
@@ -286,34 +269,30 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_grad(FlowTrainArgs a)
         }
         __syncthreads();
 
-        // ---- dL/du_l: conditioning axes add the MLP's input gradient -------
+        // ---- dL/du_{l+1}: conditioning axes add the MLP's input gradient ----
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int c = 8 * half + j;
-            if (flow_in_a(l, c)) gn[j] = g[j] + 2.f * S.dx[wave][n32 * 32 + c];
+            if (flow_in_a(l, c)) gn[j] = g[j] + kFlowXScale * S.dx[wave][n32 * 32 + c];
         }
-        if (valid) {
-            float4* go = reinterpret_cast<float4*>(a.g_out + (size_t)k * kFlowDim + 8 * half);
-            go[0] = make_float4(gn[0], gn[1], gn[2], gn[3]);
-            go[1] = make_float4(gn[4], gn[5], gn[6], gn[7]);
-        }
+        if (valid) store8(a.g_out + (size_t)k * kFlowDim + 8 * half, gn);
 
         // ---- weight gradients over the workgroup's 128 samples ------------
-        // dW3[o][h] += sum_s dO[s][o] h2[s][h]: wave owns rows o in
-        // [32 wave, 32 wave + 32), both column tiles
+        // dW3[o][h] += sum_s dO[s][o] h2[s][h]: one 32-row tile (rows o < 16
+        // used), waves 0 and 1 take the two column tiles
+        if (wave < 2) {
 #pragma unroll 1
-        for (int ks = 0; ks < 8; ++ks) {
-            const int ws = ks >> 1;
-            const int s0 = (ks & 1) * 16 + 8 * half;
-            bf16x8 av, bv0, bv1;
+            for (int ks = 0; ks < 8; ++ks) {
+                const int ws = ks >> 1;
+                const int s0 = (ks & 1) * 16 + 8 * half;
+                bf16x8 av, bv;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                av[j] = (__bf16)S.o[ws][(s0 + j) * (kFlowHalf * kFlowBins) + wave * 32 + n32];
-                bv0[j] = S.h2[ws][(s0 + j) * kFlowHidden + n32];
-                bv1[j] = S.h2[ws][(s0 + j) * kFlowHidden + 32 + n32];
+                for (int j = 0; j < 8; ++j) {
+                    av[j] = n32 < kFlowOut ? (__bf16)S.o[ws][(s0 + j) * kFlowOut + n32] : (__bf16)0.f;
+                    bv[j] = S.h2[ws][(s0 + j) * kFlowHidden + wave * 32 + n32];
+                }
+                acc3 = mfma(av, bv, acc3);
             }
-            acc3[0] = mfma(av, bv0, acc3[0]);
-            acc3[1] = mfma(av, bv1, acc3[1]);
         }
         // dW2[n2][n1] += sum_s dA2[s][n2] h1[s][n1]: one tile per wave
         {
@@ -331,8 +310,9 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_grad(FlowTrainArgs a)
                 acc2 = mfma(av, bv, acc2);
             }
         }
-        // dW1[h][axis] += sum_s dA1[s][h] x[s][axis]: waves 0 and 1
-        if (wave < 2) {
+        // dW1[h][axis] += sum_s dA1[s][h] x[s][axis]: waves 2 and 3
+        if (wave >= 2) {
+            const int mt = wave - 2;
 #pragma unroll 1
             for (int ks = 0; ks < 8; ++ks) {
                 const int ws = ks >> 1;
@@ -340,39 +320,41 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_grad(FlowTrainArgs a)
                 bf16x8 av, bv;
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
-                    av[j] = S.da1[ws][(s0 + j) * kFlowHidden + wave * 32 + n32];
+                    av[j] = S.da1[ws][(s0 + j) * kFlowHidden + mt * 32 + n32];
                     bv[j] = n32 < kFlowDim ? S.x[ws][(s0 + j) * kFlowDim + n32] : (__bf16)0.f;
                 }
                 acc1 = mfma(av, bv, acc1);
             }
         }
         // db3: one output per thread, FP32
-        if (threadIdx.x < kFlowHalf * kFlowBins) {
+        if (threadIdx.x < kFlowOut) {
             for (int ws = 0; ws < kFlowWaves; ++ws)
-                for (int s = 0; s < 32; ++s) db3 += S.o[ws][s * (kFlowHalf * kFlowBins) + threadIdx.x];
+                for (int s = 0; s < 32; ++s) db3 += S.o[ws][s * kFlowOut + threadIdx.x];
         }
         __syncthreads();
     }
 
     // ---- this workgroup's gradient of layer l ------------------------------
     float* out = a.part + (size_t)blockIdx.x * kFLayer;
+    if (wave < 2) {
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-            out[kFW3 + (wave * 32 + mrow(lane, r)) * kFlowHidden + nt * 32 + n32] = acc3[nt][r];
+        for (int r = 0; r < 16; ++r) {
+            const int o = mrow(lane, r);
+            if (o < kFlowOut) out[kFW3 + o * kFlowHidden + wave * 32 + n32] = acc3[r];
+        }
+    }
     {
         const int mt = wave >> 1, nt = wave & 1;
 #pragma unroll
         for (int r = 0; r < 16; ++r)
             out[kFW2 + (mt * 32 + mrow(lane, r)) * kFlowHidden + nt * 32 + n32] = acc2[r];
     }
-    if (wave < 2 && n32 < kFlowDim && flow_in_a(l, n32)) {
+    if (wave >= 2 && n32 < kFlowDim && flow_in_a(l, n32)) {
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-            out[kFW1 + (wave * 32 + mrow(lane, r)) * kFlowHalf + flow_pos(l, n32)] = acc1[r];
+            out[kFW1 + ((wave - 2) * 32 + mrow(lane, r)) * kFlowHalf + flow_pos(l, n32)] = acc1[r];
     }
-    if (threadIdx.x < kFlowHalf * kFlowBins) out[kFB3 + threadIdx.x] = db3;
+    if (threadIdx.x < kFlowOut) out[kFB3 + threadIdx.x] = db3;
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
         db2[nt] += __shfl_xor(db2[nt], 32, 64);
@@ -442,12 +424,17 @@ hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, 
     hipLaunchKernelGGL(k_flow_sumsq, dim3(kSumBlocks), dim3(kSumThreads), 0, st, base.om, base.n, base.stride,
                        base.off, base.gamma, ss);
     hipLaunchKernelGGL(k_flow_sumsq_final, dim3(1), dim3(kSumThreads), 0, st, ss);
-    // the inverse pass holds 80 KB of LDS: two workgroups per CU
-    hipLaunchKernelGGL(k_flow_inverse, dim3(2 * n_wg), dim3(kFlowThreads), 0, st, base);
+    // the inverse pass writes u_1..u_3 and dL/du_0 (into G1); layer l reads
+    // dL/du_l and writes dL/du_{l+1}, alternating the two buffers
+    {
+        FlowTrainArgs a = base;
+        a.g_out = G1;
+        hipLaunchKernelGGL(k_flow_inverse, dim3(2 * n_wg), dim3(kFlowThreads), 0, st, a);
+    }
     for (int l = 0; l < kFlowLayers; ++l) {
         FlowTrainArgs a = base;
         a.layer = l;
-        a.g_in = l == 0 ? nullptr : ((l & 1) ? G0 : G1);
+        a.g_in = (l & 1) ? G0 : G1;
         a.g_out = (l & 1) ? G1 : G0;
         hipLaunchKernelGGL(k_flow_grad, dim3(n_wg), dim3(kFlowThreads), 0, st, a);
         hipLaunchKernelGGL(k_flow_reduce_seg, dim3((kFLayer + 255) / 256, kRedSegs), dim3(256), 0, st,

@@ -55,4 +55,17 @@ void combine(const std::vector<double>& I, const std::vector<double>& s2, double
 void ctx_set_stream(vegas_ctx* c, hipStream_t s);
 vegas_status ctx_fill_pass(vegas_ctx* c);
 
+// integrands compiled at run time (rtc.hip)
+int user_fn_dim(const vegas_user_fn* fn);
+int user_fn_precision(const vegas_user_fn* fn);
+
+}  // namespace vgh
+
+namespace vg {
+struct FillArgs;
+}
+
+namespace vgh {
+hipError_t launch_user_fill(const vegas_user_fn* fn, const vg::FillArgs& a, int n_wg, size_t lds, hipStream_t st);
+
 }  // namespace vgh

@@ -66,6 +66,7 @@ struct FillArgs {
     TileSide* side;             // [n_tiles]
     double* hist_H;             // LDS mode: [n_wg][D*N_g]; global mode: [D*N_g]
     uint32_t* hist_C;           // same layout
+    double* hist_Cw;            // warped fill (global mode): [D*N_g] FP64 sums of J_F
     unsigned long long* vmax;   // max v_h as FP64 bits (v >= 0)
     unsigned long long* nonfinite;
 };
@@ -131,6 +132,7 @@ struct MapArgs {
     double alpha;
     const double* hist_H;       // [n_slots][D*N_g]
     const uint32_t* hist_C;
+    const double* hist_Cw;      // non-null (one slot, parts 0): FP64 weights in place of hist_C
     double* grid64;             // [D][N_g+1] in/out
     float* grid32;              // [D][N_g+1] out (FP32 copy)
     double* Hsum;               // [D][N_g] reduced histogram (kept for inspection; may be null)

@@ -22,6 +22,7 @@ namespace vg {
 template <typename R, int FAM, int MAXD, bool EXACT = false>
 struct SamplePath {
     static constexpr bool kExact = EXACT;
+    static constexpr bool kWeightedHist = false;
     const SampleConst& sc;
     Fn<R, FAM> fn;
     PhiloxKeys keys;

@@ -339,6 +339,18 @@ __device__ __forceinline__ void map_update_axis(const MapArgs& a, int d, unsigne
         double H = 0.0;
         uint64_t C = 0;
         const int bi = d * ng + i;
+        if (a.hist_Cw) {
+            // an iteration through the learned warp: importance-weighted sums
+            const double Cw = a.hist_Cw[bi];
+            H = a.hist_H[bi];
+            if (a.Hsum) {
+                a.Hsum[bi] = H;
+                a.Csum[bi] = Cw;
+            }
+            A[i] = Cw > 0.0 ? H / Cw : 0.0;
+            any |= (H != 0.0);
+            continue;
+        }
         if (a.parts > 0) {
             for (int p = 0; p < a.parts; ++p) {
                 H += Hp[p * ng + i];

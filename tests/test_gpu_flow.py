@@ -24,12 +24,12 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def random_theta(seed, scale=0.3):
+def random_theta(seed, scale=0.3, bscale=0.3):
     rng = np.random.default_rng(seed)
     th = fl.init_params(16, seed)
     for L in fl.unpack(th, 16):
         L["W3"][...] = rng.normal(0, scale, L["W3"].shape)
-        L["b3"][...] = rng.normal(0, 0.3, L["b3"].shape)
+        L["b3"][...] = rng.normal(0, bscale, L["b3"].shape)
         L["b1"][...] = rng.normal(0, 0.1, L["b1"].shape)
     return th
 
@@ -58,8 +58,8 @@ def test_mfma_layout():
 
 def oracle_y(orc, w, nh, t, ks):
     """Stratified points of samples ks as the warp's sampling pass defines
-    them: y = (s 2^33 + 2r + 1) / (N_st 2^33) in FP64 (the numerator is exact),
-    rounded to FP32; s from the cube's digits, r the oracle's Philox word."""
+    them: y = (s 2^33 + 2r + 1) / (N_st 2^33) in FP64 (the numerator is
+    exact); s from the cube's digits, r the oracle's Philox word."""
     ns, nc, _ = orc.strata(w.n_eval, w.dim, w.n_min, w.n_strat)
     start = np.concatenate([[0], np.cumsum(nh.astype(np.int64))])
     ys = np.zeros((len(ks), w.dim))
@@ -69,8 +69,21 @@ def oracle_y(orc, w, nh, t, ks):
             s = h % ns
             h //= ns
             r = orc.word(w.seed, 0, t, int(k), d)
-            ys[i, d] = np.float32((s * 2.0 ** 33 + (2.0 * r + 1.0)) / (ns * 2.0 ** 33))
+            ys[i, d] = (s * 2.0 ** 33 + (2.0 * r + 1.0)) / (ns * 2.0 ** 33)
     return ys
+
+
+def roundtrip_bound(y):
+    """|Phi(Phi^-1(y)) - y| in FP32 for the warp's sampling pass: min(y,
+    1 - y) rounded to FP32 (2^-24 relative), erfcinv and erfc to a few ulps
+    each (8 allowed), each relative error of z = Phi^-1(y) moving the tail
+    probability m = min(y, 1 - y) by z^2 + 1 times itself at most (the
+    tail's log-derivative d ln m / d ln z is about z^2), and the rounding of
+    w itself (2^-25 absolute at most)."""
+    from scipy.special import ndtri
+    m = np.minimum(y, 1.0 - y)
+    z = ndtri(m)
+    return 16 * 2.0 ** -24 * (z * z + 1.0) * m + 2.0 ** -25
 
 
 def test_flow_sample_parity(orc):
@@ -100,7 +113,8 @@ def test_flow_sample_parity(orc):
 def test_library_init_is_identity(orc):
     """The library's own starting weights (no parameters passed): W1 and W2
     inside +-1/sqrt(fan_in) and spread over it, the last layer zero; the warp
-    is then the identity, w = y bit for bit and log J_F = 0."""
+    is then the identity: log J_F = 0 exactly, and w = Phi(Phi^-1(y)) in
+    FP32 equals y up to the roundings of the two FP32 functions."""
     w = corr16()
     say("[flow init]")
     v = make(w)
@@ -123,7 +137,9 @@ def test_library_init_is_identity(orc):
     W, LJ, _ = v.flow_samples()
     ks = np.random.default_rng(3).choice(w.n_eval, 400, replace=False)
     ys = oracle_y(orc, w, nh, 0, ks)
-    assert np.array_equal(W[ks].astype(np.float64), ys)
+    dw = np.abs(W[ks].astype(np.float64) - ys)
+    say(f"  |w - y| / roundtrip bound: max {np.max(dw / roundtrip_bound(ys)):.3f}")
+    assert np.all(dw <= roundtrip_bound(ys))
     assert np.all(LJ == 0.0)
     for x in (v, v2, v3):
         x.close()
@@ -131,11 +147,11 @@ def test_library_init_is_identity(orc):
 
 def test_identity_warp_equals_plain():
     """The identity warp against the plain iteration on the same samples.
-    The warped path carries y in FP32 (one rounding) and splits w N_g
-    exactly, so each sample's point differs from the plain path's by at most
-    half an FP32 ulp of y: per-sample weights agree within the bound that
-    moves ln f by (stated below) wherever the bins agree (bins may differ
-    only where y lies within an ulp of an interval end), and the iteration's
+    The warped path's w = Phi(Phi^-1(y)) differs from the plain path's
+    exact y by the FP32 round trip (roundtrip_bound), and it splits w N_g
+    exactly: per-sample weights agree within the bound that this moves ln f
+    by (stated below) wherever the bins agree (bins may differ only where y
+    lies within the round trip of an interval end), and the iteration's
     estimate and variance to 1e-5."""
     w = corr16()
     say("[flow identity]")
@@ -153,18 +169,23 @@ def test_identity_warp_equals_plain():
     say(f"  I rel {abs(Ia[0] - Ib[0]) / abs(Ia[0]):.2e}, s2 rel {abs(sa[0] - sb[0]) / sa[0]:.2e}")
     assert abs(Ia[0] - Ib[0]) <= 1e-5 * abs(Ia[0]), (Ia[0], Ib[0])
     assert abs(sa[0] - sb[0]) <= 1e-5 * sa[0], (sa[0], sb[0])
+    # the warped iteration's importance-weighted map histograms (weights
+    # 1/J_F = 1) refine the map as the plain iteration's counts do
+    ga, gb = a.get_map(), b.get_map()
+    say(f"  map max |diff| {np.max(np.abs(ga - gb)):.2e}")
+    assert np.max(np.abs(ga - gb)) < 1e-5
     W, LJ, OM = b.flow_samples()
     bins_w = np.minimum(np.floor(W.astype(np.float64) * w.n_g), w.n_g - 1).astype(np.int64)
     same = np.all(bins_w == pr["bins"].astype(np.int64), axis=1)
     wp = pr["jac"] * pr["f"]
     rel = np.abs(OM - wp) / np.maximum(np.abs(wp), 1e-300)
     say(f"  bins differ for {np.sum(~same)} of {w.n_eval} samples; weight rel diff max {rel[same].max():.2e}")
-    # Bound per sample.  (a) y carries one FP32 rounding (|dy| <= 2^-25) that
-    # the plain path's exact fixed-point offset does not: x_d moves by at
-    # most N_g dx_d 2^-25 (the uniform map of iteration 0 has N_g dx_d = 1);
-    # each path also rounds its offset and its point x_d < 1 (2^-25 each,
-    # the offset's scaled by dx_d < 1), so x_d differs by at most 4 2^-25 and
-    # ln f by 4 2^-25 sum_d |d ln f / dx_d| with d ln f / dx = -Sigma^-1 (x - mu).  (b) Each path rounds its own FP32
+    # Bound per sample.  (a) w differs from y by the round trip (|dw| <=
+    # roundtrip_bound(y)), which moves x_d by N_g dx_d |dw| (the uniform map
+    # of iteration 0 has N_g dx_d = 1 and x = y); each path also rounds its
+    # offset and its point x_d < 1 (2^-25 each, the offset's scaled by
+    # dx_d < 1), so x_d differs by at most roundtrip_bound + 3 2^-25 and ln f
+    # by that times |d ln f / dx_d|, d ln f / dx = -Sigma^-1 (x - mu).  (b) Each path rounds its own FP32
     # evaluation of the exponent e = c1 S + c2 vbar^2 + z (log2 units; S the
     # spread sum_d u_d^2 - (sum_d u_d)^2 / D of u_d = x_d - x_0, vbar the mean
     # offset): S to (D + 2) ulps of its two terms, c2 vbar^2 to 8 ulps,
@@ -173,7 +194,7 @@ def test_identity_warp_equals_plain():
     D = w.dim
     Sig = s_ * s_ * ((1 - rho) * np.eye(D) + rho * np.ones((D, D)))
     x = pr["x"]
-    dlnf = np.abs((x - mu) @ np.linalg.inv(Sig)).sum(axis=1)
+    dlnf = (np.abs((x - mu) @ np.linalg.inv(Sig)) * (roundtrip_bound(x) + 3 * 2.0 ** -25)).sum(axis=1)
     c1 = 0.5 / (s_ * s_ * (1 - rho)) / math.log(2)
     c2 = 0.5 * D / (s_ * s_ * (1 + (D - 1) * rho)) / math.log(2)
     u = x[:, 1:] - x[:, :1]
@@ -181,7 +202,7 @@ def test_identity_warp_equals_plain():
     vbar = (x[:, 0] - mu) + a1 / D
     e = c1 * (a2 - a1 * a1 / D) + c2 * vbar * vbar
     ulps = c1 * (D + 2) * (a2 + a1 * a1 / D) + 8 * c2 * vbar * vbar + 3 * np.abs(e) + 4
-    tol = 4 * 2.0 ** -25 * dlnf * 1.01 + 2 * 2.0 ** -24 * math.log(2) * ulps
+    tol = dlnf * 1.01 + 2 * 2.0 ** -24 * math.log(2) * ulps
     say(f"  worst weight rel diff / bound {np.max(rel[same] / tol[same]):.2f}")
     assert np.sum(~same) <= 1e-3 * w.n_eval
     assert np.all(rel[same] <= tol[same])
@@ -216,13 +237,16 @@ def test_flow_adam_against_oracle():
 
 
 def test_fixed_warp_unbiased():
-    """A fixed non-trivial warp, a product Gaussian in 16-d (closed form)."""
+    """A fixed non-trivial warp, a product Gaussian in 16-d (closed form).
+    The warp is mild (log-scales and shifts of a few hundredths): a strong
+    random warp makes the weights heavy-tailed, and then the iterations'
+    own variance estimates, which Eq. 8-9 weighs by, are not reliable."""
     s = 0.2
     w = vi.Workload("gauss16_flow", 16, vi.GAUSS_DIAG, vi.gauss_diag_params(vi.normal_peak(s, 16), s, [0.5]),
                     n_g=64, n_eval=400_000, n_iter=5, precision="f32")
     say("[flow unbiased]")
     v = make(w)
-    v.attach_flow(random_theta(5, scale=0.2).astype(np.float32))
+    v.attach_flow(random_theta(5, scale=0.02, bscale=0.05).astype(np.float32))
     v.enable_flow(True)
     v.adapt(4)
     v.integrate(w.n_iter)
@@ -243,11 +267,11 @@ def test_flow_grad_parity():
     v.attach_flow(th)
     v.enable_flow(True)
     v.adapt(1)
-    W, LJ, OM = v.flow_samples()
+    W, LJ, OM, Z = v.flow_samples(with_z=True)
     g_gpu = v.flow_grad().astype(np.float64)
     om = OM.astype(np.float64)
     coef = om * om / np.sum(om * om)
-    _, g_orc = fl.loss_grad(th.astype(np.float64), W.astype(np.float64), coef, emu=True)
+    _, g_orc = fl.loss_grad(th.astype(np.float64), Z.astype(np.float64), coef, emu=True)
     n = fl.n_params(16) // 4
     for l in range(4):
         a, b = g_gpu[l * n:(l + 1) * n], g_orc[l * n:(l + 1) * n]
