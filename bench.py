@@ -340,9 +340,16 @@ def warp_run(args, w, method: str, exact: float):
     """One method on the correlated Gaussian: create, the continuation
     warm-up, then iterations combined by Eq. 8-9 in chunks until the relative
     error estimate reaches the target or the caps.  The wall time counts from
-    create.  The warp is attached at create from the library's own starting
-    weights and trains through the warm-up with the guard judge; the cost
-    judge takes over for the combined iterations."""
+    create.
+
+    Plain VEGAS+: every warm-up iteration refines the map and the
+    allocation, as do the combined iterations (Alg. 1).
+    Warp: each warm-up step runs one plain iteration, which refines the map
+    while the step's width is at least map_hold x the target's, and then
+    cont_iters iterations through the warp, which train it (library starting
+    weights, KL loss) and reallocate with the map held.  Then the map stays
+    held; the warp keeps training, judged by cost against a plain control
+    every 16th iteration."""
     import numpy as np
     import torch
     import vegas_inputs as vi
@@ -351,31 +358,39 @@ def warp_run(args, w, method: str, exact: float):
     sharp = w.name == "corr_gauss_16d"
     warm = vi.continuation(w, args.cont_steps) if sharp else [w.params] * w.n_adapt
     per = args.cont_iters if sharp else 1
+    s_target = float(w.params[1])
     cap_it, cap_s = args.cap_iters, args.cap_seconds
+    n_warm = len(warm) * (per + 1)
     cfg = make_config(w.dim, w.n_g, w.n_eval, precision="f32",
-                      max_iter=len(warm) * per + cap_it + args.steps + args.chunk + 16)
+                      max_iter=n_warm + cap_it + args.steps + args.warmup + args.chunk + 16)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     v = Vegas(cfg, w.family, warm[0])
     if method == "warp":
-        v.attach_flow(None, lr=args.flow_lr, train=True, loss=args.flow_loss, judge="guard",
-                      steps_per_iter=args.flow_steps, control_period=16, train_stride=args.train_stride,
-                      init_seed=w.seed)
-        v.enable_flow(True)
+        v.attach_flow(None, lr=args.flow_lr, train=True, loss=args.flow_loss, judge=0,
+                      steps_per_iter=args.flow_steps, train_stride=args.train_stride, init_seed=w.seed)
     for p in warm:
         v.set_params(p)
-        v.adapt(per)
+        if method == "warp":
+            v.enable_flow(False)
+            v.set_adapt(float(p[1]) >= args.map_hold * s_target, True)
+            v.adapt(1)
+            v.set_adapt(False, True)
+            v.enable_flow(True)
+            v.adapt(per)
+        else:
+            v.adapt(per + 1)
     if method == "warp":
-        v.set_flow_config(lr=args.flow_lr, train=True, loss="variance", judge="cost",
-                          steps_per_iter=args.flow_steps, control_period=16, train_stride=args.train_stride)
-    n0 = len(warm) * per
+        v.set_flow_config(lr=args.flow_lr_final, train=True, loss=args.flow_loss, judge="cost",
+                          steps_per_iter=args.flow_steps_final, control_period=16, train_stride=args.train_stride)
+    n0 = len(v.get_iterations()[0])
     n = 0
     rel = math.inf
     r = None
     while n < cap_it and time.perf_counter() - t0 < cap_s:
         v.integrate(args.chunk)
         n += args.chunk
-        r = v.result()
+        r = v.result(allow_nonfinite=True)
         rel = math.sqrt(r.sigma2) / abs(r.integral) if r.integral != 0 else math.inf
         if rel <= target:
             break
@@ -390,7 +405,8 @@ def warp_run(args, w, method: str, exact: float):
            "integral": r.integral, "sigma": sig, "rel_err_estimate": rel,
            "true_rel_err": abs(r.integral - exact) / exact, "z": (r.integral - exact) / sig if sig > 0 else None,
            "resolved": bool(sig > 0 and abs(r.integral - exact) < 3.0 * sig),
-           "median_rel_var_per_eval": float(np.median(si[sel] / np.maximum(Ii[sel] ** 2, 1e-300) * w.n_eval))}
+           "median_rel_var_per_eval": float(np.median(si[sel] / np.maximum(Ii[sel] ** 2, 1e-300) * w.n_eval)),
+           "nonfinite_samples": int(r.n_nonfinite)}
     if method == "warp":
         on, kept, rej = v.flow_status()
         rec["judge"] = {"warp_on_at_end": on, "kept": kept, "rejected": rej,
@@ -412,8 +428,8 @@ def run_warp_compare(args, w):
     v, out["warp"] = warp_run(args, w, "warp", exact)
     # throughput of the warped iteration as the run left it: W more
     # iterations untimed, then K timed between events on the library's stream
-    v.set_flow_config(lr=args.flow_lr, train=True, loss="variance", judge="guard",
-                      steps_per_iter=args.flow_steps, control_period=16, train_stride=args.train_stride)
+    v.set_flow_config(lr=args.flow_lr_final, train=True, loss=args.flow_loss, judge="guard",
+                      steps_per_iter=args.flow_steps_final, control_period=16, train_stride=args.train_stride)
     v.integrate(args.warmup)
     torch.cuda.synchronize()
     v.set_timing(True)
@@ -452,10 +468,13 @@ def run_warp_compare(args, w):
                                f"4 coupling layers, 2x64 BF16 MLPs, 16 bins",
                    "n_eval": w.n_eval, "dim": w.dim, "n_intervals": w.n_g, "target_rel_err": args.target,
                    "caps": {"iterations": args.cap_iters, "seconds": args.cap_seconds},
-                   "warmup": f"continuation over {args.cont_steps} steps x {args.cont_iters} iterations",
+                   "warmup": f"continuation over {args.cont_steps} steps (plain: {args.cont_iters + 1} "
+                             f"iterations each; warp: 1 plain refining the map while the width is >= "
+                             f"{args.map_hold} x the target's, then {args.cont_iters} warped)",
                    "warp": {"lr": args.flow_lr, "adam_steps_per_iteration": args.flow_steps,
-                            "train_stride": args.train_stride,
-                            "warmup_loss": args.flow_loss, "control_period": 16},
+                            "lr_final": args.flow_lr_final, "adam_steps_per_iteration_final": args.flow_steps_final,
+                            "train_stride": args.train_stride, "loss": args.flow_loss, "control_period": 16,
+                            "map_hold": args.map_hold},
                    "parallelism": "single-gpu"},
         "time_to_target_s": {"warp": wp["wall_s"] if wp["reached"] else None,
                              "plain": pl["wall_s"] if pl["reached"] else None},
@@ -509,14 +528,18 @@ def main():
     ap.add_argument("--cap-iters", type=int, default=2000, help="warp comparison: iteration cap per method")
     ap.add_argument("--cap-seconds", type=float, default=600.0, help="warp comparison: time cap per method")
     ap.add_argument("--chunk", type=int, default=5, help="warp comparison: iterations between error checks")
-    ap.add_argument("--cont-steps", type=int, default=20, help="warp comparison: continuation steps")
+    ap.add_argument("--cont-steps", type=int, default=30, help="warp comparison: continuation steps")
     ap.add_argument("--cont-iters", type=int, default=2, help="warp comparison: iterations per step")
-    ap.add_argument("--flow-lr", type=float, default=1e-3, help="warp comparison: Adam step of the warp")
-    ap.add_argument("--flow-steps", type=int, default=1, help="warp comparison: Adam steps per iteration")
+    ap.add_argument("--flow-lr", type=float, default=2e-3, help="warp comparison: Adam step during the warm-up")
+    ap.add_argument("--flow-steps", type=int, default=16, help="warp comparison: Adam steps per warm-up iteration")
+    ap.add_argument("--flow-lr-final", type=float, default=1e-3, help="warp comparison: Adam step afterwards")
+    ap.add_argument("--flow-steps-final", type=int, default=8,
+                    help="warp comparison: Adam steps per combined iteration")
     ap.add_argument("--train-stride", type=int, default=1,
                     help="warp comparison: a training step uses every n-th sample of the iteration")
-    ap.add_argument("--flow-loss", default="variance", choices=["variance", "kl"],
-                    help="warp comparison: training loss during the warm-up")
+    ap.add_argument("--flow-loss", default="kl", choices=["variance", "kl"], help="warp comparison: training loss")
+    ap.add_argument("--map-hold", type=float, default=2.0,
+                    help="warp comparison: the map refines while the warm-up width is >= this x the target's")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the VEGAS+ path here "
