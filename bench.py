@@ -159,29 +159,48 @@ def cpu_baseline_batch(insts, budget_evals: int):
                       f"single-threaded FP64 C oracle, {dt:.1f} s)", **host_info()}
 
 
-def cpu_baseline_warp(w, n_samples: int):
-    """The oracle's plain iteration on a reduced budget of the same workload,
-    and its warp (FP64 numpy forward pass plus the loss gradient through the
-    inverse chain, with BF16 emulation) on n_samples points: evals/s of each,
-    and of a warped iteration (the two costs added per sample)."""
+def cpu_baseline_warp(w, train_stride: int, steps: int, target_s: float = 10.0):
+    """The oracle's plain iteration on the same workload (sized to about
+    target_s seconds), and its warp on a sample sized the same way: the FP64
+    numpy forward pass with BF16 emulation for every sample, plus the loss
+    gradient through the inverse chain for the training share of a warped
+    iteration (steps / train_stride of the samples).  Evals/s of the plain
+    iteration, and of a warped one (the costs per sample added)."""
     import numpy as np
-    import oracle
     from oracle import flow as fl
-    base = cpu_baseline(w, 100_000, 2)
+    base = cpu_baseline(w, w.n_eval, 2, target_s=target_s)
     rng = np.random.default_rng(0)
     th = fl.init_params(w.dim, 0)
-    y = rng.random((n_samples, w.dim))
+    probe = 2000
     t0 = time.perf_counter()
-    wv, lj, zf = fl.forward(th, y, emu=True, return_z=True)
-    coef = np.full(n_samples, 1.0 / n_samples)
-    fl.loss_grad(th, zf, coef, emu=True)
-    dt = time.perf_counter() - t0
-    per_flow = dt / n_samples
+    _, _, zf = fl.forward(th, rng.random((probe, w.dim)), emu=True, return_z=True)
+    fl.loss_grad(th, zf, np.full(probe, 1.0 / probe), emu=True)
+    n = int(max(probe, min(200_000, target_s / ((time.perf_counter() - t0) / probe))))
+    y = rng.random((n, w.dim))
+    t0 = time.perf_counter()
+    _, _, zf = fl.forward(th, y, emu=True, return_z=True)
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    fl.loss_grad(th, zf, np.full(n, 1.0 / n), emu=True)
+    t_grad = time.perf_counter() - t0
+    share = steps / max(train_stride, 1)
+    per_flow = (t_fwd + share * t_grad) / n
     per_plain = 1.0 / base["value"]
     base["warp_value"] = 1.0 / (per_flow + per_plain)
-    base["sample"] += (f"; warp: forward + loss gradient of {n_samples} samples ({dt:.1f} s, FP64 numpy with "
-                       f"BF16 emulation), warped evals/s = 1/(plain + warp seconds per sample)")
+    base["sample"] += (f"; warp: forward of {n:,} samples ({t_fwd:.1f} s) and the loss gradient on them "
+                       f"({t_grad:.1f} s), FP64 numpy with BF16 emulation; a warped iteration trains "
+                       f"{steps} steps on 1/{train_stride} of its samples, so warped evals/s = 1/(plain + "
+                       f"forward + {share:g} x gradient seconds per sample)")
     return base
+
+
+# algorithmic multiply-add flops of the warp, per sample (2 per multiply-add;
+# the conditioner MLP is 8 -> 64 -> 64 -> 16)
+FLOW_MLP_FLOPS = 2 * (8 * 64 + 64 * 64 + 64 * 16)            # one layer's forward
+FLOW_SAMPLE_FLOPS = 4 * FLOW_MLP_FLOPS                       # the sampling pass
+# one training step: the inverse pass (4 forwards) and, per layer, the forward
+# again plus dO W3, dA2 W2, dA1 W1 and the three weight gradients
+FLOW_TRAIN_FLOPS = 4 * FLOW_MLP_FLOPS + 4 * (FLOW_MLP_FLOPS + 2 * 2 * (16 * 64 + 64 * 64 + 64 * 8))
 
 
 def run_batch(args, insts=None):
@@ -258,6 +277,18 @@ def run_batch(args, insts=None):
     return out
 
 
+def copy_calibration() -> int:
+    """A plain 256 MiB device copy, three times: its FETCH_SIZE / WRITE_SIZE
+    counters give the scale factors of the HBM counters."""
+    import torch
+    src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return src.numel() * 4
+
+
 def run_single(args, w):
     """One workload: W untimed iterations, then K timed ones."""
     import torch
@@ -321,12 +352,7 @@ def run_single(args, w):
         # chip issues at half the FP32 rate
         out["roofline"]["note"] = "FP64 sample path; the issue count is the FP32 path's"
     if args.copy_calibration:
-        src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")   # 256 MiB
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = src.numel() * 4
+        out["copy_calibration_bytes"] = copy_calibration()
     if not args.no_cpu_baseline:
         if w.name == "gauss_prod_4d":
             out["cpu_baseline"] = cpu_baseline(w, w.n_eval, w.n_iter)     # the whole run
@@ -445,11 +471,19 @@ def run_warp_compare(args, w):
     kinds = v.flow_kinds()[-args.steps:]
     ft = v.flow_timing()
     v.close()
-    # the warp's dominant kernel, the sampling pass on BF16 MFMA: 2 x (8x64 +
-    # 64x64 + 64x128) multiply-adds per layer and sample
-    flops = 2 * 4 * (8 * 64 + 64 * 64 + 64 * 128) * w.n_eval
-    samp_ms = ft["sample_ms"]
-    ach = flops / (samp_ms / 1e3) if samp_ms else None
+    # the warp's two MFMA phases per warped iteration: the sampling pass over
+    # every sample, and the training steps over 1/stride of them each; the
+    # roofline line names the longer one
+    samp_ms, train_ms = ft["sample_ms"], ft["train_ms"]
+    n_train = (w.n_eval + args.train_stride - 1) // args.train_stride
+    phases = {
+        "k_flow_sample": (FLOW_SAMPLE_FLOPS * w.n_eval, samp_ms),
+        "training (k_flow_inverse, 4 x k_flow_grad, reductions, Adam)":
+            (FLOW_TRAIN_FLOPS * n_train * args.flow_steps_final, train_ms),
+    }
+    dom = max(phases, key=lambda k: phases[k][1] or 0.0)
+    flops, dom_ms = phases[dom]
+    ach = flops / (dom_ms / 1e3) if dom_ms else None
     pl, wp = out["plain"], out["warp"]
     line = {
         "metric": "integrand evals/sec and wall time to 1e-4 rel. error; learned warp vs plain VEGAS+",
@@ -483,11 +517,16 @@ def run_warp_compare(args, w):
         "timed_iterations": {"warped": int((kinds == 1).sum()), "control": int((kinds == 2).sum()),
                              "plain": int((kinds == 0).sum())},
         "roofline": {"bound": "mfma", "achieved": ach / 1e12 if ach else None, "peak": 2500.0, "unit": "TFLOP/s",
-                     "frac": ach / 2.5e15 if ach else None, "traffic": None, "kernel": "k_flow_sample",
-                     "kernel_ms": samp_ms, "train_ms": ft["train_ms"]},
+                     "frac": ach / 2.5e15 if ach else None, "traffic": None, "kernel": dom,
+                     "kernel_ms": dom_ms, "flops_per_launch": flops,
+                     "phases": {k: {"ms": m, "tflops": (f / (m / 1e3) / 1e12) if m else None,
+                                    "frac": (f / (m / 1e3) / 2.5e15) if m else None}
+                                for k, (f, m) in phases.items()}},
     }
+    if args.copy_calibration:
+        line["copy_calibration_bytes"] = copy_calibration()
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline_warp(w, 4000)
+        line["cpu_baseline"] = cpu_baseline_warp(w, args.train_stride, args.flow_steps_final)
     return line
 
 
@@ -535,7 +574,7 @@ def main():
     ap.add_argument("--flow-lr-final", type=float, default=1e-3, help="warp comparison: Adam step afterwards")
     ap.add_argument("--flow-steps-final", type=int, default=8,
                     help="warp comparison: Adam steps per combined iteration")
-    ap.add_argument("--train-stride", type=int, default=1,
+    ap.add_argument("--train-stride", type=int, default=8,
                     help="warp comparison: a training step uses every n-th sample of the iteration")
     ap.add_argument("--flow-loss", default="kl", choices=["variance", "kl"], help="warp comparison: training loss")
     ap.add_argument("--map-hold", type=float, default=2.0,

@@ -505,15 +505,17 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
     // the warped fill's histograms are importance-weighted FP64 sums in
     // global memory (one slot)
     const int lds_hist = warp_now ? 0 : (c->g.lds_hist_ok ? 1 : 0);
-    if (!lds_hist) {
+    // while the map is held a warped fill writes no histograms
+    const bool warp_hist = warp_now && c->cfg.adapt_map;
+    if (!lds_hist && (!warp_now || warp_hist)) {
         HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histH), nb, c->stream));
         if (warp_now) HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histCw), nb, c->stream));
         else HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histC), (nb + 1) / 2, c->stream));
     }
     FillArgs a = fill_args(c, t, c->nonfinite());
     a.lds_hist = lds_hist;
-    if (warp_now) a.hist_Cw = c->at<double>(c->p.histCw);
-    c->hist_weighted = warp_now;
+    if (warp_hist) a.hist_Cw = c->at<double>(c->p.histCw);
+    c->hist_weighted = warp_hist;
     if (c->flow_on) HIPCHK(judge_mark(c, t, 0));
     // the warped fill keeps the map in LDS; k_fill reads it through the cache
     const size_t lds = fill_lds_bytes(c->g.D, c->g.ng, fp64, lds_hist, c->g.tile, c->g.n_aux, warp_now ? 1 : 0);

@@ -395,9 +395,10 @@ __device__ __forceinline__ void fill_tile(int tile, const TileIO& io, const Fill
                 if constexpr (Path::kWeightedHist) {
                     // the warped path's samples have density q = 1/J_F in w:
                     // the map's bin averages of w^2 over uniform points are
-                    // sum (w^2 / J_F) / sum J_F (global memory)
+                    // sum (w^2 / J_F) / sum J_F (global memory); none while
+                    // the map is held (null hist_Cw)
                     const double jf = sp.last_jf();
-                    if (jf > 0.0 && __builtin_isfinite(jf)) {
+                    if (io.hist_Cw && jf > 0.0 && __builtin_isfinite(jf)) {
                         const double h = w2 / jf;
 #pragma unroll
                         for (int d = 0; d < MAXD; ++d) {
