@@ -102,7 +102,7 @@ def profiled_traffic(workload: str):
     if not m:
         return None
     rec = json.loads(m.group(1))
-    return rec["traffic_bytes"] if rec.get("source_hash") == fill_source_hash() else None
+    return rec.get("traffic_bytes") if rec.get("source_hash") == fill_source_hash() else None
 
 
 def host_info():
@@ -168,14 +168,14 @@ def cpu_baseline_warp(w, train_stride: int, steps: int, target_s: float = 10.0):
     iteration, and of a warped one (the costs per sample added)."""
     import numpy as np
     from oracle import flow as fl
-    base = cpu_baseline(w, w.n_eval, 2, target_s=target_s)
+    base = cpu_baseline(w, w.n_eval, 16, target_s=target_s)
     rng = np.random.default_rng(0)
     th = fl.init_params(w.dim, 0)
-    probe = 2000
+    probe = 20_000
     t0 = time.perf_counter()
     _, _, zf = fl.forward(th, rng.random((probe, w.dim)), emu=True, return_z=True)
     fl.loss_grad(th, zf, np.full(probe, 1.0 / probe), emu=True)
-    n = int(max(probe, min(200_000, target_s / ((time.perf_counter() - t0) / probe))))
+    n = int(max(probe, min(1_000_000, target_s / ((time.perf_counter() - t0) / probe))))
     y = rng.random((n, w.dim))
     t0 = time.perf_counter()
     _, _, zf = fl.forward(th, y, emu=True, return_z=True)
@@ -387,7 +387,7 @@ def warp_run(args, w, method: str, exact: float):
     s_target = float(w.params[1])
     cap_it, cap_s = args.cap_iters, args.cap_seconds
     n_warm = len(warm) * (per + 1)
-    cfg = make_config(w.dim, w.n_g, w.n_eval, precision="f32",
+    cfg = make_config(w.dim, w.n_g, w.n_eval, precision="f32", seed=w.seed,
                       max_iter=n_warm + cap_it + args.steps + args.warmup + args.chunk + 16)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -499,7 +499,7 @@ def run_warp_compare(args, w):
         "dtype": "f32+bf16",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {WORKLOADS[w.name]}, {w.n_eval:.0e} evals/iteration; learned warp "
-                               f"4 coupling layers, 2x64 BF16 MLPs, 16 bins",
+                               f"4 affine coupling layers in Gaussian coordinates, 2x64 BF16 MLPs",
                    "n_eval": w.n_eval, "dim": w.dim, "n_intervals": w.n_g, "target_rel_err": args.target,
                    "caps": {"iterations": args.cap_iters, "seconds": args.cap_seconds},
                    "warmup": f"continuation over {args.cont_steps} steps (plain: {args.cont_iters + 1} "
@@ -545,6 +545,225 @@ def subrecords(args):
     return subs
 
 
+# --------------------------------------------------------------------------
+# the paper's own measurements (--study NAME): one JSON line per point
+# --------------------------------------------------------------------------
+STUDY_ITERS = 20          # max_it of the paper's configurations (Tab. 2)
+
+
+def _emit(rec):
+    print(json.dumps(rec), flush=True)
+
+
+def _config_of(w, n_g=None, alpha=None, beta=None, precision=None, max_iter=0):
+    from paper_2408_09229_amd import make_config
+    return make_config(w.dim, n_g or w.n_g, w.n_eval, alpha=w.alpha if alpha is None else alpha,
+                       beta=w.beta if beta is None else beta, seed=w.seed,
+                       precision=precision or w.precision, max_iter=max_iter)
+
+
+def study_phases(args):
+    """Tab. 1: where a whole run's time goes, for Roos & Arnold (10-d) and the
+    ridge of Tab. 3 (4-d), at 1e7 .. 1e10 integrand evaluations in all, with
+    the "def" parameters (1024 intervals, alpha 0.5, beta 0.75, 20
+    iterations, none skipped).  Phases: init (create: workspace, uniform map
+    and allocation, first offsets), fill, results (tile fix-up and the
+    iteration's estimate), allocation (new n_h and the sample offsets, the
+    paper's update of evals per cube and its mapping of evaluations to
+    cubes), map (rebinning), host (launch gaps and the combination), clear
+    (destroy).  GPU phases come from HIP events around each kernel group;
+    host phases from the host clock around the calls.  A first untimed run
+    of each shape loads the kernels, as the paper leaves out the context
+    start-up."""
+    import torch
+    import vegas_inputs as vi
+    from paper_2408_09229_amd import Vegas
+    from tests import closed_forms as cf
+    torch.cuda.set_device(0)
+    totals = [float(x) for x in args.study_totals.split(",")]
+    for w0 in (vi.roos_10d(), vi.ridge_tab3()):
+        for prec in args.study_precisions.split(","):
+            for total in totals:
+                w = w0.with_(n_eval=int(total / STUDY_ITERS), precision=prec)
+                cfg = _config_of(w)
+                for rep in range(2):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    v = Vegas(cfg, w.family, w.params, w.lo, w.hi)
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    v.set_timing(True)
+                    v.integrate(STUDY_ITERS)
+                    r = v.result()
+                    torch.cuda.synchronize()
+                    t2 = time.perf_counter()
+                    ph, n = v.get_timing()
+                    v.close()
+                    torch.cuda.synchronize()
+                    t3 = time.perf_counter()
+                if n != STUDY_ITERS:
+                    raise RuntimeError(f"timed {n} iterations, expected {STUDY_ITERS}")
+                ms = {"init": (t1 - t0) * 1e3, "fill": ph[0], "results": ph[1], "allocation": ph[2], "map": ph[3]}
+                ms["host"] = max((t2 - t1) * 1e3 - float(ph.sum()), 0.0)
+                ms["clear"] = (t3 - t2) * 1e3
+                tot = sum(ms.values())
+                exact = cf.exact(w)
+                _emit({"study": "phases", "integrand": w0.name, "precision": prec, "evals_total": total,
+                       "n_eval": w.n_eval, "iterations": STUDY_ITERS, "total_ms": tot,
+                       "percent": {k: 100.0 * x / tot for k, x in ms.items()}, "ms": ms,
+                       "integral": r.integral, "sigma": math.sqrt(r.sigma2), "exact": exact})
+
+
+def study_scaling(args):
+    """Tab. 6 / the fill-scaling figure: the fill kernel's time per iteration
+    (mean, standard error, min, max over the iterations of a run) while one
+    parameter moves and the others stay at 8 dimensions, 1024 intervals and
+    2e10 evaluations in all (1e9 per iteration over 20 iterations).  The
+    integrand is Roos & Arnold (the paper does not name the one it used).
+    The paper's fourth axis, its thread count, has no counterpart: the fill
+    here runs one persistent workgroup per CU over sample tiles whose size
+    follows from the budget."""
+    import numpy as np
+    import torch
+    import vegas_inputs as vi
+    from paper_2408_09229_amd import Vegas
+    torch.cuda.set_device(0)
+    base = {"evals_total": 2e10, "dim": 8, "n_g": 1024}
+    axes = {"evals_total": [2e6, 2e7, 2e8, 2e9, 2e10], "dim": [2, 4, 8, 16, 32],
+            "n_g": [16, 64, 256, 1024, 4096]}
+    iters = args.study_iters
+    for axis, values in axes.items():
+        for val in values:
+            p = dict(base, **{axis: val})
+            w = vi.roos_10d().with_(dim=int(p["dim"]), n_g=int(p["n_g"]), n_eval=int(p["evals_total"] / STUDY_ITERS),
+                                    precision=args.study_precisions.split(",")[0])
+            w = w.with_(lo=np.zeros(w.dim), hi=np.ones(w.dim))
+            v = Vegas(_config_of(w), w.family, w.params, w.lo, w.hi)
+            v.set_timing(True)
+            v.adapt(1)
+            per = []
+            prev = v.get_timing()[0][0]
+            for _ in range(iters):
+                v.adapt(1)
+                cur = v.get_timing()[0][0]
+                per.append(cur - prev)
+                prev = cur
+            v.close()
+            a = np.array(per)
+            _emit({"study": "scaling", "axis": axis, "value": val, "dim": w.dim, "n_g": w.n_g, "n_eval": w.n_eval,
+                   "precision": w.precision, "fill_ms_mean": float(a.mean()),
+                   "fill_ms_stderr": float(a.std(ddof=1) / math.sqrt(len(a))) if len(a) > 1 else 0.0,
+                   "fill_ms_min": float(a.min()), "fill_ms_max": float(a.max()), "iterations": len(a),
+                   "evals_per_s": w.n_eval / (a.mean() * 1e-3)})
+
+
+PARAM_SETS = {"def": {"n_g": 1024, "alpha": 0.5}, "vf": {"n_g": 50, "alpha": 1.5}, "tq": {"n_g": None, "alpha": 0.5}}
+
+
+def tq_intervals(n_eval: int) -> int:
+    """The "tq" set's interval count "computed on n_eval" (Tab. 2), which the
+    paper does not spell out: read here as one interval per 1000 evaluations,
+    kept within 2 .. 1024."""
+    return max(2, min(1024, n_eval // 1000))
+
+
+def study_accuracy(args):
+    """The test-integrand comparison: wall time against relative standard
+    error for Tab. 3's integrands #1-7 at their dimensions, under the def,
+    vf and tq parameter sets (Tab. 2: 20 iterations, none skipped, beta
+    0.75), at several budgets.  Each point is the mean over five runs after
+    an untimed one; the summary line per set and budget is the geometric
+    mean over the seven integrands, as the paper plots it."""
+    import numpy as np
+    import torch
+    import vegas_inputs as vi
+    from paper_2408_09229_amd import Vegas
+    from tests import closed_forms as cf
+    torch.cuda.set_device(0)
+    budgets = [float(x) for x in args.study_budgets.split(",")]
+    for set_name in args.study_sets.split(","):
+        ps = PARAM_SETS[set_name]
+        for total in budgets:
+            n_eval = int(total / STUDY_ITERS)
+            n_g = ps["n_g"] or tq_intervals(n_eval)
+            per = []
+            for w0 in vi.tab3_suite():
+                w = w0.with_(n_eval=n_eval, n_g=n_g, alpha=ps["alpha"], beta=0.75,
+                             precision=args.study_precisions.split(",")[0])
+                exact = cf.exact(w)
+                walls, rels, zs = [], [], []
+                for rep in range(6):
+                    w_rep = w.with_(seed=rep)
+                    cfg = _config_of(w_rep)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    v = Vegas(cfg, w.family, w.params, w.lo, w.hi)
+                    v.integrate(STUDY_ITERS)
+                    r = v.result()
+                    v.close()
+                    torch.cuda.synchronize()
+                    if rep == 0:
+                        continue
+                    walls.append(time.perf_counter() - t0)
+                    sig = math.sqrt(r.sigma2)
+                    rels.append(sig / abs(r.integral))
+                    zs.append((r.integral - exact) / sig if sig > 0 else 0.0)
+                rec = {"study": "accuracy", "set": set_name, "integrand": w0.name, "dim": w.dim, "n_g": n_g,
+                       "alpha": ps["alpha"], "evals_total": total, "wall_s": float(np.mean(walls)),
+                       "rel_std_err": float(np.mean(rels)), "max_abs_z": float(np.max(np.abs(zs)))}
+                _emit(rec)
+                per.append(rec)
+            _emit({"study": "accuracy_geomean", "set": set_name, "evals_total": total, "n_g": n_g,
+                   "wall_s": float(np.exp(np.mean(np.log([p["wall_s"] for p in per])))),
+                   "rel_std_err": float(np.exp(np.mean(np.log([p["rel_std_err"] for p in per])))),
+                   "max_abs_z": float(max(p["max_abs_z"] for p in per))})
+
+
+def study_beta(args):
+    """Adaptive stratification on and off: beta 0.25 against beta 0 with
+    alpha 1.5 and 500 intervals, 20 iterations of which the first 5 are not
+    combined, wall time against relative standard error at several budgets;
+    mean over five runs after an untimed one.  Integrands: the Tab. 3 ridge
+    and Gaussian (peaked), Roos & Arnold and the cosine (smooth)."""
+    import numpy as np
+    import torch
+    import vegas_inputs as vi
+    from paper_2408_09229_amd import Vegas
+    from tests import closed_forms as cf
+    torch.cuda.set_device(0)
+    budgets = [float(x) for x in args.study_budgets.split(",")]
+    suite = {w.name: w for w in vi.tab3_suite()}
+    for w0 in (vi.ridge_tab3(), suite["gauss4"], suite["roos10"], suite["cosine10"]):
+        for beta in (0.25, 0.0):
+            for total in budgets:
+                n_eval = int(total / STUDY_ITERS)
+                w = w0.with_(n_eval=n_eval, n_g=500, alpha=1.5, beta=beta,
+                             precision=args.study_precisions.split(",")[0])
+                exact = cf.exact(w)
+                walls, rels, errs = [], [], []
+                for rep in range(6):
+                    cfg = _config_of(w.with_(seed=rep))
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    v = Vegas(cfg, w.family, w.params, w.lo, w.hi)
+                    v.adapt(5)
+                    v.integrate(STUDY_ITERS - 5)
+                    r = v.result()
+                    v.close()
+                    torch.cuda.synchronize()
+                    if rep == 0:
+                        continue
+                    walls.append(time.perf_counter() - t0)
+                    rels.append(math.sqrt(r.sigma2) / abs(r.integral))
+                    errs.append(abs(r.integral - exact) / abs(exact))
+                _emit({"study": "beta", "integrand": w0.name, "beta": beta, "evals_total": total,
+                       "wall_s": float(np.mean(walls)), "rel_std_err": float(np.mean(rels)),
+                       "true_rel_err": float(np.mean(errs))})
+
+
+STUDIES = {"phases": study_phases, "scaling": study_scaling, "accuracy": study_accuracy, "beta": study_beta}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -574,9 +793,19 @@ def main():
     ap.add_argument("--flow-lr-final", type=float, default=1e-3, help="warp comparison: Adam step afterwards")
     ap.add_argument("--flow-steps-final", type=int, default=8,
                     help="warp comparison: Adam steps per combined iteration")
-    ap.add_argument("--train-stride", type=int, default=8,
+    ap.add_argument("--train-stride", type=int, default=32,
                     help="warp comparison: a training step uses every n-th sample of the iteration")
     ap.add_argument("--flow-loss", default="kl", choices=["variance", "kl"], help="warp comparison: training loss")
+    ap.add_argument("--study", default="", choices=[""] + sorted(STUDIES),
+                    help="one of the paper's measurements instead of the benchmark (JSON lines)")
+    ap.add_argument("--study-totals", default="1e7,1e8,1e9,1e10", help="phases: evaluations in all (20 iterations)")
+    ap.add_argument("--study-budgets", default="1e6,1e7,1e8,1e9",
+                    help="accuracy / beta: evaluations in all (20 iterations)")
+    ap.add_argument("--study-sets", default="def,vf,tq", help="accuracy: parameter sets")
+    ap.add_argument("--study-precisions", default="f32,f64", help="sample-path precisions (scaling, accuracy and "
+                    "beta take the first)")
+    ap.add_argument("--study-iters", type=int, default=10, help="scaling: timed iterations per point")
+    ap.add_argument("--seed", type=int, default=-1, help="warp comparison: sampling and warp seed (-1: the workload's)")
     ap.add_argument("--map-hold", type=float, default=2.0,
                     help="warp comparison: the map refines while the warm-up width is >= this x the target's")
     args = ap.parse_args()
@@ -605,9 +834,16 @@ def main():
         print(json.dumps(rates))
         return
 
+    if args.study:
+        STUDIES[args.study](args)
+        return
+
     import vegas_inputs as vi
     if args.workload == "headline":
-        line = run_warp_compare(args, vi.corr_gauss_16d())
+        w = vi.corr_gauss_16d()
+        if args.seed >= 0:
+            w = w.with_(seed=args.seed)
+        line = run_warp_compare(args, w)
         if not args.no_sub:
             line["sub_records"] = subrecords(args)
         print(json.dumps(line), flush=True)
@@ -617,6 +853,8 @@ def main():
         return
     w = getattr(vi, args.workload)()
     if args.workload in ("corr_gauss_16d", "corr_gauss_16d_mild"):
+        if args.seed >= 0:
+            w = w.with_(seed=args.seed)
         print(json.dumps(run_warp_compare(args, w)), flush=True)
         return
     if args.n_eval:

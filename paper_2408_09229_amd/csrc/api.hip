@@ -1250,7 +1250,7 @@ FlowPlan flow_plan(uint32_t n_eval, int n_wg)
     return p;
 }
 
-// one training workgroup per CU (150 KB of LDS each)
+// one training workgroup per CU (the backward kernel takes 94 KB of LDS)
 int flow_train_wg(const vegas_ctx* c)
 {
     const int chunks = (int)((c->g.n_eval + 127) / 128);
