@@ -3,11 +3,12 @@
 // layers -> w = Phi(z_4), log J_F), and the fill of an iteration through the
 // warp (weight f(map(w)) J_map(w) J_F(y)).
 //
-// One wavefront evaluates the flow for 32 samples at a time.  Its matrix
-// products are v_mfma_f32_32x32x16_bf16 with the samples as rows; a layer's
-// hidden activations go through LDS to change from the product's output
-// layout to the next product's input layout, and the conditioner outputs go
-// through LDS to the lanes that move each sample's axes.
+// One wavefront evaluates the flow for 32 samples at a time, each lane
+// holding 8 axes of one sample.  Its matrix products are
+// v_mfma_f32_32x32x16_bf16 with the samples as columns (W . act^T), so that
+// each product's output registers feed the next product directly and the
+// last one's land in the lanes that move each axis; the weights are read
+// from LDS, staged once per workgroup.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -64,12 +65,22 @@ __global__ void k_flow_pack(const float* __restrict__ theta, bf16x8* __restrict_
         const int nt = r >> 8, ks = (r >> 6) & 3;
         const int n = nt * 32 + n32;
         for (int j = 0; j < 8; ++j) v[j] = W2[(ks * 16 + kb + j) * kFlowHidden + n];
-    } else {                              // R1[ks]: B[k = h][n = axis] = W1[h][pos(axis)] for axes in A
+    } else if (r < kPT2) {                // R1[ks]: B[k = h][n = axis] = W1[h][pos(axis)] for axes in A
         r -= kPR1;
         const int ks = r >> 6;
         const int c = n32;
         for (int j = 0; j < 8; ++j)
             v[j] = (c < kFlowDim && flow_in_a(l, c)) ? W1[(ks * 16 + kb + j) * kFlowHalf + flow_pos(l, c)] : 0.f;
+    } else if (r < kPT3) {                // T2[mt][ks]: A[m][k] = W2[m][unit(ks, k)]
+        r -= kPT2;
+        const int mt = r >> 8, ks = (r >> 6) & 3;
+        const int m = mt * 32 + n32;
+        for (int j = 0; j < 8; ++j) v[j] = W2[m * kFlowHidden + flow_t_unit(ks, lane >> 5, j)];
+    } else {                              // T3[ks]: A[m][k] = W3[row(m)][unit(ks, k)], zero rows padded
+        r -= kPT3;
+        const int ks = r >> 6;
+        const int o = flow_t3_row(l, n32);
+        for (int j = 0; j < 8; ++j) v[j] = o >= 0 ? W3[o * kFlowHidden + flow_t_unit(ks, lane >> 5, j)] : 0.f;
     }
     bf16x8 o;
     for (int j = 0; j < 8; ++j) o[j] = (__bf16)v[j];
@@ -120,33 +131,56 @@ __global__ void k_mfma_probe(const float* A, const float* B, float* D)
 // ---------------------------------------------------------------------------
 // sampling pass: y of every sample of iteration t, pushed through F
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kFlowThreads) void k_flow_sample(FlowSampleArgs a)
+// Cube of sample k for the wave's 32 consecutive samples k0 .. k0 + 31
+// (k0 <= k < N).  A 64-way search over the start offsets finds k0's cube c0
+// (one gather and a ballot per step, the same for the whole wave); then each
+// lane searches the 64 starts from c0, held one per lane, by shuffles.
+// Every cube holds at least n_min >= 2 samples, so the wave's samples lie in
+// cubes c0 .. c0 + 16.
+__device__ __forceinline__ uint32_t flow_cube(const uint32_t* __restrict__ start, uint32_t n_cubes, uint32_t k0,
+                                              uint32_t k, int lane)
 {
-    __shared__ FlowLds S;
+    uint32_t lo = 0, span = n_cubes;          // start[lo] <= k0 < start[lo + span]
+    while (span > 1) {
+        const uint32_t step = (span + 63u) >> 6;
+        const uint32_t off = (uint32_t)lane * step;
+        const bool ok = off < span && start[lo + off] <= k0;
+        const unsigned long long m = __ballot(ok);
+        const uint32_t last = 63u - (uint32_t)__clzll(m);   // lane 0 always holds
+        lo += last * step;
+        span = min(step, span - last * step);
+    }
+    const uint32_t idx = lo + (uint32_t)lane;
+    const uint32_t sw = idx < n_cubes ? start[idx] : 0xFFFFFFFFu;
+    int a = 0, b = 64;
+#pragma unroll
+    for (int it = 0; it < 6; ++it) {
+        const int mid = (a + b) >> 1;
+        const uint32_t v = __shfl(sw, mid, 64);
+        if (v <= k) a = mid; else b = mid;
+    }
+    return lo + (uint32_t)a;
+}
+
+__global__ __launch_bounds__(kFlowSampleThreads, 4) void k_flow_sample(FlowSampleArgs a)
+{
+    __shared__ FlowFwdLds S;
+    flow_stage_fwd(S, reinterpret_cast<const bf16x8*>(a.packed), a.theta);
+    __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
     const int half = lane >> 5;
     const int n32 = lane & 31;
     const SampleConst& sc = a.sc;
     const PhiloxKeys keys = philox_keys<false>(sc.key0, sc.key1);
     const uint32_t N = sc.n_eval;
     const uint32_t chunks = (N + 31u) / 32u;
-    const uint32_t per_round = gridDim.x * kFlowWaves;
-    const uint32_t rounds = (chunks + per_round - 1u) / per_round;
-    const bf16x8* pk = reinterpret_cast<const bf16x8*>(a.packed);
+    const uint32_t n_waves = gridDim.x * kFlowSampleWaves;
     const double den = (double)sc.nst * 0x1p33;
-    for (uint32_t rd = 0; rd < rounds; ++rd) {
-        // every wave runs every round (the layers synchronise the workgroup)
-        const uint32_t chunk = rd * per_round + blockIdx.x * kFlowWaves + wave;
-        const bool live = chunk < chunks;
-        const uint32_t k = live ? min(chunk * 32u + (uint32_t)n32, N - 1u) : 0u;
-        // cube of k and its stratum digits
-        uint32_t lo = 0, hi = sc.n_cubes;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (a.start[mid] <= k) lo = mid; else hi = mid;
-        }
-        uint32_t hc = lo, dig[kFlowDim];
+    // waves run independently: no barrier inside the loop
+    for (uint32_t chunk = blockIdx.x * kFlowSampleWaves + (threadIdx.x >> 6); chunk < chunks; chunk += n_waves) {
+        const uint32_t k0 = chunk * 32u;
+        const uint32_t k = min(k0 + (uint32_t)n32, N - 1u);
+        uint32_t hc = flow_cube(a.start, sc.n_cubes, k0, k, lane), dig[kFlowDim];
 #pragma unroll
         for (int d = 0; d < kFlowDim; ++d) {
             const uint32_t q = div_magic(hc, sc.nst_magic, sc.nst_shift);
@@ -171,20 +205,10 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_sample(FlowSampleArgs a)
             }
         }
         float lj = 0.f;
-        for (int l = 0; l < kFlowLayers; ++l) {
-            const float* P = a.theta + (size_t)l * kFLayer;
-            flow_mlp(l, z, P, pk + (size_t)l * kPLayer, S.h[wave], S.o[wave]);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int c = 8 * half + j;
-                if (flow_in_a(l, c)) continue;
-                const float* ob = S.o[wave] + n32 * kFlowOut + flow_pos(l, c);
-                const float s = flow_scale(ob[0]);
-                z[j] = fmaf(z[j], expf(s), ob[kFlowHalf]);
-                lj += s;
-            }
-            __syncthreads();
-        }
+        flow_layer_fwd<0>(z, lj, S);
+        flow_layer_fwd<1>(z, lj, S);
+        flow_layer_fwd<2>(z, lj, S);
+        flow_layer_fwd<3>(z, lj, S);
         float wv[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -192,7 +216,7 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_sample(FlowSampleArgs a)
             wv[j] = flow_phi(z[j]);
         }
         lj += __shfl_xor(lj, 32, 64);
-        if (live && chunk * 32u + (uint32_t)n32 < N) {
+        if (k0 + (uint32_t)n32 < N) {
             float4* wo = reinterpret_cast<float4*>(a.w + (size_t)k * kFlowDim + 8 * half);
             wo[0] = make_float4(wv[0], wv[1], wv[2], wv[3]);
             wo[1] = make_float4(wv[4], wv[5], wv[6], wv[7]);
@@ -361,7 +385,7 @@ hipError_t launch_mfma_probe(const float* A, const float* B, float* D, hipStream
 
 hipError_t launch_flow_sample(const FlowSampleArgs& a, int n_wg, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_flow_sample, dim3(n_wg), dim3(kFlowThreads), 0, st, a);
+    hipLaunchKernelGGL(k_flow_sample, dim3(n_wg), dim3(kFlowSampleThreads), 0, st, a);
     return hipGetLastError();
 }
 

@@ -44,13 +44,32 @@ constexpr int kFParams = kFlowLayers * kFLayer;
 //   R3: dO . W3     (backward; k = output)                 [2 n-tiles][1 k]
 //   R2: dA2 . W2                                           [2 n-tiles][4 k]
 //   R1: dA1 . W1 (n = axis, 16 of 32 used)                 [1 n-tile][4 k]
+// and as A operands of the transposed forward products W . act^T (samples
+// as columns; lane l holds A[l % 32][8 (l/32) + j]), where one product's
+// output registers are the next product's B operand as they stand:
+//   F1 (the same entries): W1 . x^T                          [2 m-tiles]
+//   T2: W2 . h1^T, k in the hidden units' register order     [2 m-tiles][4 k]
+//   T3: W3 . h2^T, output rows placed where the lanes that
+//       move each axis hold them (flow_t3_row)               [4 k]
 constexpr int kPF1 = 0;
 constexpr int kPF2 = kPF1 + 2 * 64;
 constexpr int kPF3 = kPF2 + 2 * 4 * 64;
 constexpr int kPR3 = kPF3 + 4 * 64;
 constexpr int kPR2 = kPR3 + 2 * 64;
 constexpr int kPR1 = kPR2 + 2 * 4 * 64;
-constexpr int kPLayer = kPR1 + 4 * 64;           // 1792 entries of 16 bytes
+constexpr int kPT2 = kPR1 + 4 * 64;
+constexpr int kPT3 = kPT2 + 2 * 4 * 64;
+constexpr int kPLayer = kPT3 + 4 * 64;           // 2560 entries of 16 bytes
+constexpr int kPFwdT = 2 * 64 + 2 * 4 * 64 + 4 * 64;   // F1, T2, T3: 896 entries per layer
+
+// Register order of a product's 32x32 output (register r of lane l holds
+// row 8 (r/4) + 4 (l/32) + r % 4): fed to the next product as its B operand,
+// k-step ks takes registers 8 (ks % 2) .. + 7 of tile ks / 2, so k index
+// 8 h + i of k-step ks is hidden unit flow_t_unit(ks, h, i).
+__host__ __device__ inline int flow_t_unit(int ks, int h, int i)
+{
+    return 32 * (ks >> 1) + 16 * (ks & 1) + 8 * (i >> 2) + 4 * h + (i & 3);
+}
 
 // axis c is conditioning (in A) in layer l
 __host__ __device__ inline bool flow_in_a(int l, int c)
@@ -59,6 +78,20 @@ __host__ __device__ inline bool flow_in_a(int l, int c)
 }
 // position of axis c inside its set (A or B) of layer l
 __host__ __device__ inline int flow_pos(int l, int c) { return l < 2 ? (c & 7) : (c >> 1); }
+
+// Conditioner output carried by row m of the transposed last product of
+// layer l, or -1 for a zero row.  Row m lands in register r = 4 (m/8) + m % 4
+// of the lanes of half (m/4) % 2, which hold axes 8 half + j of their sample:
+// register j < 8 gets the raw log-scale of axis 8 half + j, register 8 + j
+// its shift, where that axis moves in layer l.
+__host__ __device__ inline int flow_t3_row(int l, int m)
+{
+    const int half = (m >> 2) & 1;
+    const int r = 4 * (m >> 3) + (m & 3);
+    const int c = 8 * half + (r & 7);
+    if (flow_in_a(l, c)) return -1;
+    return (r < 8 ? 0 : kFlowHalf) + flow_pos(l, c);
+}
 
 struct FlowSampleArgs {
     SampleConst sc;

@@ -44,6 +44,8 @@ __device__ __forceinline__ float flow_phi_inv(float m, bool upper)
 // ---------------------------------------------------------------------------
 constexpr int kFlowWaves = 4;
 constexpr int kFlowThreads = 64 * kFlowWaves;
+constexpr int kFlowSampleWaves = 8;                    // the sampling pass: independent waves
+constexpr int kFlowSampleThreads = 64 * kFlowSampleWaves;
 struct __align__(16) FlowLds {
     __bf16 h[kFlowWaves][32 * kFlowHidden];            // hidden activations [sample][unit]
     float o[kFlowWaves][32 * kFlowOut];                // conditioner outputs [sample][a(8), t(8)]
@@ -117,6 +119,138 @@ __device__ __forceinline__ void flow_mlp(int l, const float (&z)[8], const float
         }
     }
     __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// the conditioner MLP with the samples as columns
+// ---------------------------------------------------------------------------
+// The products run as W . act^T, so each one's output registers (register r
+// of lane l: unit 8 (r/4) + 4 (l/32) + r % 4 of its tile, sample l % 32) are
+// the next one's B operand as they stand, with the weights' k order packed
+// to match (T2, T3).  Nothing passes through LDS between the products and
+// no barrier is needed; the forward weights of all layers are staged in LDS
+// once per workgroup.
+struct __align__(16) FlowFwdLds {
+    bf16x8 w[kFlowLayers][kPFwdT];                         // F1, T2, T3
+    float b[kFlowLayers][2 * kFlowHidden + kFlowOut];      // b1, b2, b3
+};
+
+// Copies the forward operands and biases into LDS (every thread of the
+// workgroup takes part; the caller synchronises afterwards).
+__device__ __forceinline__ void flow_stage_fwd(FlowFwdLds& S, const bf16x8* __restrict__ pk,
+                                               const float* __restrict__ theta)
+{
+    for (int e = threadIdx.x; e < kFlowLayers * kPFwdT; e += blockDim.x) {
+        const int l = e / kPFwdT;
+        const int r = e - l * kPFwdT;
+        // F1 first, then T2 and T3, which are adjacent in the packed layer
+        S.w[l][r] = pk[(size_t)l * kPLayer + (r < 2 * 64 ? kPF1 + r : kPT2 + (r - 2 * 64))];
+    }
+    constexpr int nb = 2 * kFlowHidden + kFlowOut;
+    for (int e = threadIdx.x; e < kFlowLayers * nb; e += blockDim.x) {
+        const int l = e / nb;
+        const int r = e - l * nb;
+        const int src = r < kFlowHidden ? kFB1 + r : r < 2 * kFlowHidden ? kFB2 + (r - kFlowHidden)
+                                                                         : kFB3 + (r - 2 * kFlowHidden);
+        S.b[l][r] = theta[(size_t)l * kFLayer + src];
+    }
+}
+
+// Conditioner of layer L for the wave's 32 samples; lane l holds axes
+// 8 (l/32) + j of sample l % 32 in z.  Returns the last product's
+// registers: j < 8 the raw log-scale of the lane's axis j, 8 + j its shift
+// (meaningful where that axis moves in layer L).  Biases start the
+// accumulators.
+template <int L>
+__device__ __forceinline__ f32x16 flow_mlp_t(const float (&z)[8], const FlowFwdLds& S)
+{
+    // the weights in LDS do not change inside the callers' loops: this
+    // compiler-only fence keeps their loads here instead of hoisted (and
+    // held in registers) across all layers and iterations
+    __asm__ volatile("" ::: "memory");
+    const int lane = threadIdx.x & 63;
+    const int half = lane >> 5;
+    const bf16x8* W = S.w[L];
+    const float* B = S.b[L];
+    bf16x8 x;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = flow_in_a(L, 8 * half + j) ? (__bf16)(kFlowXScale * z[j]) : (__bf16)0.f;
+    // h1 = relu(W1 x + b1): the rows of register group q are units
+    // 32 mt + 8 q + 4 half + 0..3, contiguous in the bias
+    bf16x8 h1[4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        f32x16 acc;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 b = *reinterpret_cast<const float4*>(B + 32 * mt + 8 * q + 4 * half);
+            acc[4 * q] = b.x;
+            acc[4 * q + 1] = b.y;
+            acc[4 * q + 2] = b.z;
+            acc[4 * q + 3] = b.w;
+        }
+        acc = mfma(W[mt * 64 + lane], x, acc);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) h1[2 * mt + (r >> 3)][r & 7] = (__bf16)fmaxf(acc[r], 0.f);
+    }
+    // h2 = relu(W2 h1 + b2)
+    bf16x8 h2[4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        f32x16 acc;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 b = *reinterpret_cast<const float4*>(B + kFlowHidden + 32 * mt + 8 * q + 4 * half);
+            acc[4 * q] = b.x;
+            acc[4 * q + 1] = b.y;
+            acc[4 * q + 2] = b.z;
+            acc[4 * q + 3] = b.w;
+        }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) acc = mfma(W[2 * 64 + (mt * 4 + ks) * 64 + lane], h1[ks], acc);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) h2[2 * mt + (r >> 3)][r & 7] = (__bf16)fmaxf(acc[r], 0.f);
+    }
+    // outputs = W3 h2 + b3, rows placed by flow_t3_row
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int o = flow_t3_row(L, mrow(lane, r));
+        acc[r] = o >= 0 ? B[2 * kFlowHidden + o] : 0.f;
+    }
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) acc = mfma(W[10 * 64 + ks * 64 + lane], h2[ks], acc);
+    return acc;
+}
+
+// Forward coupling layer L on the lane's axes: z_B -> z_B e^s + t; adds the
+// log-scales to lj.
+template <int L>
+__device__ __forceinline__ void flow_layer_fwd(float (&z)[8], float& lj, const FlowFwdLds& S)
+{
+    const f32x16 o = flow_mlp_t<L>(z, S);
+    const int half = (threadIdx.x >> 5) & 1;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if (flow_in_a(L, 8 * half + j)) continue;
+        const float s = flow_scale(o[j]);
+        z[j] = fmaf(z[j], expf(s), o[8 + j]);
+        lj += s;
+    }
+}
+
+// Inverse coupling layer L: u_B -> (u_B - t) e^-s.
+template <int L>
+__device__ __forceinline__ void flow_layer_inv(float (&z)[8], const FlowFwdLds& S)
+{
+    const f32x16 o = flow_mlp_t<L>(z, S);
+    const int half = (threadIdx.x >> 5) & 1;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if (flow_in_a(L, 8 * half + j)) continue;
+        const float s = flow_scale(o[j]);
+        z[j] = (z[j] - o[8 + j]) * expf(-s);
+    }
 }
 
 }  // namespace vg

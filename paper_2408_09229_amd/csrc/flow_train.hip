@@ -94,38 +94,32 @@ __device__ __forceinline__ float train_coef(const FlowTrainArgs& a, uint32_t k, 
     return (float)((a.gamma == 2 ? om * om : om) * inv_ss);
 }
 
-__global__ __launch_bounds__(kFlowThreads) void k_flow_inverse(FlowTrainArgs a)
+__global__ __launch_bounds__(kFlowSampleThreads) void k_flow_inverse(FlowTrainArgs a)
 {
-    __shared__ FlowLds S;
+    __shared__ FlowFwdLds S;
+    flow_stage_fwd(S, reinterpret_cast<const bf16x8*>(a.packed), a.theta);
+    __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
     const int half = lane >> 5;
     const int n32 = lane & 31;
     const uint32_t N = a.n;
     const uint32_t chunks = (N + 31u) / 32u;
-    const uint32_t per_round = gridDim.x * kFlowWaves;
-    const uint32_t rounds = (chunks + per_round - 1u) / per_round;
-    const bf16x8* pk = reinterpret_cast<const bf16x8*>(a.packed);
-    for (uint32_t rd = 0; rd < rounds; ++rd) {
-        const uint32_t chunk = rd * per_round + blockIdx.x * kFlowWaves + wave;
-        const bool live = chunk < chunks;
-        const uint32_t k = live ? min(chunk * 32u + (uint32_t)n32, N - 1u) : 0u;
-        const bool valid = live && chunk * 32u + (uint32_t)n32 < N;
+    const uint32_t n_waves = gridDim.x * kFlowSampleWaves;
+    // waves run independently: no barrier inside the loop
+    for (uint32_t chunk = blockIdx.x * kFlowSampleWaves + (threadIdx.x >> 6); chunk < chunks; chunk += n_waves) {
+        const uint32_t k = min(chunk * 32u + (uint32_t)n32, N - 1u);
+        const bool valid = chunk * 32u + (uint32_t)n32 < N;
         float z[8];
         load8(a.zf + ((size_t)a.off + (size_t)k * a.stride) * kFlowDim + 8 * half, z);
-        for (int l = kFlowLayers - 1; l >= 0; --l) {
-            flow_mlp(l, z, a.theta + (size_t)l * kFLayer, pk + (size_t)l * kPLayer, S.h[wave], S.o[wave]);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int c = 8 * half + j;
-                if (flow_in_a(l, c)) continue;
-                const float* ob = S.o[wave] + n32 * kFlowOut + flow_pos(l, c);
-                const float s = flow_scale(ob[0]);
-                z[j] = (z[j] - ob[kFlowHalf]) * expf(-s);
-            }
-            __syncthreads();
-            if (l > 0 && valid) store8(a.U + ((size_t)(l - 1) * N + k) * kFlowDim + 8 * half, z);
-        }
+        float* U = a.U + (size_t)k * kFlowDim + 8 * half;
+        const size_t lay = (size_t)N * kFlowDim;
+        flow_layer_inv<3>(z, S);
+        if (valid) store8(U + 2 * lay, z);
+        flow_layer_inv<2>(z, S);
+        if (valid) store8(U + lay, z);
+        flow_layer_inv<1>(z, S);
+        if (valid) store8(U, z);
+        flow_layer_inv<0>(z, S);
         // dL/du_0 = c u_0 (the term u_0^2 / 2 of log J_F)
         if (valid) {
             const float c = train_coef(a, k, true);
@@ -429,7 +423,7 @@ hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, 
     {
         FlowTrainArgs a = base;
         a.g_out = G1;
-        hipLaunchKernelGGL(k_flow_inverse, dim3(2 * n_wg), dim3(kFlowThreads), 0, st, a);
+        hipLaunchKernelGGL(k_flow_inverse, dim3(2 * n_wg), dim3(kFlowSampleThreads), 0, st, a);
     }
     for (int l = 0; l < kFlowLayers; ++l) {
         FlowTrainArgs a = base;
