@@ -1239,8 +1239,8 @@ FlowPlan flow_plan(uint32_t n_eval, int n_wg)
     p.U = take(sizeof(float) * 3 * kFlowDim * (size_t)n_eval);
     p.G0 = take(sizeof(float) * kFlowDim * (size_t)n_eval);
     p.G1 = take(sizeof(float) * kFlowDim * (size_t)n_eval);
-    p.part = take(sizeof(float) * kFLayer * (size_t)n_wg);
-    p.seg = take(sizeof(float) * kFLayer * 16);
+    p.part = take(sizeof(float) * kFParams * (size_t)n_wg);
+    p.seg = take(sizeof(float) * kFParams * 16);
     p.grad = take(sizeof(float) * kFParams);
     p.m = take(sizeof(float) * kFParams);
     p.v = take(sizeof(float) * kFParams);
@@ -1279,12 +1279,12 @@ FlowTrainArgs flow_train_args(vegas_ctx* c, uint32_t stride, uint32_t off)
 }
 
 // gradient of the warp's loss on the last warped iteration's samples
-// off, off + stride, ...
-vegas_status flow_gradient(vegas_ctx* c, uint32_t stride, uint32_t off)
+// off, off + stride, ...; with adam set, the Adam step on it too
+vegas_status flow_gradient(vegas_ctx* c, uint32_t stride, uint32_t off, const FlowAdamArgs* adam)
 {
     HIPCHK(launch_flow_gradient(flow_train_args(c, stride, off), c->f_nwg, reinterpret_cast<float*>(c->fws + c->f_G0),
                                 reinterpret_cast<float*>(c->fws + c->f_G1), reinterpret_cast<float*>(c->fws + c->f_grad),
-                                reinterpret_cast<float*>(c->fws + c->f_seg), c->stream));
+                                reinterpret_cast<float*>(c->fws + c->f_seg), adam, c->stream));
     return VEGAS_OK;
 }
 
@@ -1424,12 +1424,16 @@ vegas_status flow_train_step(vegas_ctx* c)
 {
     // a strided subset of the samples, its offset turning with the steps
     const uint32_t stride = (uint32_t)std::min<int64_t>(c->fcfg.train_stride, c->g.n_eval);
-    vegas_status s = flow_gradient(c, stride, (uint32_t)(c->f_step % stride));
+    float* th = reinterpret_cast<float*>(c->fws + c->f_theta);
+    FlowAdamArgs adam;
+    adam.theta = th;
+    adam.m = reinterpret_cast<float*>(c->fws + c->f_m);
+    adam.v = reinterpret_cast<float*>(c->fws + c->f_v);
+    adam.lr = c->fcfg.lr;
+    adam.step = (int)(c->f_step + 1);
+    vegas_status s = flow_gradient(c, stride, (uint32_t)(c->f_step % stride), &adam);
     if (s != VEGAS_OK) return s;
     c->f_step += 1;
-    float* th = reinterpret_cast<float*>(c->fws + c->f_theta);
-    HIPCHK(launch_flow_adam(th, reinterpret_cast<const float*>(c->fws + c->f_grad), reinterpret_cast<float*>(c->fws + c->f_m),
-                            reinterpret_cast<float*>(c->fws + c->f_v), c->fcfg.lr, c->f_step, c->stream));
     HIPCHK(launch_flow_pack(th, c->fws + c->f_packed, c->stream));
     return VEGAS_OK;
 }
@@ -1642,7 +1646,7 @@ vegas_status vegas_flow_grad(vegas_ctx* c, float* grad)
 {
     if (!c || !grad) return fail(VEGAS_EINVAL, "bad arguments");
     if (!c->flow_attached) return fail(VEGAS_ESTATE, "no flow attached");
-    const vegas_status s = flow_gradient(c, 1, 0);
+    const vegas_status s = flow_gradient(c, 1, 0, nullptr);
     if (s != VEGAS_OK) return s;
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipMemcpy(grad, c->fws + c->f_grad, sizeof(float) * kFParams, hipMemcpyDeviceToHost));

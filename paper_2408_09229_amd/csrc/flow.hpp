@@ -124,7 +124,17 @@ struct FlowTrainArgs {
     float* U;                     // [3][n][16]: u_1, u_2, u_3 of the training samples
     const float* g_in;            // [n][16] upstream gradient dL/du_layer
     float* g_out;                 // [n][16] dL/du_{layer+1}
-    float* part;                  // [n_wg][kFLayer] per-workgroup gradient
+    float* part;                  // [n_wg][kFParams] per-workgroup gradient
+};
+
+// Adam step fused into the gradient's last reduction (training), or none
+// (the gradient alone)
+struct FlowAdamArgs {
+    float* theta;
+    float* m;
+    float* v;
+    float lr;
+    int step;                     // counts from 1
 };
 
 }  // namespace vg

@@ -87,7 +87,7 @@ hipError_t launch_flow_sample(const FlowSampleArgs& a, int n_wg, hipStream_t st)
 hipError_t launch_fill_flow(const FillArgs& a, const float* w, const float* lj, float* om, int n_wg, size_t lds,
                             hipStream_t st);
 hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, float* G1, float* grad,
-                                float* seg, hipStream_t st);
+                                float* seg, const FlowAdamArgs* adam, hipStream_t st);
 hipError_t launch_flow_adam(float* theta, const float* grad, float* m, float* v, float lr, int step, hipStream_t st);
 
 constexpr int kAllocThreads = 1024;
