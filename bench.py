@@ -763,7 +763,55 @@ def study_beta(args):
                        "true_rel_err": float(np.mean(errs))})
 
 
-STUDIES = {"phases": study_phases, "scaling": study_scaling, "accuracy": study_accuracy, "beta": study_beta}
+def study_applications(args):
+    """The application integrands (Sec. 4.5-4.6) compiled at run time: the
+    Asian call (8 normal variates) and the harmonic-oscillator path integral
+    (N = 8 lattice spacings, T = 4, ends at 0; 7 interior points on
+    [-5, 5]^7), in FP64 with the "def" parameters (1024 intervals, alpha 0.5,
+    beta 0.75, 20 iterations, none skipped); wall time (create to result)
+    against relative standard error at several budgets, the mean over five
+    runs after an untimed one, and the hipRTC compile time of each source."""
+    import numpy as np
+    import torch
+    from paper_2408_09229_amd import UserIntegrand, Vegas, make_config
+    from paper_2408_09229_amd import integrands as itg
+    from tests import closed_forms as cf
+    torch.cuda.set_device(0)
+    budgets = [float(x) for x in args.study_budgets.split(",")]
+    lo_f, hi_f = itg.feynman_box(8)
+    cases = [("asian_call8", itg.ASIAN_CALL, 8, itg.asian_params(), np.zeros(8), np.ones(8),
+              cf.asian_call(itg.asian_params(), 8)),
+             ("feynman_ho7", itg.FEYNMAN_HO, 7, itg.feynman_params(0.0, 4.0, 8), lo_f, hi_f,
+              cf.feynman_ho(itg.feynman_params(0.0, 4.0, 8), 7))]
+    for name, src, dim, params, lo, hi, exact in cases:
+        t0 = time.perf_counter()
+        fn = UserIntegrand(src, dim, "f64")
+        compile_ms = (time.perf_counter() - t0) * 1e3
+        for total in budgets:
+            n_eval = int(total / STUDY_ITERS)
+            walls, rels, errs = [], [], []
+            for rep in range(6):
+                cfg = make_config(dim, 1024, n_eval, alpha=0.5, beta=0.75, seed=rep, precision="f64")
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                v = Vegas(cfg, 0, params, lo, hi, user=fn)
+                v.integrate(STUDY_ITERS)
+                r = v.result()
+                v.close()
+                torch.cuda.synchronize()
+                if rep == 0:
+                    continue
+                walls.append(time.perf_counter() - t0)
+                rels.append(math.sqrt(r.sigma2) / abs(r.integral))
+                errs.append(abs(r.integral - exact) / abs(exact))
+            _emit({"study": "applications", "integrand": name, "dim": dim, "evals_total": total,
+                   "compile_ms": compile_ms, "wall_s": float(np.mean(walls)), "rel_std_err": float(np.mean(rels)),
+                   "true_rel_err": float(np.mean(errs)), "exact": exact})
+        fn.close()
+
+
+STUDIES = {"phases": study_phases, "scaling": study_scaling, "accuracy": study_accuracy, "beta": study_beta,
+           "applications": study_applications}
 
 
 def main():

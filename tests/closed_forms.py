@@ -127,3 +127,41 @@ def exact(w: vi.Workload) -> float:
     if f == vi.GAUSS_CORR:
         return 1.0   # normalised density; mass outside [0,1]^16 is below 1e-60
     raise ValueError(f)
+
+
+def asian_call(params, n: int) -> float:
+    """The Asian call of Eq. 10-11 as printed: the exponent holds
+    sigma sqrt(T) times a sum of n standard normal variates, a normal of
+    variance n sigma^2 T, so the price is Black-Scholes' with that variance:
+    e^{-rT} [S_0 e^{mu + v/2} Phi(d_1) - K Phi(d_2)], mu = (r - sigma^2/2) T,
+    v = n sigma^2 T, d_2 = (ln(S_0/K) + mu) / sqrt(v), d_1 = d_2 + sqrt(v)."""
+    s0, k, r, sig, t = (mp.mpf(v) for v in params[:5])
+    mu = (r - sig * sig / 2) * t
+    sd = sig * mp.sqrt(t * n)
+    d2 = (mp.log(s0 / k) + mu) / sd
+    d1 = d2 + sd
+    return float(mp.exp(-r * t) * (s0 * mp.exp(mu + sd * sd / 2) * mp.ncdf(d1) - k * mp.ncdf(d2)))
+
+
+def feynman_ho(params, n_interior: int) -> float:
+    """The lattice path integral of Eq. 12-13 for V = x^2/2 over all of
+    R^{N-1} (N = n_interior + 1 spacings): a Gaussian integral,
+    A (2 pi)^{(N-1)/2} det(M)^{-1/2} exp(b^T M^{-1} b / 2 - c), with
+    S_lat = y^T M y / 2 - b^T y + c over the interior points y:
+    M = tridiag(-m/a, 2m/a + a, -m/a), b_1 = b_{N-1} += m x / a, and
+    c = m x^2 / a + a x^2 / 2 (both end links and V at the first end)."""
+    xe, a, m = (mp.mpf(v) for v in params[:3])
+    n = n_interior
+    N = n + 1
+    M = mp.matrix(n, n)
+    for i in range(n):
+        M[i, i] = 2 * m / a + a
+        if i + 1 < n:
+            M[i, i + 1] = M[i + 1, i] = -m / a
+    b = mp.matrix(n, 1)
+    b[0] += m * xe / a
+    b[n - 1] += m * xe / a
+    c = m * xe * xe / a + a * xe * xe / 2
+    quad = (b.T * mp.inverse(M) * b)[0]
+    amp = (m / (2 * mp.pi * a)) ** (mp.mpf(N) / 2)
+    return float(amp * (2 * mp.pi) ** (mp.mpf(n) / 2) / mp.sqrt(mp.det(M)) * mp.exp(quad / 2 - c))
