@@ -225,7 +225,9 @@ Plan plan(const Geometry& g, int max_iter, bool ordered)
     p.fix_part = take(sizeof(double) * 2 * g.n_tiles);
     // one slot per fill workgroup; a problem never runs more workgroups
     // than tiles
-    const size_t slots = g.lds_hist_ok ? (size_t)std::min(kMaxWG, g.n_tiles) : 1;
+    // one histogram slot per workgroup in both modes (LDS histograms are
+    // copied out into them; global ones are added into them directly)
+    const size_t slots = (size_t)std::min(kMaxWG, g.n_tiles);
     p.histH = take(sizeof(double) * nb * slots);
     p.histC = take(sizeof(uint32_t) * nb * slots);
     // the learned warp's iterations (dimension 16): FP64 count weights
@@ -458,6 +460,7 @@ FillArgs fill_args(vegas_ctx* c, int t, unsigned long long* nonfinite)
     a.hist_Cw = nullptr;
     a.vmax = c->vmax(t);
     a.nonfinite = nonfinite;
+    a.hist_slots = c->g.lds_hist_ok ? 0 : 1;
     return a;
 }
 
@@ -507,13 +510,17 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
     const int lds_hist = warp_now ? 0 : (c->g.lds_hist_ok ? 1 : 0);
     // while the map is held a warped fill writes no histograms
     const bool warp_hist = warp_now && c->cfg.adapt_map;
+    // a plain fill with global histograms adds into one slot per workgroup
+    const bool slotted = !lds_hist && !warp_now;
+    const size_t nbr = slotted ? (size_t)nb * c->n_wg : (size_t)nb;
     if (!lds_hist && (!warp_now || warp_hist)) {
-        HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histH), nb, c->stream));
-        if (warp_now) HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histCw), nb, c->stream));
-        else HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histC), (nb + 1) / 2, c->stream));
+        HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histH), (int)nbr, c->stream));
+        if (warp_now) HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histCw), (int)nbr, c->stream));
+        else HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histC), (int)((nbr + 1) / 2), c->stream));
     }
     FillArgs a = fill_args(c, t, c->nonfinite());
     a.lds_hist = lds_hist;
+    a.hist_slots = slotted ? 1 : 0;
     if (warp_hist) a.hist_Cw = c->at<double>(c->p.histCw);
     c->hist_weighted = warp_hist;
     if (c->flow_on) HIPCHK(judge_mark(c, t, 0));
@@ -554,7 +561,7 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
     fa.wg_part = a.wg_part;
     fa.fix_part = fx.fix_part;
     fa.iter_out = c->at<double>(c->p.iter) + 2 * t;
-    const int n_slots = lds_hist ? c->n_wg : 1;
+    const int n_slots = lds_hist || slotted ? c->n_wg : 1;
     if (c->fused) {
         // small problem: fix-up, estimate and map in one launch, then the
         // allocation (the timing puts the map into the estimate phase)
@@ -709,8 +716,9 @@ vegas_status ctx_fill_pass(vegas_ctx* c)
     const int nb = c->g.D * c->g.ng;
     HIPCHK(launch_reset(c->vmax(t), 1, c->stream));
     if (!lds_hist) {
-        HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histH), nb, c->stream));
-        HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histC), (nb + 1) / 2, c->stream));
+        const size_t nbr = (size_t)nb * c->n_wg;
+        HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histH), (int)nbr, c->stream));
+        HIPCHK(launch_reset(c->at<unsigned long long>(c->p.histC), (int)((nbr + 1) / 2), c->stream));
     }
     // non-finite weights of this pass go to a spare counter, so the
     // iteration's own count is not touched

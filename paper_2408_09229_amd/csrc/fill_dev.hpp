@@ -722,8 +722,13 @@ __device__ __forceinline__ void fill_body(const FillArgs& a, unsigned char* smem
     io.tile_first = a.tile_first;
     io.v_out = a.v_out;
     io.side = a.side;
-    io.hist_H = a.hist_H;
-    io.hist_C = a.hist_C;
+    // global mode: with hist_slots each workgroup adds into a slot of its
+    // own, so a histogram line stays in one XCD's L2 instead of moving
+    // between the XCDs that add to it (the map kernel adds the slots in
+    // order)
+    const size_t slot = !a.lds_hist && a.hist_slots ? (size_t)blockIdx.x * nbins : 0;
+    io.hist_H = a.hist_H + slot;
+    io.hist_C = a.hist_C + slot;
     io.hist_Cw = nullptr;
     io.grid = a.grid;
 

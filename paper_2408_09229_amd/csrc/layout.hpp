@@ -64,11 +64,12 @@ struct FillArgs {
     double* v_out;              // [N_c] unbiased per-cube variance
     double* wg_part;            // [n_wg][2]: sum of cube means, sum of v/n
     TileSide* side;             // [n_tiles]
-    double* hist_H;             // LDS mode: [n_wg][D*N_g]; global mode: [D*N_g]
+    double* hist_H;             // LDS mode or hist_slots: [n_wg][D*N_g]; else [D*N_g]
     uint32_t* hist_C;           // same layout
     double* hist_Cw;            // warped fill (global mode): [D*N_g] FP64 sums of J_F
     unsigned long long* vmax;   // max v_h as FP64 bits (v >= 0)
     unsigned long long* nonfinite;
+    int32_t hist_slots;         // global mode: 1 = each workgroup adds into its own slot [n_wg][D*N_g]
 };
 
 struct FixupArgs {
