@@ -36,51 +36,46 @@ __global__ void k_flow_pack(const float* __restrict__ theta, bf16x8* __restrict_
     const float* W2 = P + kFW2;
     const float* W3 = P + kFW3;
     const int lane = r & 63;
-    const int kb = 8 * (lane >> 5);       // first k of this lane
-    const int n32 = lane & 31;
+    const int h = lane >> 5;              // k half of this lane
+    const int n32 = lane & 31;            // its row (A operand) or column (B operand)
     float v[8];
-    if (r < kPF2) {                       // F1[nt]: B[k = axis][n] = W1[n][pos(axis)] for axes in A
-        const int nt = r >> 6;
-        const int n = nt * 32 + n32;
+    if (r < kPT2) {                       // F1[mt]: W1[unit][pos(axis 8h + j)], axes in A
+        const int m = (r >> 6) * 32 + n32;
         for (int j = 0; j < 8; ++j) {
-            const int c = kb + j;
-            v[j] = flow_in_a(l, c) ? W1[n * kFlowHalf + flow_pos(l, c)] : 0.f;
+            const int c = 8 * h + j;
+            v[j] = flow_in_a(l, c) ? W1[m * kFlowHalf + flow_pos(l, c)] : 0.f;
         }
-    } else if (r < kPF3) {                // F2[nt][ks]: B[k][n] = W2[n][k]
-        r -= kPF2;
-        const int nt = r >> 8, ks = (r >> 6) & 3;
-        const int n = nt * 32 + n32;
-        for (int j = 0; j < 8; ++j) v[j] = W2[n * kFlowHidden + ks * 16 + kb + j];
-    } else if (r < kPR3) {                // F3[ks]: B[k][n = output] = W3[n][k], n < 16
-        r -= kPF3;
-        const int ks = r >> 6;
-        for (int j = 0; j < 8; ++j) v[j] = n32 < kFlowOut ? W3[n32 * kFlowHidden + ks * 16 + kb + j] : 0.f;
-    } else if (r < kPR2) {                // R3[nt]: B[k = o][n = h] = W3[o][h]
-        r -= kPR3;
-        const int nt = r >> 6;
-        const int n = nt * 32 + n32;
-        for (int j = 0; j < 8; ++j) v[j] = W3[(kb + j) * kFlowHidden + n];
-    } else if (r < kPR1) {                // R2[nt][ks]: B[k = n2][n = n1] = W2[n2][n1]
-        r -= kPR2;
-        const int nt = r >> 8, ks = (r >> 6) & 3;
-        const int n = nt * 32 + n32;
-        for (int j = 0; j < 8; ++j) v[j] = W2[(ks * 16 + kb + j) * kFlowHidden + n];
-    } else if (r < kPT2) {                // R1[ks]: B[k = h][n = axis] = W1[h][pos(axis)] for axes in A
-        r -= kPR1;
-        const int ks = r >> 6;
-        const int c = n32;
-        for (int j = 0; j < 8; ++j)
-            v[j] = (c < kFlowDim && flow_in_a(l, c)) ? W1[(ks * 16 + kb + j) * kFlowHalf + flow_pos(l, c)] : 0.f;
-    } else if (r < kPT3) {                // T2[mt][ks]: A[m][k] = W2[m][unit(ks, k)]
+    } else if (r < kPT3) {                // T2[mt][ks]: W2[unit2][unit1(ks, k)]
         r -= kPT2;
-        const int mt = r >> 8, ks = (r >> 6) & 3;
-        const int m = mt * 32 + n32;
-        for (int j = 0; j < 8; ++j) v[j] = W2[m * kFlowHidden + flow_t_unit(ks, lane >> 5, j)];
-    } else {                              // T3[ks]: A[m][k] = W3[row(m)][unit(ks, k)], zero rows padded
+        const int m = (r >> 8) * 32 + n32, ks = (r >> 6) & 3;
+        for (int j = 0; j < 8; ++j) v[j] = W2[m * kFlowHidden + flow_t_unit(ks, h, j)];
+    } else if (r < kPU3) {                // T3[ks]: W3[row(m)][unit2(ks, k)]
         r -= kPT3;
         const int ks = r >> 6;
         const int o = flow_t3_row(l, n32);
-        for (int j = 0; j < 8; ++j) v[j] = o >= 0 ? W3[o * kFlowHidden + flow_t_unit(ks, lane >> 5, j)] : 0.f;
+        for (int j = 0; j < 8; ++j) v[j] = o >= 0 ? W3[o * kFlowHidden + flow_t_unit(ks, h, j)] : 0.f;
+    } else if (r < kPU2) {                // U3[mt][ks]: W3[row(k)][unit2 = m]
+        r -= kPU3;
+        const int m = (r >> 7) * 32 + n32, ks = (r >> 6) & 1;
+        for (int j = 0; j < 8; ++j) {
+            const int o = flow_t3_row(l, flow_t_unit(ks, h, j));
+            v[j] = o >= 0 ? W3[o * kFlowHidden + m] : 0.f;
+        }
+    } else if (r < kPU1) {                // U2[mt][ks]: W2[unit2(ks, k)][unit1 = m]
+        r -= kPU2;
+        const int m = (r >> 8) * 32 + n32, ks = (r >> 6) & 3;
+        for (int j = 0; j < 8; ++j) v[j] = W2[flow_t_unit(ks, h, j) * kFlowHidden + m];
+    } else if (r < kPP) {                 // U1[ks]: W1[unit1(ks, k)][pos of row m's axis]
+        r -= kPU1;
+        const int ks = r >> 6;
+        const int p = flow_dx_row(l, n32);
+        for (int j = 0; j < 8; ++j) v[j] = p >= 0 ? W1[flow_t_unit(ks, h, j) * kFlowHalf + p] : 0.f;
+    } else if (r < kPI) {                 // P[ks]: 1 where T3's row (ks, k) carries output n
+        r -= kPP;
+        const int ks = r >> 6;
+        for (int j = 0; j < 8; ++j) v[j] = flow_t3_row(l, flow_t_unit(ks, h, j)) == n32 ? 1.f : 0.f;
+    } else {                              // I: 1 where axis 8h + j is column n
+        for (int j = 0; j < 8; ++j) v[j] = 8 * h + j == n32 ? 1.f : 0.f;
     }
     bf16x8 o;
     for (int j = 0; j < 8; ++j) o[j] = (__bf16)v[j];

@@ -35,32 +35,37 @@ constexpr int kFB3 = kFW3 + kFlowOut * kFlowHidden;        // [16]
 constexpr int kFLayer = kFB3 + kFlowOut;                   // 5776
 constexpr int kFParams = kFlowLayers * kFLayer;
 
-// Packed BF16 operands of one layer, one 8-value entry per (tile, k-step,
-// lane), for v_mfma_f32_32x32x16_bf16 (B operand: lane l holds
-// B[8 (l/32) + j][l % 32], j < 8):
-//   F1: x (k = axis, 16 with the B axes zeroed) . W1^T      [2 n-tiles]
-//   F2: h1 . W2^T                                          [2 n-tiles][4 k]
-//   F3: h2 . W3^T (n = output, 16 of 32 used)              [1 n-tile][4 k]
-//   R3: dO . W3     (backward; k = output)                 [2 n-tiles][1 k]
-//   R2: dA2 . W2                                           [2 n-tiles][4 k]
-//   R1: dA1 . W1 (n = axis, 16 of 32 used)                 [1 n-tile][4 k]
-// and as A operands of the transposed forward products W . act^T (samples
-// as columns; lane l holds A[l % 32][8 (l/32) + j]), where one product's
-// output registers are the next product's B operand as they stand:
-//   F1 (the same entries): W1 . x^T                          [2 m-tiles]
-//   T2: W2 . h1^T, k in the hidden units' register order     [2 m-tiles][4 k]
-//   T3: W3 . h2^T, output rows placed where the lanes that
-//       move each axis hold them (flow_t3_row)               [4 k]
+// Packed BF16 operands of one layer for v_mfma_f32_32x32x16_bf16, one
+// 8-value entry per (tile, k-step, lane): lane l holds A[l % 32][8 (l/32) + j]
+// of an A operand, or B[8 (l/32) + j][l % 32] of a B operand.  A product's
+// output register r of lane l holds row 8 (r/4) + 4 (l/32) + r % 4, column
+// l % 32 ("register order").  The forward products run as W . act^T
+// (samples as columns), so each one's output registers are the next one's B
+// operand as they stand, with the weights' k order packed to match:
+//   F1: W1 (rows: hidden unit; k: axis, B axes zero)        [2 m-tiles]
+//   T2: W2, k in the hidden units' register order           [2 m-tiles][4 k]
+//   T3: W3, k likewise; rows placed where the lanes that
+//       move each axis hold them (flow_t3_row)              [4 k]
+// The backward products run the same way (samples as columns) on the
+// transposed weights, and read as B operands with samples as rows they give
+// the activations and deltas with samples in registers, which the weight
+// gradients (sums over samples) take as both operands:
+//   U3: W3^T (rows: hidden unit of h2; k: T3's rows)        [2 m-tiles][2 k]
+//   U2: W2^T (rows: unit of h1; k: units of h2, reg. order) [2 m-tiles][4 k]
+//   U1: W1^T (rows placed on the lanes holding each
+//       conditioning axis, flow_dx_row; k: units of h1)    [4 k]
+//   P:  0/1, T3's rows -> conditioner outputs (a transpose) [2 k]
+//   I:  0/1, axes -> axes (a transpose)                     [1]
 constexpr int kPF1 = 0;
-constexpr int kPF2 = kPF1 + 2 * 64;
-constexpr int kPF3 = kPF2 + 2 * 4 * 64;
-constexpr int kPR3 = kPF3 + 4 * 64;
-constexpr int kPR2 = kPR3 + 2 * 64;
-constexpr int kPR1 = kPR2 + 2 * 4 * 64;
-constexpr int kPT2 = kPR1 + 4 * 64;
+constexpr int kPT2 = kPF1 + 2 * 64;
 constexpr int kPT3 = kPT2 + 2 * 4 * 64;
-constexpr int kPLayer = kPT3 + 4 * 64;           // 2560 entries of 16 bytes
-constexpr int kPFwdT = 2 * 64 + 2 * 4 * 64 + 4 * 64;   // F1, T2, T3: 896 entries per layer
+constexpr int kPU3 = kPT3 + 4 * 64;
+constexpr int kPU2 = kPU3 + 2 * 2 * 64;
+constexpr int kPU1 = kPU2 + 2 * 4 * 64;
+constexpr int kPP = kPU1 + 4 * 64;
+constexpr int kPI = kPP + 2 * 64;
+constexpr int kPLayer = kPI + 64;                // 2112 entries of 16 bytes
+constexpr int kPFwdT = kPU3;                     // F1, T2, T3: the forward pass's 896 entries
 
 // Register order of a product's 32x32 output (register r of lane l holds
 // row 8 (r/4) + 4 (l/32) + r % 4): fed to the next product as its B operand,
@@ -91,6 +96,19 @@ __host__ __device__ inline int flow_t3_row(int l, int m)
     const int c = 8 * half + (r & 7);
     if (flow_in_a(l, c)) return -1;
     return (r < 8 ? 0 : kFlowHalf) + flow_pos(l, c);
+}
+
+// Conditioning axis (its position in A) carried by row m of the transposed
+// input-gradient product dX^T = W1^T dA1^T of layer l, or -1: row m lands in
+// register j = 4 (m/8) + m % 4 < 8 of the lanes of half (m/4) % 2, the
+// lane's own axis 8 half + j.
+__host__ __device__ inline int flow_dx_row(int l, int m)
+{
+    const int half = (m >> 2) & 1;
+    const int r = 4 * (m >> 3) + (m & 3);
+    const int c = 8 * half + (r & 7);
+    if (r >= 8 || !flow_in_a(l, c)) return -1;
+    return flow_pos(l, c);
 }
 
 struct FlowSampleArgs {

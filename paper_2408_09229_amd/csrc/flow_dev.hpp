@@ -40,87 +40,12 @@ __device__ __forceinline__ float flow_phi_inv(float m, bool upper)
 }
 
 // ---------------------------------------------------------------------------
-// one coupling layer for the 32 samples of a wavefront
+// launch shapes
 // ---------------------------------------------------------------------------
 constexpr int kFlowWaves = 4;
 constexpr int kFlowThreads = 64 * kFlowWaves;
 constexpr int kFlowSampleWaves = 8;                    // the sampling pass: independent waves
 constexpr int kFlowSampleThreads = 64 * kFlowSampleWaves;
-struct __align__(16) FlowLds {
-    __bf16 h[kFlowWaves][32 * kFlowHidden];            // hidden activations [sample][unit]
-    float o[kFlowWaves][32 * kFlowOut];                // conditioner outputs [sample][a(8), t(8)]
-};
-
-// MLP of layer l for the wave's 32 samples: outputs into ob[sample][16].
-// z: the lane's 8 Gaussian coordinates (axes 8 (lane/32) + j of sample
-// lane % 32).  h1 goes to hb, h2 to h2b (may be hb); xb (if not null) keeps
-// the BF16 product input x [sample][axis].  Called by every lane of the
-// workgroup (it synchronises it).
-__device__ __forceinline__ void flow_mlp(int l, const float (&z)[8], const float* __restrict__ P,
-                                         const bf16x8* __restrict__ pk, __bf16* hb, float* ob,
-                                         __bf16* h2b = nullptr, __bf16* xb = nullptr)
-{
-    if (!h2b) h2b = hb;
-    const int lane = threadIdx.x & 63;
-    const int half = lane >> 5;
-    const int n32 = lane & 31;
-    bf16x8 xa;
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-        xa[j] = flow_in_a(l, 8 * half + j) ? (__bf16)(kFlowXScale * z[j]) : (__bf16)0.f;
-    if (xb) *reinterpret_cast<bf16x8*>(xb + n32 * kFlowDim + 8 * half) = xa;
-    // h1 = relu(W1 x + b1)
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-        f32x16 acc = {};
-        acc = mfma(xa, pk[kPF1 + nt * 64 + lane], acc);
-        const float bias = P[kFB1 + nt * 32 + n32];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const float v = acc[r] + bias;
-            hb[mrow(lane, r) * kFlowHidden + nt * 32 + n32] = (__bf16)(v > 0.f ? v : 0.f);
-        }
-    }
-    __syncthreads();
-    // h2 = relu(W2 h1 + b2)
-    bf16x8 ha[4];
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) ha[ks] = *reinterpret_cast<const bf16x8*>(hb + n32 * kFlowHidden + ks * 16 + 8 * half);
-    f32x16 acc2[2];
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-        f32x16 acc = {};
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) acc = mfma(ha[ks], pk[kPF2 + (nt * 4 + ks) * 64 + lane], acc);
-        acc2[nt] = acc;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-        const float bias = P[kFB2 + nt * 32 + n32];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const float v = acc2[nt][r] + bias;
-            h2b[mrow(lane, r) * kFlowHidden + nt * 32 + n32] = (__bf16)(v > 0.f ? v : 0.f);
-        }
-    }
-    __syncthreads();
-    // outputs = W3 h2 + b3 (columns 16..31 of the product are zero padding)
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) ha[ks] = *reinterpret_cast<const bf16x8*>(h2b + n32 * kFlowHidden + ks * 16 + 8 * half);
-    {
-        f32x16 acc = {};
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) acc = mfma(ha[ks], pk[kPF3 + ks * 64 + lane], acc);
-        if (n32 < kFlowOut) {
-            const float bias = P[kFB3 + n32];
-#pragma unroll
-            for (int r = 0; r < 16; ++r) ob[mrow(lane, r) * kFlowOut + n32] = acc[r] + bias;
-        }
-    }
-    __syncthreads();
-}
-
 // ---------------------------------------------------------------------------
 // the conditioner MLP with the samples as columns
 // ---------------------------------------------------------------------------
@@ -156,13 +81,42 @@ __device__ __forceinline__ void flow_stage_fwd(FlowFwdLds& S, const bf16x8* __re
     }
 }
 
+// the 8 values of register-order k-step q of a product's output (registers
+// 8 (q % 2) .. + 7 of tile q / 2), through relu, as a BF16 operand
+__device__ __forceinline__ bf16x8 relu_bf16(const f32x16& acc, int q2)
+{
+    bf16x8 o;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) o[i] = (__bf16)fmaxf(acc[8 * q2 + i], 0.f);
+    return o;
+}
+
+// start of an accumulator with the bias of the product's rows: register
+// group q holds rows 32 tile + 8 q + 4 half + 0..3, contiguous in the bias
+__device__ __forceinline__ f32x16 bias_rows(const float* __restrict__ b, int half)
+{
+    f32x16 acc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float4 v = *reinterpret_cast<const float4*>(b + 8 * q + 4 * half);
+        acc[4 * q] = v.x;
+        acc[4 * q + 1] = v.y;
+        acc[4 * q + 2] = v.z;
+        acc[4 * q + 3] = v.w;
+    }
+    return acc;
+}
+
 // Conditioner of layer L for the wave's 32 samples; lane l holds axes
-// 8 (l/32) + j of sample l % 32 in z.  Returns the last product's
+// 8 (l/32) + j of sample l % 32 in z.  W: the layer's packed operands (F1,
+// T2, T3 first), B: its biases b1, b2, b3.  Returns the last product's
 // registers: j < 8 the raw log-scale of the lane's axis j, 8 + j its shift
-// (meaningful where that axis moves in layer L).  Biases start the
-// accumulators.
+// (meaningful where that axis moves in layer L).  x, h1 and h2 receive the
+// BF16 product inputs (register order, after relu).
 template <int L>
-__device__ __forceinline__ f32x16 flow_mlp_t(const float (&z)[8], const FlowFwdLds& S)
+__device__ __forceinline__ f32x16 flow_mlp_t(const float (&z)[8], const bf16x8* __restrict__ W,
+                                             const float* __restrict__ B, bf16x8& x, bf16x8 (&h1)[4],
+                                             bf16x8 (&h2)[4])
 {
     // the weights in LDS do not change inside the callers' loops: this
     // compiler-only fence keeps their loads here instead of hoisted (and
@@ -170,46 +124,24 @@ __device__ __forceinline__ f32x16 flow_mlp_t(const float (&z)[8], const FlowFwdL
     __asm__ volatile("" ::: "memory");
     const int lane = threadIdx.x & 63;
     const int half = lane >> 5;
-    const bf16x8* W = S.w[L];
-    const float* B = S.b[L];
-    bf16x8 x;
 #pragma unroll
     for (int j = 0; j < 8; ++j) x[j] = flow_in_a(L, 8 * half + j) ? (__bf16)(kFlowXScale * z[j]) : (__bf16)0.f;
-    // h1 = relu(W1 x + b1): the rows of register group q are units
-    // 32 mt + 8 q + 4 half + 0..3, contiguous in the bias
-    bf16x8 h1[4];
+    // h1 = relu(W1 x + b1)
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
-        f32x16 acc;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float4 b = *reinterpret_cast<const float4*>(B + 32 * mt + 8 * q + 4 * half);
-            acc[4 * q] = b.x;
-            acc[4 * q + 1] = b.y;
-            acc[4 * q + 2] = b.z;
-            acc[4 * q + 3] = b.w;
-        }
-        acc = mfma(W[mt * 64 + lane], x, acc);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) h1[2 * mt + (r >> 3)][r & 7] = (__bf16)fmaxf(acc[r], 0.f);
+        f32x16 acc = bias_rows(B + 32 * mt, half);
+        acc = mfma(W[kPF1 + mt * 64 + lane], x, acc);
+        h1[2 * mt] = relu_bf16(acc, 0);
+        h1[2 * mt + 1] = relu_bf16(acc, 1);
     }
     // h2 = relu(W2 h1 + b2)
-    bf16x8 h2[4];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
-        f32x16 acc;
+        f32x16 acc = bias_rows(B + kFlowHidden + 32 * mt, half);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float4 b = *reinterpret_cast<const float4*>(B + kFlowHidden + 32 * mt + 8 * q + 4 * half);
-            acc[4 * q] = b.x;
-            acc[4 * q + 1] = b.y;
-            acc[4 * q + 2] = b.z;
-            acc[4 * q + 3] = b.w;
-        }
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) acc = mfma(W[2 * 64 + (mt * 4 + ks) * 64 + lane], h1[ks], acc);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) h2[2 * mt + (r >> 3)][r & 7] = (__bf16)fmaxf(acc[r], 0.f);
+        for (int ks = 0; ks < 4; ++ks) acc = mfma(W[kPT2 + (mt * 4 + ks) * 64 + lane], h1[ks], acc);
+        h2[2 * mt] = relu_bf16(acc, 0);
+        h2[2 * mt + 1] = relu_bf16(acc, 1);
     }
     // outputs = W3 h2 + b3, rows placed by flow_t3_row
     f32x16 acc;
@@ -219,8 +151,15 @@ __device__ __forceinline__ f32x16 flow_mlp_t(const float (&z)[8], const FlowFwdL
         acc[r] = o >= 0 ? B[2 * kFlowHidden + o] : 0.f;
     }
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) acc = mfma(W[10 * 64 + ks * 64 + lane], h2[ks], acc);
+    for (int ks = 0; ks < 4; ++ks) acc = mfma(W[kPT3 + ks * 64 + lane], h2[ks], acc);
     return acc;
+}
+
+template <int L>
+__device__ __forceinline__ f32x16 flow_mlp_t(const float (&z)[8], const FlowFwdLds& S)
+{
+    bf16x8 x, h1[4], h2[4];
+    return flow_mlp_t<L>(z, S.w[L], S.b[L], x, h1, h2);
 }
 
 // Forward coupling layer L on the lane's axes: z_B -> z_B e^s + t; adds the

@@ -14,11 +14,10 @@
 //                   the upstream gradient dL/du_0 = c u_0
 //   k_flow_grad     the coupling layers l = 0..3 in turn: from g = dL/du_l,
 //                   the layer's log-scales and inverse transform give
-//                   dL/d(a, t); the MLP backward runs on MFMA (dO W3, dA2 W2,
-//                   dA1 W1); the weight gradients dW = sum_samples delta^T
-//                   activation are MFMA products over the workgroup's 128
-//                   samples, each wave owning some output tiles,
-//                   accumulated across the workgroup's chunks
+//                   dL/d(a, t); the MLP backward and the weight gradients
+//                   dW = sum_samples delta^T activation run on MFMA with
+//                   every activation and delta in registers, each wave
+//                   summing its samples, the waves added in LDS
 //   k_flow_reduce   per-workgroup gradients summed in a fixed order, and
 //                   Adam on the FP32 parameters (then the BF16 repack)
 #include <hip/hip_runtime.h>
@@ -132,251 +131,339 @@ __global__ __launch_bounds__(kFlowSampleThreads) void k_flow_inverse(FlowTrainAr
 }
 
 // ---------------------------------------------------------------------------
-// backward pass of one coupling layer
+// backward pass of the coupling layers
 // ---------------------------------------------------------------------------
-struct __align__(16) FlowGradLds {
-    float o[kFlowWaves][32 * kFlowOut];                // conditioner outputs, then dL/d(a, t) (FP32)
-    __bf16 h1[kFlowWaves][32 * kFlowHidden];
-    __bf16 h2[kFlowWaves][32 * kFlowHidden];
-    __bf16 da2[kFlowWaves][32 * kFlowHidden];
-    __bf16 da1[kFlowWaves][32 * kFlowHidden];
-    __bf16 x[kFlowWaves][32 * kFlowDim];
-    float dx[kFlowWaves][32 * 32];
-    float red[2][kFlowWaves][kFlowHidden];
+// Per wave and 32 samples, all in registers: the conditioner forward with
+// samples as columns (h1, h2 and the outputs in register order); the inverse
+// transform's derivatives per lane; the deltas back through the MLP with
+// samples as columns (U3, U2, U1), which give the next dL/du in the lanes of
+// their axes; the same activations and deltas with samples as rows (the
+// column products read as B operands, and the 0/1 products P and I), whose
+// output registers hold 16 samples per lane; and the weight gradients as
+// products over samples with both operands in that layout.  Each wave sums
+// its samples' gradients in registers; at the end of a layer the waves add
+// theirs in LDS and the workgroup writes its part.
+struct __align__(16) FlowBwdLds {
+    bf16x8 w[kPLayer];                         // this layer's operands
+    float b[2 * kFlowHidden + kFlowOut];       // b1, b2, b3
+    float red[kFlowWaves][kFLayer];            // per-wave gradients of the layer
 };
 
-__device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
-
-__global__ __launch_bounds__(kFlowThreads) void k_flow_grad(FlowTrainArgs a)
+// the 8 registers of k-step q2 (registers 8 q2 .. + 7) as BF16
+__device__ __forceinline__ bf16x8 to_bf16(const f32x16& acc, int q2)
 {
-    __shared__ FlowGradLds S;
+    bf16x8 o;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) o[i] = (__bf16)acc[8 * q2 + i];
+    return o;
+}
+
+// sum of a lane's 16 registers
+__device__ __forceinline__ float reg_sum(const f32x16& a)
+{
+    float s = 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s += a[r];
+    return s;
+}
+
+// relu mask of a register-order tile: where the activation (BF16, k-steps
+// 2 t and 2 t + 1 of a register-order input) is positive
+__device__ __forceinline__ void mask_by(f32x16& d, const bf16x8& a0, const bf16x8& a1)
+{
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        if (!((float)a0[i] > 0.f)) d[i] = 0.f;
+        if (!((float)a1[i] > 0.f)) d[8 + i] = 0.f;
+    }
+}
+
+// per-wave gradient of one layer, in registers
+struct LayerGrad {
+    f32x16 w3[2];          // dW3[o][32 nt + column], rows o < 16
+    f32x16 w2[2][2];       // dW2[32 mt + row][32 nt + column]
+    f32x16 w1[2];          // dW1[32 mt + row][axis = column]
+    float b3, b2[2], b1[2];
+};
+
+// one layer's backward pass for the wave's 32 samples; g holds dL/du_l of
+// the lane's axes and receives dL/du_{l+1}
+template <int L>
+__device__ __forceinline__ void grad_chunk(const float (&u)[8], float (&g)[8], float coef, const bf16x8* __restrict__ W,
+                                           const float* __restrict__ B, LayerGrad& G)
+{
+    const int lane = threadIdx.x & 63;
+    const int half = lane >> 5;
+    bf16x8 x, h1[4], h2[4];
+    const f32x16 o = flow_mlp_t<L>(u, W, B, x, h1, h2);
+
+    // ---- inverse transform and log-scale: dL/d(a, t) ----------------------
+    // u_l,B = (u_{l+1},B - t) e^-s: dL/ds = c - g_B u_l,B (the log-scale is
+    // a term of log J_F), dL/dt = -g_B e^-s, dL/du_{l+1},B = g_B e^-s;
+    // s = S tanh(a/S), ds/da = 1 - (s/S)^2.  dO in T3's row order.
+    f32x16 dO;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) dO[r] = 0.f;
+    float gn[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        gn[j] = g[j];
+        if (flow_in_a(L, 8 * half + j)) continue;
+        const float s = flow_scale(o[j]);
+        const float es = expf(-s);
+        const float ub = (u[j] - o[8 + j]) * es;
+        const float ds = coef - g[j] * ub;
+        const float rs = s * (1.f / kFlowSMax);
+        dO[j] = ds * (1.f - rs * rs);
+        dO[8 + j] = -g[j] * es;
+        gn[j] = g[j] * es;
+    }
+    const bf16x8 dOb[2] = {to_bf16(dO, 0), to_bf16(dO, 1)};
+
+    // ---- deltas with samples as columns ------------------------------------
+    bf16x8 dA2[4], dA1[4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        f32x16 acc = {};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) acc = mfma(W[kPU3 + (mt * 2 + ks) * 64 + lane], dOb[ks], acc);
+        mask_by(acc, h2[2 * mt], h2[2 * mt + 1]);
+        dA2[2 * mt] = to_bf16(acc, 0);
+        dA2[2 * mt + 1] = to_bf16(acc, 1);
+    }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        f32x16 acc = {};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) acc = mfma(W[kPU2 + (mt * 4 + ks) * 64 + lane], dA2[ks], acc);
+        mask_by(acc, h1[2 * mt], h1[2 * mt + 1]);
+        dA1[2 * mt] = to_bf16(acc, 0);
+        dA1[2 * mt + 1] = to_bf16(acc, 1);
+    }
+    {
+        // dX: register j < 8 is the lane's conditioning axis j
+        f32x16 acc = {};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) acc = mfma(W[kPU1 + ks * 64 + lane], dA1[ks], acc);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (flow_in_a(L, 8 * half + j)) gn[j] = g[j] + kFlowXScale * acc[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) g[j] = gn[j];
+
+    // ---- the same with samples as rows (16 samples in each lane's registers)
+    const int n32 = lane & 31;
+    bf16x8 h1r[2][2], h2r[2][2], dA2r[2][2], dA1r[2][2], dOr[2], xr[2];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        f32x16 acc;
+        const float b1 = B[32 * nt + n32];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = b1;
+        acc = mfma(x, W[kPF1 + nt * 64 + lane], acc);
+        h1r[nt][0] = relu_bf16(acc, 0);
+        h1r[nt][1] = relu_bf16(acc, 1);
+    }
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        f32x16 acc;
+        const float b2 = B[kFlowHidden + 32 * nt + n32];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = b2;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) acc = mfma(h1[ks], W[kPT2 + (nt * 4 + ks) * 64 + lane], acc);
+        h2r[nt][0] = relu_bf16(acc, 0);
+        h2r[nt][1] = relu_bf16(acc, 1);
+    }
+    {
+        // dO with samples as rows through the 0/1 product P: its BF16 part
+        // (the weight gradient's operand) and, for the bias sum, the
+        // rounding remainder too (dO = hi + lo to about 16 bits)
+        f32x16 acc = {}, rem = {};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            bf16x8 lo;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) lo[i] = (__bf16)(dO[8 * ks + i] - (float)dOb[ks][i]);
+            acc = mfma(dOb[ks], W[kPP + ks * 64 + lane], acc);
+            rem = mfma(lo, W[kPP + ks * 64 + lane], rem);
+        }
+        G.b3 += reg_sum(acc) + reg_sum(rem);
+        dOr[0] = to_bf16(acc, 0);
+        dOr[1] = to_bf16(acc, 1);
+    }
+    {
+        f32x16 acc = {};
+        acc = mfma(x, W[kPI + lane], acc);
+        xr[0] = to_bf16(acc, 0);
+        xr[1] = to_bf16(acc, 1);
+    }
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        f32x16 acc = {};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) acc = mfma(dOb[ks], W[kPU3 + (nt * 2 + ks) * 64 + lane], acc);
+        mask_by(acc, h2r[nt][0], h2r[nt][1]);
+        G.b2[nt] += reg_sum(acc);
+        dA2r[nt][0] = to_bf16(acc, 0);
+        dA2r[nt][1] = to_bf16(acc, 1);
+    }
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        f32x16 acc = {};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) acc = mfma(dA2[ks], W[kPU2 + (nt * 4 + ks) * 64 + lane], acc);
+        mask_by(acc, h1r[nt][0], h1r[nt][1]);
+        G.b1[nt] += reg_sum(acc);
+        dA1r[nt][0] = to_bf16(acc, 0);
+        dA1r[nt][1] = to_bf16(acc, 1);
+    }
+
+    // ---- weight gradients: sums over the samples ---------------------------
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) G.w3[nt] = mfma(dOr[ks], h2r[nt][ks], G.w3[nt]);
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) G.w2[mt][nt] = mfma(dA2r[mt][ks], h1r[nt][ks], G.w2[mt][nt]);
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) G.w1[mt] = mfma(dA1r[mt][ks], xr[ks], G.w1[mt]);
+}
+
+// this wave's gradient of layer L into its LDS slice (every entry written)
+template <int L>
+__device__ __forceinline__ void grad_to_lds(const LayerGrad& G, float* __restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const int n32 = lane & 31;
+    const int half = lane >> 5;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int o = mrow(lane, r);
+            if (o < kFlowOut) out[kFW3 + o * kFlowHidden + 32 * nt + n32] = G.w3[nt][r];
+        }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                out[kFW2 + (32 * mt + mrow(lane, r)) * kFlowHidden + 32 * nt + n32] = G.w2[mt][nt][r];
+    if (n32 < kFlowDim && flow_in_a(L, n32)) {
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                out[kFW1 + (32 * mt + mrow(lane, r)) * kFlowHalf + flow_pos(L, n32)] = G.w1[mt][r];
+    }
+    // bias sums: each lane holds 16 samples of its column; the other half
+    // holds the other 16
+    const float b3 = G.b3 + __shfl_xor(G.b3, 32, 64);
+    float b2[2], b1[2];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        b2[nt] = G.b2[nt] + __shfl_xor(G.b2[nt], 32, 64);
+        b1[nt] = G.b1[nt] + __shfl_xor(G.b1[nt], 32, 64);
+    }
+    if (half == 0) {
+        if (n32 < kFlowOut) out[kFB3 + n32] = b3;
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            out[kFB2 + 32 * nt + n32] = b2[nt];
+            out[kFB1 + 32 * nt + n32] = b1[nt];
+        }
+    }
+}
+
+// layer L: every chunk of the workgroup, then its part of the gradient
+template <int L>
+__device__ void grad_layer(const FlowTrainArgs& a, FlowBwdLds& S, float* const (&gbuf)[2])
+{
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int half = lane >> 5;
     const int n32 = lane & 31;
     const uint32_t N = a.n;
-    const uint32_t chunks = (N + 31u) / 32u;
-    const uint32_t per_round = gridDim.x * kFlowWaves;
-    const uint32_t rounds = (chunks + per_round - 1u) / per_round;
-    // dL/du_l passes between the layers through two buffers: the inverse
-    // pass left dL/du_0 in g_in; a sample's gradient is written and read
-    // again by the same lane, as every layer maps chunks to waves alike
-    float* const gbuf[2] = {const_cast<float*>(a.g_in), a.g_out};
-    for (int l = 0; l < kFlowLayers; ++l) {
-        const float* g_in = gbuf[l & 1];
-        float* g_out = gbuf[(l & 1) ^ 1];
-        const float* P = a.theta + (size_t)l * kFLayer;
-        const bf16x8* pk = reinterpret_cast<const bf16x8*>(a.packed) + (size_t)l * kPLayer;
-        // the layer's input in the inverse direction, u_{l+1}: z_4 itself for
-        // the last layer (at the training samples), else the inverse pass's
-        // compact output
-        const bool from_z = l == kFlowLayers - 1;
-        const float* uin = from_z ? a.zf : a.U + (size_t)l * N * kFlowDim;
-        f32x16 acc3 = {}, acc2 = {}, acc1 = {};
-        float db3 = 0.f, db2[2] = {0.f, 0.f}, db1[2] = {0.f, 0.f};
-        for (uint32_t rd = 0; rd < rounds; ++rd) {
-            const uint32_t chunk = rd * per_round + blockIdx.x * kFlowWaves + wave;
-            const bool live = chunk < chunks;
-            const uint32_t k = live ? min(chunk * 32u + (uint32_t)n32, N - 1u) : 0u;
-            const bool valid = live && chunk * 32u + (uint32_t)n32 < N;
-            float u[8], g[8];
-            load8(uin + (from_z ? (size_t)a.off + (size_t)k * a.stride : (size_t)k) * kFlowDim + 8 * half, u);
-            if (valid) {
-                load8(g_in + (size_t)k * kFlowDim + 8 * half, g);
-            } else {
-    #pragma unroll
-                for (int j = 0; j < 8; ++j) g[j] = 0.f;
-            }
-            const float coef = train_coef(a, k, valid);
-
-            // ---- recompute the conditioner of this layer -----------------------
-            flow_mlp(l, u, P, pk, S.h1[wave], S.o[wave], S.h2[wave], S.x[wave]);
-
-            // ---- inverse transform and log-scale: dL/d(a, t) -------------------
-            // u_l,B = (u_{l+1},B - t) e^-s: dL/ds = c - g_B u_l,B (the log-scale
-            // is a term of log J_F), dL/dt = -g_B e^-s, dL/du_{l+1},B = g_B e^-s;
-            // s = S tanh(a/S), ds/da = 1 - (s/S)^2
-            float gn[8];
-    #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int c = 8 * half + j;
-                gn[j] = g[j];
-                if (flow_in_a(l, c)) continue;
-                float* ob = S.o[wave] + n32 * kFlowOut + flow_pos(l, c);
-                const float s = flow_scale(ob[0]);
-                const float es = expf(-s);
-                const float ub = (u[j] - ob[kFlowHalf]) * es;
-                const float ds = valid ? coef - g[j] * ub : 0.f;
-                const float rs = s * (1.f / kFlowSMax);
-                ob[0] = ds * (1.f - rs * rs);
-                ob[kFlowHalf] = -g[j] * es;
-                gn[j] = g[j] * es;
-            }
-            __syncthreads();
-
-            // ---- dH2 = dO W3; dA2 = dH2 (h2 > 0) -------------------------------
-            {
-                f32x16 t[2] = {};
-                const float* orow = S.o[wave] + n32 * kFlowOut + 8 * half;
-                bf16x8 av;
-    #pragma unroll
-                for (int j = 0; j < 8; ++j) av[j] = (__bf16)orow[j];
-    #pragma unroll
-                for (int nt = 0; nt < 2; ++nt) t[nt] = mfma(av, pk[kPR3 + nt * 64 + lane], t[nt]);
-    #pragma unroll
-                for (int nt = 0; nt < 2; ++nt) {
-    #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const int idx = mrow(lane, r) * kFlowHidden + nt * 32 + n32;
-                        const float d = (float)S.h2[wave][idx] > 0.f ? t[nt][r] : 0.f;
-                        db2[nt] += d;
-                        S.da2[wave][idx] = (__bf16)d;
-                    }
-                }
-            }
-            __syncthreads();
-
-            // ---- dH1 = dA2 W2; dA1 = dH1 (h1 > 0) ------------------------------
-            {
-                f32x16 t[2] = {};
-    #pragma unroll
-                for (int ks = 0; ks < 4; ++ks) {
-                    const bf16x8 av = ld8(S.da2[wave] + n32 * kFlowHidden + ks * 16 + 8 * half);
-    #pragma unroll
-                    for (int nt = 0; nt < 2; ++nt) t[nt] = mfma(av, pk[kPR2 + (nt * 4 + ks) * 64 + lane], t[nt]);
-                }
-    #pragma unroll
-                for (int nt = 0; nt < 2; ++nt) {
-    #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const int idx = mrow(lane, r) * kFlowHidden + nt * 32 + n32;
-                        const float d = (float)S.h1[wave][idx] > 0.f ? t[nt][r] : 0.f;
-                        db1[nt] += d;
-                        S.da1[wave][idx] = (__bf16)d;
-                    }
-                }
-            }
-            __syncthreads();
-
-            // ---- dX = dA1 W1 (columns = axes) ---------------------------------
-            {
-                f32x16 t = {};
-    #pragma unroll
-                for (int ks = 0; ks < 4; ++ks)
-                    t = mfma(ld8(S.da1[wave] + n32 * kFlowHidden + ks * 16 + 8 * half), pk[kPR1 + ks * 64 + lane], t);
-    #pragma unroll
-                for (int r = 0; r < 16; ++r) S.dx[wave][mrow(lane, r) * 32 + n32] = t[r];
-            }
-            __syncthreads();
-
-            // ---- dL/du_{l+1}: conditioning axes add the MLP's input gradient ----
-    #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int c = 8 * half + j;
-                if (flow_in_a(l, c)) gn[j] = g[j] + kFlowXScale * S.dx[wave][n32 * 32 + c];
-            }
-            if (valid) store8(g_out + (size_t)k * kFlowDim + 8 * half, gn);
-
-            // ---- weight gradients over the workgroup's 128 samples ------------
-            // dW3[o][h] += sum_s dO[s][o] h2[s][h]: one 32-row tile (rows o < 16
-            // used), waves 0 and 1 take the two column tiles
-            if (wave < 2) {
-    #pragma unroll 1
-                for (int ks = 0; ks < 8; ++ks) {
-                    const int ws = ks >> 1;
-                    const int s0 = (ks & 1) * 16 + 8 * half;
-                    bf16x8 av, bv;
-    #pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        av[j] = n32 < kFlowOut ? (__bf16)S.o[ws][(s0 + j) * kFlowOut + n32] : (__bf16)0.f;
-                        bv[j] = S.h2[ws][(s0 + j) * kFlowHidden + wave * 32 + n32];
-                    }
-                    acc3 = mfma(av, bv, acc3);
-                }
-            }
-            // dW2[n2][n1] += sum_s dA2[s][n2] h1[s][n1]: one tile per wave
-            {
-                const int mt = wave >> 1, nt = wave & 1;
-    #pragma unroll 1
-                for (int ks = 0; ks < 8; ++ks) {
-                    const int ws = ks >> 1;
-                    const int s0 = (ks & 1) * 16 + 8 * half;
-                    bf16x8 av, bv;
-    #pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        av[j] = S.da2[ws][(s0 + j) * kFlowHidden + mt * 32 + n32];
-                        bv[j] = S.h1[ws][(s0 + j) * kFlowHidden + nt * 32 + n32];
-                    }
-                    acc2 = mfma(av, bv, acc2);
-                }
-            }
-            // dW1[h][axis] += sum_s dA1[s][h] x[s][axis]: waves 2 and 3
-            if (wave >= 2) {
-                const int mt = wave - 2;
-    #pragma unroll 1
-                for (int ks = 0; ks < 8; ++ks) {
-                    const int ws = ks >> 1;
-                    const int s0 = (ks & 1) * 16 + 8 * half;
-                    bf16x8 av, bv;
-    #pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        av[j] = S.da1[ws][(s0 + j) * kFlowHidden + mt * 32 + n32];
-                        bv[j] = n32 < kFlowDim ? S.x[ws][(s0 + j) * kFlowDim + n32] : (__bf16)0.f;
-                    }
-                    acc1 = mfma(av, bv, acc1);
-                }
-            }
-            // db3: one output per thread, FP32
-            if (threadIdx.x < kFlowOut) {
-                for (int ws = 0; ws < kFlowWaves; ++ws)
-                    for (int s = 0; s < 32; ++s) db3 += S.o[ws][s * kFlowOut + threadIdx.x];
-            }
-            __syncthreads();
-        }
-
-        // ---- this workgroup's gradient of layer l ------------------------------
-        float* out = a.part + (size_t)blockIdx.x * kFParams + (size_t)l * kFLayer;
-        if (wave < 2) {
-    #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int o = mrow(lane, r);
-                if (o < kFlowOut) out[kFW3 + o * kFlowHidden + wave * 32 + n32] = acc3[r];
-            }
-        }
-        {
-            const int mt = wave >> 1, nt = wave & 1;
-    #pragma unroll
-            for (int r = 0; r < 16; ++r)
-                out[kFW2 + (mt * 32 + mrow(lane, r)) * kFlowHidden + nt * 32 + n32] = acc2[r];
-        }
-        if (wave >= 2 && n32 < kFlowDim && flow_in_a(l, n32)) {
-    #pragma unroll
-            for (int r = 0; r < 16; ++r)
-                out[kFW1 + ((wave - 2) * 32 + mrow(lane, r)) * kFlowHalf + flow_pos(l, n32)] = acc1[r];
-        }
-        if (threadIdx.x < kFlowOut) out[kFB3 + threadIdx.x] = db3;
-    #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-            db2[nt] += __shfl_xor(db2[nt], 32, 64);
-            db1[nt] += __shfl_xor(db1[nt], 32, 64);
-            if (half == 0) {
-                S.red[0][wave][nt * 32 + n32] = db2[nt];
-                S.red[1][wave][nt * 32 + n32] = db1[nt];
-            }
-        }
-        __syncthreads();
-        if (threadIdx.x < kFlowHidden) {
-            float s2 = 0.f, s1 = 0.f;
-            for (int w = 0; w < kFlowWaves; ++w) {
-                s2 += S.red[0][w][threadIdx.x];
-                s1 += S.red[1][w][threadIdx.x];
-            }
-            out[kFB2 + threadIdx.x] = s2;
-            out[kFB1 + threadIdx.x] = s1;
-        }
-        // S.red and the activations are reused by the next layer
-        __syncthreads();
+    const float* g_in = gbuf[L & 1];
+    float* g_out = gbuf[(L & 1) ^ 1];
+    // this layer's operands and biases into LDS (the previous layer's
+    // reduction is done with them)
+    {
+        const bf16x8* pk = reinterpret_cast<const bf16x8*>(a.packed) + (size_t)L * kPLayer;
+        for (int e = threadIdx.x; e < kPLayer; e += kFlowThreads) S.w[e] = pk[e];
+        const float* P = a.theta + (size_t)L * kFLayer;
+        for (int e = threadIdx.x; e < 2 * kFlowHidden + kFlowOut; e += kFlowThreads)
+            S.b[e] = P[e < kFlowHidden ? kFB1 + e : e < 2 * kFlowHidden ? kFB2 + (e - kFlowHidden)
+                                                                          : kFB3 + (e - 2 * kFlowHidden)];
     }
+    __syncthreads();
+    // the layer's input in the inverse direction, u_{l+1}: z_4 itself for
+    // the last layer (at the training samples), else the inverse pass's
+    // compact output
+    constexpr bool from_z = L == kFlowLayers - 1;
+    const float* uin = from_z ? a.zf : a.U + (size_t)L * N * kFlowDim;
+    LayerGrad G;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        G.w3[t] = {};
+        G.w1[t] = {};
+        G.w2[t][0] = {};
+        G.w2[t][1] = {};
+        G.b2[t] = 0.f;
+        G.b1[t] = 0.f;
+    }
+    G.b3 = 0.f;
+    const uint32_t chunks = (N + 31u) / 32u;
+    const uint32_t n_waves = gridDim.x * kFlowWaves;
+    // waves run independently: no barrier inside the loop.  A sample's
+    // dL/du is written and read again by the same lane, as every layer maps
+    // chunks to waves alike.
+    for (uint32_t chunk = blockIdx.x * kFlowWaves + wave; chunk < chunks; chunk += n_waves) {
+        const uint32_t k = min(chunk * 32u + (uint32_t)n32, N - 1u);
+        const bool valid = chunk * 32u + (uint32_t)n32 < N;
+        float u[8], g[8];
+        load8(uin + (from_z ? (size_t)a.off + (size_t)k * a.stride : (size_t)k) * kFlowDim + 8 * half, u);
+        if (valid) {
+            load8(g_in + (size_t)k * kFlowDim + 8 * half, g);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) g[j] = 0.f;
+        }
+        const float coef = train_coef(a, k, valid);
+        grad_chunk<L>(u, g, coef, S.w, S.b, G);
+        if (valid) store8(g_out + (size_t)k * kFlowDim + 8 * half, g);
+    }
+    grad_to_lds<L>(G, S.red[wave]);
+    __syncthreads();
+    float* out = a.part + (size_t)blockIdx.x * kFParams + (size_t)L * kFLayer;
+    for (int i = threadIdx.x; i < kFLayer; i += kFlowThreads) {
+        float s = 0.f;
+#pragma unroll
+        for (int w = 0; w < kFlowWaves; ++w) s += S.red[w][i];
+        out[i] = s;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kFlowThreads) void k_flow_grad(FlowTrainArgs a)
+{
+    __shared__ FlowBwdLds S;
+    // dL/du_l passes between the layers through two buffers: the inverse
+    // pass left dL/du_0 in g_in
+    float* const gbuf[2] = {const_cast<float*>(a.g_in), a.g_out};
+    grad_layer<0>(a, S, gbuf);
+    grad_layer<1>(a, S, gbuf);
+    grad_layer<2>(a, S, gbuf);
+    grad_layer<3>(a, S, gbuf);
 }
 
 // per-workgroup gradients summed in a fixed order: segments of consecutive

@@ -259,7 +259,8 @@ def test_fixed_warp_unbiased():
 
 def test_flow_grad_parity():
     """GPU gradient of the warp's loss against the oracle with BF16
-    emulation, per layer (relative L2)."""
+    emulation, per layer: relative L2 below 1e-4 (measured 3e-7 to 9e-7;
+    FP32 arithmetic against FP64, with the same BF16 operands)."""
     w = corr16()
     say("[flow grad]")
     v = make(w)
@@ -277,7 +278,7 @@ def test_flow_grad_parity():
         a, b = g_gpu[l * n:(l + 1) * n], g_orc[l * n:(l + 1) * n]
         rel = np.linalg.norm(a - b) / np.linalg.norm(b)
         say(f"  layer {l}: |g| {np.linalg.norm(b):.3e} rel L2 {rel:.2e}")
-        assert rel < 2e-2
+        assert rel < 1e-4
     v.close()
 
 
