@@ -841,7 +841,7 @@ def main():
     ap.add_argument("--flow-lr", type=float, default=2e-3, help="warp comparison: Adam step during the warm-up")
     ap.add_argument("--flow-steps", type=int, default=16, help="warp comparison: Adam steps per warm-up iteration")
     ap.add_argument("--flow-lr-final", type=float, default=1e-3, help="warp comparison: Adam step afterwards")
-    ap.add_argument("--flow-steps-final", type=int, default=8,
+    ap.add_argument("--flow-steps-final", type=int, default=12,
                     help="warp comparison: Adam steps per combined iteration")
     ap.add_argument("--train-stride", type=int, default=32,
                     help="warp comparison: a training step uses every n-th sample of the iteration")
