@@ -1427,7 +1427,7 @@ vegas_status flow_judge(vegas_ctx* c, int t, bool* keep)
     return VEGAS_OK;
 }
 
-// one training step: gradient, Adam, BF16 repack
+// one training step: gradient, Adam and the BF16 repack
 vegas_status flow_train_step(vegas_ctx* c)
 {
     // a strided subset of the samples, its offset turning with the steps
@@ -1437,12 +1437,12 @@ vegas_status flow_train_step(vegas_ctx* c)
     adam.theta = th;
     adam.m = reinterpret_cast<float*>(c->fws + c->f_m);
     adam.v = reinterpret_cast<float*>(c->fws + c->f_v);
+    adam.packed = c->fws + c->f_packed;
     adam.lr = c->fcfg.lr;
     adam.step = (int)(c->f_step + 1);
     vegas_status s = flow_gradient(c, stride, (uint32_t)(c->f_step % stride), &adam);
     if (s != VEGAS_OK) return s;
     c->f_step += 1;
-    HIPCHK(launch_flow_pack(th, c->fws + c->f_packed, c->stream));
     return VEGAS_OK;
 }
 

@@ -148,9 +148,10 @@ struct FlowTrainArgs {
 // Adam step fused into the gradient's last reduction (training), or none
 // (the gradient alone)
 struct FlowAdamArgs {
-    float* theta;
+    float* theta;                 // null: the gradient alone
     float* m;
     float* v;
+    void* packed;                 // repacked BF16 operands
     float lr;
     int step;                     // counts from 1
 };

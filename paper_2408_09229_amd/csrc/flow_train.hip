@@ -9,7 +9,8 @@
 // u_4 = z_4 -> u_3 -> u_2 -> u_1 -> u_0, where log J_F depends on the
 // parameters through each layer's log-scales and through u_0 (the term
 // u_0^2 / 2):
-//   k_flow_sumsq    sum of |omega|^gamma (block partials, then in order)
+//   k_flow_sumsq    sum of |omega|^gamma (block partials; the inverse pass
+//                   adds them in order)
 //   k_flow_inverse  u_3, u_2, u_1 of every training sample (MLP on MFMA) and
 //                   the upstream gradient dL/du_0 = c u_0
 //   k_flow_grad     the coupling layers l = 0..3 in turn: from g = dL/du_l,
@@ -18,8 +19,9 @@
 //                   dW = sum_samples delta^T activation run on MFMA with
 //                   every activation and delta in registers, each wave
 //                   summing its samples, the waves added in LDS
-//   k_flow_reduce   per-workgroup gradients summed in a fixed order, and
-//                   Adam on the FP32 parameters (then the BF16 repack)
+//   k_flow_reduce_seg, k_flow_update  per-workgroup gradients summed in a
+//                   fixed order, Adam on the FP32 parameters and their BF16
+//                   repacking
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -54,18 +56,6 @@ __global__ __launch_bounds__(kSumThreads) void k_flow_sumsq(const float* om, uin
     if (threadIdx.x == 0) part[1 + blockIdx.x] = red[0];
 }
 
-__global__ __launch_bounds__(kSumThreads) void k_flow_sumsq_final(double* part)
-{
-    __shared__ double red[kSumThreads];
-    red[threadIdx.x] = threadIdx.x < kSumBlocks ? part[1 + threadIdx.x] : 0.0;
-    __syncthreads();
-    for (int w = kSumThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[0] = red[0];
-}
-
 // ---------------------------------------------------------------------------
 // inverse pass
 // ---------------------------------------------------------------------------
@@ -85,9 +75,8 @@ __device__ __forceinline__ void store8(float* p, const float (&v)[8])
 
 // c_k of a training sample in double, rounded to FP32: tiny weights (an
 // integrand that underflows almost everywhere) put 1/sum beyond FP32
-__device__ __forceinline__ float train_coef(const FlowTrainArgs& a, uint32_t k, bool valid)
+__device__ __forceinline__ float train_coef(const FlowTrainArgs& a, uint32_t k, bool valid, double ss)
 {
-    const double ss = *a.sumsq;
     const double inv_ss = ss > 0.0 && ss < INFINITY ? 1.0 / ss : 0.0;
     const double om = valid ? fabs((double)a.om[(size_t)a.off + (size_t)k * a.stride]) : 0.0;
     return (float)((a.gamma == 2 ? om * om : om) * inv_ss);
@@ -96,8 +85,18 @@ __device__ __forceinline__ float train_coef(const FlowTrainArgs& a, uint32_t k, 
 __global__ __launch_bounds__(kFlowSampleThreads) void k_flow_inverse(FlowTrainArgs a)
 {
     __shared__ FlowFwdLds S;
+    __shared__ double red[kSumThreads];
     flow_stage_fwd(S, reinterpret_cast<const bf16x8*>(a.packed), a.theta);
+    // the total of the sums' block partials, by every workgroup in the same
+    // order (workgroup 0 keeps it for the backward pass)
+    if (threadIdx.x < kSumThreads) red[threadIdx.x] = threadIdx.x < kSumBlocks ? a.sumsq[1 + threadIdx.x] : 0.0;
     __syncthreads();
+    for (int w = kSumThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double ss = red[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) const_cast<double*>(a.sumsq)[0] = ss;
     const int lane = threadIdx.x & 63;
     const int half = lane >> 5;
     const int n32 = lane & 31;
@@ -121,7 +120,7 @@ __global__ __launch_bounds__(kFlowSampleThreads) void k_flow_inverse(FlowTrainAr
         flow_layer_inv<0>(z, S);
         // dL/du_0 = c u_0 (the term u_0^2 / 2 of log J_F)
         if (valid) {
-            const float c = train_coef(a, k, true);
+            const float c = train_coef(a, k, true, ss);
             float g[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) g[j] = c * z[j];
@@ -438,7 +437,7 @@ __device__ void grad_layer(const FlowTrainArgs& a, FlowBwdLds& S, float* const (
 #pragma unroll
             for (int j = 0; j < 8; ++j) g[j] = 0.f;
         }
-        const float coef = train_coef(a, k, valid);
+        const float coef = train_coef(a, k, valid, *a.sumsq);
         grad_chunk<L>(u, g, coef, S.w, S.b, G);
         if (valid) store8(g_out + (size_t)k * kFlowDim + 8 * half, g);
     }
@@ -483,33 +482,46 @@ __global__ void k_flow_reduce_seg(const float* part, int n_wg, float* seg)
     seg[(size_t)blockIdx.y * kFParams + i] = s;
 }
 
-__device__ __forceinline__ void adam_update(float* theta, float* m, float* v, int i, float gi, float lr, float c1,
-                                            float c2)
+__device__ __forceinline__ float adam_update(float* theta, float* m, float* v, int i, float gi, float lr, float c1,
+                                             float c2)
 {
     const float mi = fmaf(0.9f, m[i], 0.1f * gi);
     const float vi = fmaf(0.999f, v[i], 0.001f * gi * gi);
     m[i] = mi;
     v[i] = vi;
-    theta[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
+    const float t = theta[i] - lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
+    theta[i] = t;
+    return t;
 }
 
-// the segments in order into grad; with theta set, the Adam step too
-__global__ void k_flow_reduce(const float* seg, float* grad, float* theta, float* m, float* v, float lr, float c1,
-                              float c2)
+// One workgroup per layer: the segments in order into grad; with adam set,
+// the Adam step on the layer's parameters and their BF16 repacking (from a
+// copy of the new parameters in LDS).
+constexpr int kUpdThreads = 1024;
+
+__global__ __launch_bounds__(kUpdThreads) void k_flow_update(const float* seg, float* grad, FlowAdamArgs adam,
+                                                             float c1, float c2)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= kFParams) return;
-    float s = 0.f;
-    for (int g = 0; g < kRedSegs; ++g) s += seg[(size_t)g * kFParams + i];
-    grad[i] = s;
-    if (theta) adam_update(theta, m, v, i, s, lr, c1, c2);
+    __shared__ float P[kFLayer];
+    const int l = blockIdx.x;
+    for (int i = threadIdx.x; i < kFLayer; i += kUpdThreads) {
+        const int gi = l * kFLayer + i;
+        float s = 0.f;
+        for (int g = 0; g < kRedSegs; ++g) s += seg[(size_t)g * kFParams + gi];
+        grad[gi] = s;
+        if (adam.theta) P[i] = adam_update(adam.theta, adam.m, adam.v, gi, s, adam.lr, c1, c2);
+    }
+    if (!adam.theta) return;
+    __syncthreads();
+    bf16x8* pk = reinterpret_cast<bf16x8*>(adam.packed) + (size_t)l * kPLayer;
+    for (int r = threadIdx.x; r < kPLayer; r += kUpdThreads) pk[r] = flow_pack_entry(l, r, P);
 }
 
 __global__ void k_flow_adam(float* theta, const float* grad, float* m, float* v, float lr, float c1, float c2)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kFParams) return;
-    adam_update(theta, m, v, i, grad[i], lr, c1, c2);
+    (void)adam_update(theta, m, v, i, grad[i], lr, c1, c2);
 }
 
 // ---------------------------------------------------------------------------
@@ -531,9 +543,9 @@ hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, 
     double* ss = const_cast<double*>(base.sumsq);
     hipLaunchKernelGGL(k_flow_sumsq, dim3(kSumBlocks), dim3(kSumThreads), 0, st, base.om, base.n, base.stride,
                        base.off, base.gamma, ss);
-    hipLaunchKernelGGL(k_flow_sumsq_final, dim3(1), dim3(kSumThreads), 0, st, ss);
-    // the inverse pass writes u_1..u_3 and dL/du_0 (into G1); then every
-    // layer's backward pass in one launch, alternating G1 and G0
+    // the inverse pass totals those sums, writes u_1..u_3 and dL/du_0 (into
+    // G1); then every layer's backward pass in one launch, alternating G1
+    // and G0
     FlowTrainArgs a = base;
     a.g_in = G1;
     a.g_out = G1;
@@ -542,11 +554,11 @@ hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, 
     hipLaunchKernelGGL(k_flow_grad, dim3(n_wg), dim3(kFlowThreads), 0, st, a);
     hipLaunchKernelGGL(k_flow_reduce_seg, dim3((kFParams + 255) / 256, kRedSegs), dim3(256), 0, st,
                        (const float*)a.part, n_wg, seg);
+    FlowAdamArgs none = {};
     float c1 = 0.f, c2 = 0.f;
     if (adam) adam_corrections(adam->step, &c1, &c2);
-    hipLaunchKernelGGL(k_flow_reduce, dim3((kFParams + 255) / 256), dim3(256), 0, st, (const float*)seg, grad,
-                       adam ? adam->theta : nullptr, adam ? adam->m : nullptr, adam ? adam->v : nullptr,
-                       adam ? adam->lr : 0.f, c1, c2);
+    hipLaunchKernelGGL(k_flow_update, dim3(kFlowLayers), dim3(kUpdThreads), 0, st, (const float*)seg, grad,
+                       adam ? *adam : none, c1, c2);
     return hipGetLastError();
 }
 
