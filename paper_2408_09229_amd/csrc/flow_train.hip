@@ -494,27 +494,47 @@ __device__ __forceinline__ float adam_update(float* theta, float* m, float* v, i
     return t;
 }
 
-// One workgroup per layer: the segments in order into grad; with adam set,
-// the Adam step on the layer's parameters and their BF16 repacking (from a
-// copy of the new parameters in LDS).
-constexpr int kUpdThreads = 1024;
+// The segments in order into grad, one thread per parameter; with adam
+// set, the Adam step on it too.  The workgroup that finishes last with a
+// layer (a counter per layer, after a device-scope fence) repacks that
+// layer's BF16 operands and clears the counter for the next launch.
+constexpr int kUpdThreads = 256;
+constexpr int kUpdBlocks = (kFParams + kUpdThreads - 1) / kUpdThreads;
 
 __global__ __launch_bounds__(kUpdThreads) void k_flow_update(const float* seg, float* grad, FlowAdamArgs adam,
                                                              float c1, float c2)
 {
-    __shared__ float P[kFLayer];
-    const int l = blockIdx.x;
-    for (int i = threadIdx.x; i < kFLayer; i += kUpdThreads) {
-        const int gi = l * kFLayer + i;
+    __shared__ uint32_t last[2];
+    const int i = blockIdx.x * kUpdThreads + threadIdx.x;
+    if (i < kFParams) {
         float s = 0.f;
-        for (int g = 0; g < kRedSegs; ++g) s += seg[(size_t)g * kFParams + gi];
-        grad[gi] = s;
-        if (adam.theta) P[i] = adam_update(adam.theta, adam.m, adam.v, gi, s, adam.lr, c1, c2);
+        for (int g = 0; g < kRedSegs; ++g) s += seg[(size_t)g * kFParams + i];
+        grad[i] = s;
+        if (adam.theta) (void)adam_update(adam.theta, adam.m, adam.v, i, s, adam.lr, c1, c2);
     }
     if (!adam.theta) return;
+    // layers this workgroup's parameters belong to, and how many
+    // workgroups hold parameters of each
+    const int i0 = blockIdx.x * kUpdThreads;
+    const int i1 = min(i0 + kUpdThreads, kFParams) - 1;
+    const int l0 = i0 / kFLayer, l1 = i1 / kFLayer;
+    __threadfence();
     __syncthreads();
-    bf16x8* pk = reinterpret_cast<bf16x8*>(adam.packed) + (size_t)l * kPLayer;
-    for (int r = threadIdx.x; r < kPLayer; r += kUpdThreads) pk[r] = flow_pack_entry(l, r, P);
+    if (threadIdx.x == 0) {
+        for (int l = l0; l <= l1; ++l) {
+            const int n_blk = ((l + 1) * kFLayer - 1) / kUpdThreads - (l * kFLayer) / kUpdThreads + 1;
+            last[l - l0] = atomicAdd(adam.done + l, 1u) + 1u == (uint32_t)n_blk ? 1u : 0u;
+        }
+    }
+    __syncthreads();
+    for (int l = l0; l <= l1; ++l) {
+        if (!last[l - l0]) continue;
+        __threadfence();
+        const float* P = adam.theta + (size_t)l * kFLayer;
+        bf16x8* pk = reinterpret_cast<bf16x8*>(adam.packed) + (size_t)l * kPLayer;
+        for (int r = threadIdx.x; r < kPLayer; r += kUpdThreads) pk[r] = flow_pack_entry(l, r, P);
+        if (threadIdx.x == 0) adam.done[l] = 0u;
+    }
 }
 
 __global__ void k_flow_adam(float* theta, const float* grad, float* m, float* v, float lr, float c1, float c2)
@@ -557,7 +577,7 @@ hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, 
     FlowAdamArgs none = {};
     float c1 = 0.f, c2 = 0.f;
     if (adam) adam_corrections(adam->step, &c1, &c2);
-    hipLaunchKernelGGL(k_flow_update, dim3(kFlowLayers), dim3(kUpdThreads), 0, st, (const float*)seg, grad,
+    hipLaunchKernelGGL(k_flow_update, dim3(kUpdBlocks), dim3(kUpdThreads), 0, st, (const float*)seg, grad,
                        adam ? *adam : none, c1, c2);
     return hipGetLastError();
 }

@@ -362,3 +362,44 @@ def test_flow_cost_judge_switches_off():
     r = v.result()
     assert r.n_iter_combined == 16 - int(np.sum(kinds == 2))
     v.close()
+
+
+def test_flow_judge_on_side_stream():
+    """The judge reads each iteration's estimate on the host: on a side stream
+    (torch.cuda.Stream, which does not wait for the default stream) it must
+    read the finished values.  The same guarded, training run on the default
+    stream and on a side stream, the default stream busy with other work
+    meanwhile, keeps the same record and gives the same estimate up to the
+    histogram sums' rounding order.  Every tensor of the side-stream run is
+    allocated under that stream, and the busy work allocates nothing, so no
+    memory changes hands between the streams."""
+    import torch
+    from paper_2408_09229_amd import Vegas, make_config
+    w = corr16(n_eval=100_003, n_g=64)
+    say("[flow judge, side stream]")
+    busy_a = torch.randn(4096, 4096, device="cuda")
+    busy_b = torch.empty_like(busy_a)
+    torch.cuda.synchronize()
+    out = []
+    for side in (False, True):
+        st = torch.cuda.Stream() if side else torch.cuda.current_stream()
+        with torch.cuda.stream(st):
+            cfg = make_config(w.dim, w.n_g, w.n_eval, seed=w.seed, precision="f32")
+            v = Vegas(cfg, w.family, w.params, stream=st)
+            v.adapt(4)
+            v.attach_flow(None, lr=1e-3, train=True, loss="kl", judge="guard", steps_per_iter=4, train_stride=4)
+            v.enable_flow(True)
+            if side:
+                with torch.cuda.stream(torch.cuda.default_stream()):
+                    for _ in range(8):
+                        torch.matmul(busy_a, busy_a, out=busy_b)
+                        torch.matmul(busy_b, busy_b, out=busy_a)
+            v.integrate(10)
+            r = v.result()
+            out.append((v.flow_status(), r.integral, math.sqrt(r.sigma2)))
+            say(f"  side={side}: status {out[-1][0]} I {r.integral:.8f} +- {math.sqrt(r.sigma2):.2e}")
+            v.close()
+        torch.cuda.synchronize()
+    (s0, I0, e0), (s1, I1, e1) = out
+    assert s0 == s1 and s0[0]
+    assert abs(I0 - I1) <= 1e-6 * abs(I0) + 1e-3 * e0
