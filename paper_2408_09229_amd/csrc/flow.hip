@@ -122,6 +122,7 @@ __global__ __launch_bounds__(kFlowSampleThreads, 4) void k_flow_sample(FlowSampl
     const uint32_t chunks = (N + 31u) / 32u;
     const uint32_t n_waves = gridDim.x * kFlowSampleWaves;
     const double den = (double)sc.nst * 0x1p33;
+    const double inv_den = 1.0 / den;
     // waves run independently: no barrier inside the loop
     for (uint32_t chunk = blockIdx.x * kFlowSampleWaves + (threadIdx.x >> 6); chunk < chunks; chunk += n_waves) {
         const uint32_t k0 = chunk * 32u;
@@ -135,7 +136,8 @@ __global__ __launch_bounds__(kFlowSampleThreads, 4) void k_flow_sample(FlowSampl
         }
         // the stratified point y = (s 2^33 + 2r + 1) / (N_st 2^33) and
         // z_0 = Phi^-1(y): numerator and den - numerator are exact in FP64
-        // (s < 2^20), so min(y, 1 - y) is one FP64 division, rounded to FP32
+        // (s < 2^20), so min(y, 1 - y) is one FP64 product by 1/den (two
+        // roundings in FP64), rounded to FP32
         float z0[8], z[8];
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(kFlowSampleThreads, 4) void k_flow_sample(FlowSampl
                 const int j = 4 * b + q;
                 const double num = fma((double)dig[8 * half + j], 0x1p33, 2.0 * (double)o.v[q] + 1.0);
                 const bool upper = 2.0 * num > den;
-                const float m = (float)((upper ? den - num : num) / den);
+                const float m = (float)((upper ? den - num : num) * inv_den);
                 z0[j] = flow_phi_inv(m, upper);
                 z[j] = z0[j];
             }

@@ -20,8 +20,16 @@ __device__ __forceinline__ f32x16 mfma(const bf16x8& a, const bf16x8& b, const f
 // mrow(l, r), column l % 32
 __device__ __forceinline__ int mrow(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
-// log-scale of a moved axis from its raw conditioner output: s = S tanh(a/S)
-__device__ __forceinline__ float flow_scale(float a) { return kFlowSMax * tanhf(a * (1.f / kFlowSMax)); }
+// log-scale of a moved axis from its raw conditioner output:
+// s = S tanh(a/S) = S (1 - 2 / (e^{2a/S} + 1)), from the hardware exp2 and
+// reciprocal (a few ulps of S; exact 0 at a = 0, and +-S in the limits)
+__device__ __forceinline__ float flow_scale(float a)
+{
+    const float e = __builtin_amdgcn_exp2f(a * (2.f / kFlowSMax * 1.44269504088896341f));
+    return kFlowSMax * fmaf(-2.f, __builtin_amdgcn_rcpf(e + 1.f), 1.f);
+}
+// e^x for the log-scales, |x| <= S: the hardware exp2 of x log2 e
+__device__ __forceinline__ float flow_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
 
 // Gaussian distribution function and its inverse in FP32 (the device
 // library's erfc and erfcinv).  phi_inv takes min(y, 1 - y) separately, so
@@ -140,12 +148,38 @@ __device__ __forceinline__ void flow_stage_fwd(FlowFwdLds& S, const bf16x8* __re
 
 // the 8 values of register-order k-step q of a product's output (registers
 // 8 (q % 2) .. + 7 of tile q / 2), through relu, as a BF16 operand
+// 8 FP32 values to BF16 (round to nearest even), two per instruction
+__device__ __forceinline__ bf16x8 cvt_bf16x8(float v0, float v1, float v2, float v3, float v4, float v5, float v6,
+                                             float v7)
+{
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    const f32x2 a = {v0, v1}, b = {v2, v3}, c = {v4, v5}, d = {v6, v7};
+    const u32x4 w = {__builtin_bit_cast(unsigned, __builtin_convertvector(a, bf16x2)),
+                     __builtin_bit_cast(unsigned, __builtin_convertvector(b, bf16x2)),
+                     __builtin_bit_cast(unsigned, __builtin_convertvector(c, bf16x2)),
+                     __builtin_bit_cast(unsigned, __builtin_convertvector(d, bf16x2))};
+    return __builtin_bit_cast(bf16x8, w);
+}
+
+// registers 8 q2 .. + 7 of a product's output as BF16
+__device__ __forceinline__ bf16x8 to_bf16(const f32x16& acc, int q2)
+{
+    const int b = 8 * q2;
+    return cvt_bf16x8(acc[b], acc[b + 1], acc[b + 2], acc[b + 3], acc[b + 4], acc[b + 5], acc[b + 6], acc[b + 7]);
+}
+
 __device__ __forceinline__ bf16x8 relu_bf16(const f32x16& acc, int q2)
 {
-    bf16x8 o;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) o[i] = (__bf16)fmaxf(acc[8 * q2 + i], 0.f);
-    return o;
+    const bf16x8 o = to_bf16(acc, q2);
+    // relu on the rounded values' bit patterns, two per instruction: a BF16
+    // with its sign bit set is a negative 16-bit integer (-0 included), so
+    // max(v, 0) as integers maps it to +0 and keeps every positive value
+    typedef short s16x8 __attribute__((ext_vector_type(8)));
+    const s16x8 zero = {};
+    const s16x8 v = __builtin_elementwise_max(__builtin_bit_cast(s16x8, o), zero);
+    return __builtin_bit_cast(bf16x8, v);
 }
 
 // start of an accumulator with the bias of the product's rows: register
@@ -181,8 +215,10 @@ __device__ __forceinline__ f32x16 flow_mlp_t(const float (&z)[8], const bf16x8* 
     __asm__ volatile("" ::: "memory");
     const int lane = threadIdx.x & 63;
     const int half = lane >> 5;
+    float xs[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) x[j] = flow_in_a(L, 8 * half + j) ? (__bf16)(kFlowXScale * z[j]) : (__bf16)0.f;
+    for (int j = 0; j < 8; ++j) xs[j] = flow_in_a(L, 8 * half + j) ? kFlowXScale * z[j] : 0.f;
+    x = cvt_bf16x8(xs[0], xs[1], xs[2], xs[3], xs[4], xs[5], xs[6], xs[7]);
     // h1 = relu(W1 x + b1)
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
@@ -230,7 +266,7 @@ __device__ __forceinline__ void flow_layer_fwd(float (&z)[8], float& lj, const F
     for (int j = 0; j < 8; ++j) {
         if (flow_in_a(L, 8 * half + j)) continue;
         const float s = flow_scale(o[j]);
-        z[j] = fmaf(z[j], expf(s), o[8 + j]);
+        z[j] = fmaf(z[j], flow_exp(s), o[8 + j]);
         lj += s;
     }
 }
@@ -245,7 +281,7 @@ __device__ __forceinline__ void flow_layer_inv(float (&z)[8], const FlowFwdLds& 
     for (int j = 0; j < 8; ++j) {
         if (flow_in_a(L, 8 * half + j)) continue;
         const float s = flow_scale(o[j]);
-        z[j] = (z[j] - o[8 + j]) * expf(-s);
+        z[j] = (z[j] - o[8 + j]) * flow_exp(-s);
     }
 }
 

@@ -148,15 +148,6 @@ struct __align__(16) FlowBwdLds {
     float red[kFlowWaves][kFLayer];            // per-wave gradients of the layer
 };
 
-// the 8 registers of k-step q2 (registers 8 q2 .. + 7) as BF16
-__device__ __forceinline__ bf16x8 to_bf16(const f32x16& acc, int q2)
-{
-    bf16x8 o;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) o[i] = (__bf16)acc[8 * q2 + i];
-    return o;
-}
-
 // sum of a lane's 16 registers
 __device__ __forceinline__ float reg_sum(const f32x16& a)
 {
@@ -209,7 +200,7 @@ __device__ __forceinline__ void grad_chunk(const float (&u)[8], float (&g)[8], f
         gn[j] = g[j];
         if (flow_in_a(L, 8 * half + j)) continue;
         const float s = flow_scale(o[j]);
-        const float es = expf(-s);
+        const float es = flow_exp(-s);
         const float ub = (u[j] - o[8 + j]) * es;
         const float ds = coef - g[j] * ub;
         const float rs = s * (1.f / kFlowSMax);
@@ -282,9 +273,10 @@ __device__ __forceinline__ void grad_chunk(const float (&u)[8], float (&g)[8], f
         f32x16 acc = {}, rem = {};
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-            bf16x8 lo;
+            float r[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) lo[i] = (__bf16)(dO[8 * ks + i] - (float)dOb[ks][i]);
+            for (int i = 0; i < 8; ++i) r[i] = dO[8 * ks + i] - (float)dOb[ks][i];
+            const bf16x8 lo = cvt_bf16x8(r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7]);
             acc = mfma(dOb[ks], W[kPP + ks * 64 + lane], acc);
             rem = mfma(lo, W[kPP + ks * 64 + lane], rem);
         }
