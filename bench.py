@@ -78,31 +78,36 @@ WORKLOADS = {
 
 
 FILL_SOURCES = ["fill.hip", "fill_dev.hpp", "batch.hip", "sample.hpp", "common.hpp", "families.hpp", "layout.hpp"]
+FLOW_SOURCES = ["flow.hip", "flow.hpp", "flow_dev.hpp", "common.hpp", "fill_dev.hpp", "layout.hpp"]
 
 
-def fill_source_hash() -> str:
-    """Hash of the fill kernel's sources: a profiled HBM figure is reported
-    only while it still describes the kernel being timed."""
+def source_hash(files=FILL_SOURCES) -> str:
+    """Hash of a kernel's sources: a profiled HBM figure is reported only
+    while it still describes the kernel being timed."""
     import hashlib
     h = hashlib.sha256()
-    for f in FILL_SOURCES:
+    for f in files:
         h.update(open(os.path.join(ROOT, "paper_2408_09229_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(workload: str):
-    """HBM bytes per fill launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary in profiles/ (scaled by a device copy of known size), or None
-    when there is none or the kernel changed since it was taken."""
+def fill_source_hash() -> str:
+    return source_hash(FILL_SOURCES)
+
+
+def profiled_traffic(workload: str, kernel: str = "k_fill", files=FILL_SOURCES):
+    """HBM bytes per launch of a kernel from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary in profiles/ (scaled by a device copy of known size),
+    or None when there is none or the kernel changed since it was taken."""
     import re
-    path = os.path.join(ROOT, "profiles", f"k_fill_{workload}.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
     if not os.path.exists(path):
         return None
     m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
     if not m:
         return None
     rec = json.loads(m.group(1))
-    return rec.get("traffic_bytes") if rec.get("source_hash") == fill_source_hash() else None
+    return rec.get("traffic_bytes") if rec.get("source_hash") == source_hash(files) else None
 
 
 def host_info():
@@ -517,7 +522,8 @@ def run_warp_compare(args, w):
         "timed_iterations": {"warped": int((kinds == 1).sum()), "control": int((kinds == 2).sum()),
                              "plain": int((kinds == 0).sum())},
         "roofline": {"bound": "mfma", "achieved": ach / 1e12 if ach else None, "peak": 2500.0, "unit": "TFLOP/s",
-                     "frac": ach / 2.5e15 if ach else None, "traffic": None, "kernel": dom,
+                     "frac": ach / 2.5e15 if ach else None,
+                     "traffic": profiled_traffic(w.name, "k_flow", FLOW_SOURCES), "kernel": dom,
                      "kernel_ms": dom_ms, "flops_per_launch": flops,
                      "phases": {k: {"ms": m, "tflops": (f / (m / 1e3) / 1e12) if m else None,
                                     "frac": (f / (m / 1e3) / 2.5e15) if m else None}

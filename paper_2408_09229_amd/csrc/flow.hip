@@ -127,25 +127,37 @@ __global__ __launch_bounds__(kFlowSampleThreads, 4) void k_flow_sample(FlowSampl
     for (uint32_t chunk = blockIdx.x * kFlowSampleWaves + (threadIdx.x >> 6); chunk < chunks; chunk += n_waves) {
         const uint32_t k0 = chunk * 32u;
         const uint32_t k = min(k0 + (uint32_t)n32, N - 1u);
-        uint32_t hc = flow_cube(a.start, sc.n_cubes, k0, k, lane), dig[kFlowDim];
+        // the stratum digits of the lane's axes: axis d sits in register
+        // 4 (d / 8) + d % 4 of half (d / 4) % 2 (written per register, as an
+        // index into all 16 digits that depends on the lane would be a
+        // 16-way select chain)
+        uint32_t hc = flow_cube(a.start, sc.n_cubes, k0, k, lane), dig[8];
 #pragma unroll
         for (int d = 0; d < kFlowDim; ++d) {
             const uint32_t q = div_magic(hc, sc.nst_magic, sc.nst_shift);
-            dig[d] = hc - q * sc.nst;
+            const uint32_t digit = hc - q * sc.nst;
             hc = q;
+            const int j = 4 * (d >> 3) + (d & 3);
+            if ((d >> 2) & 1) {
+                if (half) dig[j] = digit;
+            } else {
+                dig[j] = digit;
+            }
         }
         // the stratified point y = (s 2^33 + 2r + 1) / (N_st 2^33) and
         // z_0 = Phi^-1(y): numerator and den - numerator are exact in FP64
         // (s < 2^20), so min(y, 1 - y) is one FP64 product by 1/den (two
-        // roundings in FP64), rounded to FP32
+        // roundings in FP64), rounded to FP32.  Axis c takes word c % 4 of
+        // counter c / 4; register block b of this lane's half holds axes
+        // 8 b + 4 half + q, counter 2 b + half.
         float z0[8], z[8];
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            const W4 o = philox10(k, 0u, a.t, sc.ctr3 | (uint32_t)(2 * half + b), keys);
+            const W4 o = philox10(k, 0u, a.t, sc.ctr3 | (uint32_t)(2 * b + half), keys);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int j = 4 * b + q;
-                const double num = fma((double)dig[8 * half + j], 0x1p33, 2.0 * (double)o.v[q] + 1.0);
+                const double num = fma((double)dig[j], 0x1p33, 2.0 * (double)o.v[q] + 1.0);
                 const bool upper = 2.0 * num > den;
                 const float m = (float)((upper ? den - num : num) * inv_den);
                 z0[j] = flow_phi_inv(m, upper);
@@ -165,12 +177,8 @@ __global__ __launch_bounds__(kFlowSampleThreads, 4) void k_flow_sample(FlowSampl
         }
         lj += __shfl_xor(lj, 32, 64);
         if (k0 + (uint32_t)n32 < N) {
-            float4* wo = reinterpret_cast<float4*>(a.w + (size_t)k * kFlowDim + 8 * half);
-            wo[0] = make_float4(wv[0], wv[1], wv[2], wv[3]);
-            wo[1] = make_float4(wv[4], wv[5], wv[6], wv[7]);
-            float4* zo = reinterpret_cast<float4*>(a.z + (size_t)k * kFlowDim + 8 * half);
-            zo[0] = make_float4(z[0], z[1], z[2], z[3]);
-            zo[1] = make_float4(z[4], z[5], z[6], z[7]);
+            flow_lane_store(a.w + (size_t)k * kFlowDim, half, wv);
+            flow_lane_store(a.z + (size_t)k * kFlowDim, half, z);
             if (half == 0) a.lj[k] = lj;
         }
     }

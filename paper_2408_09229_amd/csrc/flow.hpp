@@ -77,23 +77,44 @@ __host__ __device__ inline int flow_t_unit(int ks, int h, int i)
 }
 
 // axis c is conditioning (in A) in layer l
-__host__ __device__ inline bool flow_in_a(int l, int c)
+__host__ __device__ constexpr bool flow_in_a(int l, int c)
 {
     return l == 0 ? c < 8 : l == 1 ? c >= 8 : l == 2 ? (c & 1) == 0 : (c & 1) == 1;
 }
 // position of axis c inside its set (A or B) of layer l
-__host__ __device__ inline int flow_pos(int l, int c) { return l < 2 ? (c & 7) : (c >> 1); }
+__host__ __device__ constexpr int flow_pos(int l, int c) { return l < 2 ? (c & 7) : (c >> 1); }
+
+// A sample's 16 axes are held by two lanes, 8 in registers each: register j
+// of the lanes of half h holds axis 8 (j/4) + 4 h + j % 4 (h = 0: axes 0-3
+// and 8-11; h = 1: axes 4-7 and 12-15).  Both halves then hold two axes of
+// each class (c < 8 or not, c even or odd) at the same registers, so in
+// every layer the moved axes sit at the same 4 registers of every lane, and
+// the conditioner's per-axis work is the same for the whole wave.  Axis
+// m < 16 is also the row that register j of half h holds in a product's
+// output (8 (r/4) + 4 h + r % 4).
+__host__ __device__ constexpr int flow_axis(int h, int j) { return 8 * (j >> 2) + 4 * h + (j & 3); }
+// register j holds a conditioning axis of layer l, in both halves
+__host__ __device__ constexpr bool flow_reg_in_a(int l, int j) { return flow_in_a(l, flow_axis(0, j)); }
+
+constexpr bool flow_axis_layout_ok()
+{
+    for (int l = 0; l < 4; ++l)
+        for (int j = 0; j < 8; ++j)
+            if (flow_in_a(l, flow_axis(0, j)) != flow_in_a(l, flow_axis(1, j))) return false;
+    return true;
+}
+static_assert(flow_axis_layout_ok(), "both lane halves move the same registers in every layer");
 
 // Conditioner output carried by row m of the transposed last product of
 // layer l, or -1 for a zero row.  Row m lands in register r = 4 (m/8) + m % 4
-// of the lanes of half (m/4) % 2, which hold axes 8 half + j of their sample:
-// register j < 8 gets the raw log-scale of axis 8 half + j, register 8 + j
-// its shift, where that axis moves in layer l.
+// of the lanes of half (m/4) % 2: register j < 8 gets the raw log-scale of
+// the lane's axis flow_axis(half, j), register 8 + j its shift, where that
+// axis moves in layer l.
 __host__ __device__ inline int flow_t3_row(int l, int m)
 {
     const int half = (m >> 2) & 1;
     const int r = 4 * (m >> 3) + (m & 3);
-    const int c = 8 * half + (r & 7);
+    const int c = flow_axis(half, r & 7);
     if (flow_in_a(l, c)) return -1;
     return (r < 8 ? 0 : kFlowHalf) + flow_pos(l, c);
 }
@@ -101,14 +122,28 @@ __host__ __device__ inline int flow_t3_row(int l, int m)
 // Conditioning axis (its position in A) carried by row m of the transposed
 // input-gradient product dX^T = W1^T dA1^T of layer l, or -1: row m lands in
 // register j = 4 (m/8) + m % 4 < 8 of the lanes of half (m/4) % 2, the
-// lane's own axis 8 half + j.
+// lane's own axis flow_axis(half, j).
 __host__ __device__ inline int flow_dx_row(int l, int m)
 {
     const int half = (m >> 2) & 1;
     const int r = 4 * (m >> 3) + (m & 3);
-    const int c = 8 * half + (r & 7);
+    const int c = flow_axis(half, r & 7);
     if (r >= 8 || !flow_in_a(l, c)) return -1;
     return flow_pos(l, c);
+}
+
+// the lane's 8 axes of a sample's 16 values (row: the sample's first value)
+__host__ __device__ inline void flow_lane_load(const float* row, int half, float (&v)[8])
+{
+    const float4 a = *reinterpret_cast<const float4*>(row + 4 * half);
+    const float4 b = *reinterpret_cast<const float4*>(row + 8 + 4 * half);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+__host__ __device__ inline void flow_lane_store(float* row, int half, const float (&v)[8])
+{
+    *reinterpret_cast<float4*>(row + 4 * half) = make_float4(v[0], v[1], v[2], v[3]);
+    *reinterpret_cast<float4*>(row + 8 + 4 * half) = make_float4(v[4], v[5], v[6], v[7]);
 }
 
 struct FlowSampleArgs {

@@ -98,10 +98,10 @@ __device__ inline bf16x8 flow_pack_entry(int l, int r, const float* __restrict__
     const int h = lane >> 5;              // k half of this lane
     const int n32 = lane & 31;            // its row (A operand) or column (B operand)
     float v[8];
-    if (r < kPT2) {                       // F1[mt]: W1[unit][pos(axis 8h + j)], axes in A
+    if (r < kPT2) {                       // F1[mt]: W1[unit][pos(axis of (h, j))], axes in A
         const int m = (r >> 6) * 32 + n32;
         for (int j = 0; j < 8; ++j) {
-            const int c = 8 * h + j;
+            const int c = flow_axis(h, j);
             v[j] = flow_in_a(l, c) ? W1[m * kFlowHalf + flow_pos(l, c)] : 0.f;
         }
     } else if (r < kPT3) {                // T2[mt][ks]: W2[unit2][unit1(ks, k)]
@@ -133,8 +133,8 @@ __device__ inline bf16x8 flow_pack_entry(int l, int r, const float* __restrict__
         r -= kPP;
         const int ks = r >> 6;
         for (int j = 0; j < 8; ++j) v[j] = flow_t3_row(l, flow_t_unit(ks, h, j)) == n32 ? 1.f : 0.f;
-    } else {                              // I: 1 where axis 8h + j is column n
-        for (int j = 0; j < 8; ++j) v[j] = 8 * h + j == n32 ? 1.f : 0.f;
+    } else {                              // I: 1 where the axis of (h, j) is column n
+        for (int j = 0; j < 8; ++j) v[j] = flow_axis(h, j) == n32 ? 1.f : 0.f;
     }
     bf16x8 o;
     for (int j = 0; j < 8; ++j) o[j] = (__bf16)v[j];
@@ -254,7 +254,7 @@ __device__ __forceinline__ f32x16 flow_mlp_t(const float (&z)[8], const bf16x8* 
     const int half = lane >> 5;
     float xs[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) xs[j] = flow_in_a(L, 8 * half + j) ? kFlowXScale * z[j] : 0.f;
+    for (int j = 0; j < 8; ++j) xs[j] = flow_reg_in_a(L, j) ? kFlowXScale * z[j] : 0.f;
     x = cvt_bf16x8(xs[0], xs[1], xs[2], xs[3], xs[4], xs[5], xs[6], xs[7]);
     // h1 = relu(W1 x + b1)
 #pragma unroll
@@ -298,10 +298,9 @@ template <int L>
 __device__ __forceinline__ void flow_layer_fwd(float (&z)[8], float& lj, const FlowFwdLds& S)
 {
     const f32x16 o = flow_mlp_t<L>(z, S);
-    const int half = (threadIdx.x >> 5) & 1;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        if (flow_in_a(L, 8 * half + j)) continue;
+        if (flow_reg_in_a(L, j)) continue;
         const float s = flow_scale(o[j]);
         z[j] = fmaf(z[j], flow_exp(s), o[8 + j]);
         lj += s;
@@ -313,10 +312,9 @@ template <int L>
 __device__ __forceinline__ void flow_layer_inv(float (&z)[8], const FlowFwdLds& S)
 {
     const f32x16 o = flow_mlp_t<L>(z, S);
-    const int half = (threadIdx.x >> 5) & 1;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        if (flow_in_a(L, 8 * half + j)) continue;
+        if (flow_reg_in_a(L, j)) continue;
         const float s = flow_scale(o[j]);
         z[j] = (z[j] - o[8 + j]) * flow_exp(-s);
     }

@@ -59,20 +59,6 @@ __global__ __launch_bounds__(kSumThreads) void k_flow_sumsq(const float* om, uin
 // ---------------------------------------------------------------------------
 // inverse pass
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void load8(const float* p, float (&v)[8])
-{
-    const float4* q = reinterpret_cast<const float4*>(p);
-    const float4 a = q[0], b = q[1];
-    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-}
-__device__ __forceinline__ void store8(float* p, const float (&v)[8])
-{
-    float4* q = reinterpret_cast<float4*>(p);
-    q[0] = make_float4(v[0], v[1], v[2], v[3]);
-    q[1] = make_float4(v[4], v[5], v[6], v[7]);
-}
-
 // c_k of a training sample in double, rounded to FP32: tiny weights (an
 // integrand that underflows almost everywhere) put 1/sum beyond FP32
 __device__ __forceinline__ float train_coef(const FlowTrainArgs& a, uint32_t k, bool valid, double ss)
@@ -108,15 +94,15 @@ __global__ __launch_bounds__(kFlowSampleThreads) void k_flow_inverse(FlowTrainAr
         const uint32_t k = min(chunk * 32u + (uint32_t)n32, N - 1u);
         const bool valid = chunk * 32u + (uint32_t)n32 < N;
         float z[8];
-        load8(a.zf + ((size_t)a.off + (size_t)k * a.stride) * kFlowDim + 8 * half, z);
-        float* U = a.U + (size_t)k * kFlowDim + 8 * half;
+        flow_lane_load(a.zf + ((size_t)a.off + (size_t)k * a.stride) * kFlowDim, half, z);
+        float* U = a.U + (size_t)k * kFlowDim;
         const size_t lay = (size_t)N * kFlowDim;
         flow_layer_inv<3>(z, S);
-        if (valid) store8(U + 2 * lay, z);
+        if (valid) flow_lane_store(U + 2 * lay, half, z);
         flow_layer_inv<2>(z, S);
-        if (valid) store8(U + lay, z);
+        if (valid) flow_lane_store(U + lay, half, z);
         flow_layer_inv<1>(z, S);
-        if (valid) store8(U, z);
+        if (valid) flow_lane_store(U, half, z);
         flow_layer_inv<0>(z, S);
         // dL/du_0 = c u_0 (the term u_0^2 / 2 of log J_F)
         if (valid) {
@@ -124,7 +110,7 @@ __global__ __launch_bounds__(kFlowSampleThreads) void k_flow_inverse(FlowTrainAr
             float g[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) g[j] = c * z[j];
-            store8(a.g_out + (size_t)k * kFlowDim + 8 * half, g);
+            flow_lane_store(a.g_out + (size_t)k * kFlowDim, half, g);
         }
     }
 }
@@ -198,7 +184,7 @@ __device__ __forceinline__ void grad_chunk(const float (&u)[8], float (&g)[8], f
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         gn[j] = g[j];
-        if (flow_in_a(L, 8 * half + j)) continue;
+        if (flow_reg_in_a(L, j)) continue;
         const float s = flow_scale(o[j]);
         const float es = flow_exp(-s);
         const float ub = (u[j] - o[8 + j]) * es;
@@ -237,7 +223,7 @@ __device__ __forceinline__ void grad_chunk(const float (&u)[8], float (&g)[8], f
         for (int ks = 0; ks < 4; ++ks) acc = mfma(W[kPU1 + ks * 64 + lane], dA1[ks], acc);
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-            if (flow_in_a(L, 8 * half + j)) gn[j] = g[j] + kFlowXScale * acc[j];
+            if (flow_reg_in_a(L, j)) gn[j] = g[j] + kFlowXScale * acc[j];
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j) g[j] = gn[j];
@@ -422,16 +408,16 @@ __device__ void grad_layer(const FlowTrainArgs& a, FlowBwdLds& S, float* const (
         const uint32_t k = min(chunk * 32u + (uint32_t)n32, N - 1u);
         const bool valid = chunk * 32u + (uint32_t)n32 < N;
         float u[8], g[8];
-        load8(uin + (from_z ? (size_t)a.off + (size_t)k * a.stride : (size_t)k) * kFlowDim + 8 * half, u);
+        flow_lane_load(uin + (from_z ? (size_t)a.off + (size_t)k * a.stride : (size_t)k) * kFlowDim, half, u);
         if (valid) {
-            load8(g_in + (size_t)k * kFlowDim + 8 * half, g);
+            flow_lane_load(g_in + (size_t)k * kFlowDim, half, g);
         } else {
 #pragma unroll
             for (int j = 0; j < 8; ++j) g[j] = 0.f;
         }
         const float coef = train_coef(a, k, valid, *a.sumsq);
         grad_chunk<L>(u, g, coef, S.w, S.b, G);
-        if (valid) store8(g_out + (size_t)k * kFlowDim + 8 * half, g);
+        if (valid) flow_lane_store(g_out + (size_t)k * kFlowDim, half, g);
     }
     grad_to_lds<L>(G, S.red[wave]);
     __syncthreads();
