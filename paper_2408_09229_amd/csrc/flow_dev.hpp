@@ -31,10 +31,44 @@ __device__ __forceinline__ float flow_scale(float a)
 // e^x for the log-scales, |x| <= S: the hardware exp2 of x log2 e
 __device__ __forceinline__ float flow_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
 
-// Gaussian distribution function in FP32 (the device library's erfc)
+// Lower tail h(a) = Phi(-a), a >= 0: h = t 2^(Q(s) - a^2 log2(e) / 2) with
+// t = 1 / (1 + 0.4 a), s = 2t - 1, Q a degree-10 polynomial fitted here
+// (fit_phi.py).  The exponent's roundings (a^2, its product by log2(e)/2
+// with that constant's own remainder, and the difference with Q) are
+// carried as the factor 1 + ln2 dy, so the result stays within about 6
+// ulps (plus the hardware exp2's and reciprocal's) for all a; beyond
+// a = 13.5 it underflows toward 0.
+__device__ __forceinline__ float phi_lower(float a)
+{
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.4f, a, 1.f));
+    const float s = fmaf(2.f, t, -1.f);
+    float q = -2.496585366e-04f;
+    q = fmaf(q, s, 3.146245726e-04f);
+    q = fmaf(q, s, 1.360302093e-03f);
+    q = fmaf(q, s, -2.809225582e-03f);
+    q = fmaf(q, s, -3.100826871e-03f);
+    q = fmaf(q, s, 1.396346372e-02f);
+    q = fmaf(q, s, 3.256450873e-03f);
+    q = fmaf(q, s, -7.306771725e-02f);
+    q = fmaf(q, s, -2.237056615e-03f);
+    q = fmaf(q, s, 8.854163885e-01f);
+    q = fmaf(q, s, -1.822846770e+00f);
+    constexpr float kHi = 0.72134752f;                         // log2(e) / 2, rounded
+    constexpr float kLo = (float)(0.72134752044448170 - (double)kHi);
+    const float sq = a * a;
+    const float u = kHi * sq;
+    float corr = fmaf(kHi, sq, -u);                            // u's rounding
+    corr = fmaf(kHi, fmaf(a, a, -sq), corr);                   // sq's
+    corr = fmaf(kLo, sq, corr);                                // the constant's
+    const float y = q - u;
+    const float ylo = q - (y + u);                             // y's (u >= |q| beyond a = 1.6)
+    const float f = fmaf(ylo - corr, 0.69314718f, 1.f);
+    return t * __builtin_amdgcn_exp2f(y) * f;
+}
+// Gaussian distribution function in FP32
 __device__ __forceinline__ float flow_phi(float z)
 {
-    const float h = 0.5f * erfcf(fabsf(z) * 0.70710678118654752f);
+    const float h = phi_lower(fabsf(z));
     return z < 0.f ? h : 1.f - h;
 }
 
@@ -42,7 +76,7 @@ __device__ __forceinline__ float flow_phi(float z)
 // two-piece form ("Approximating the erfinv function", GPU Computing Gems,
 // 2011): erfinv(x) = x p(w) with w = -ln(4m(1 - m)) = -ln(1 - x^2), p a
 // polynomial in w - 2.5 for w < 5 and in sqrt(w) - 3 for 5 <= w <= 16.2
-// (m >= 1e-7).  The coefficients are fitted here (fit_phi_inv.py): within
+// (m >= 1e-7).  The coefficients are fitted here (fit_phi.py): within
 // 2.1e-7 relative (3.5 ulps) over that range.  Below m = 1e-7 (a rare,
 // divergent branch) the device library's erfcinv takes over.
 __device__ __forceinline__ float phi_inv_lower(float m)
@@ -64,7 +98,7 @@ __device__ __forceinline__ float phi_inv_lower(float m)
     } else {
         const float t = __builtin_amdgcn_sqrtf(w) - 3.f;
         p = -1.941565133e-04f;
-        p = fmaf(p, t, 1.017520626e-04f);
+        p = fmaf(p, t, 1.017520699e-04f);
         p = fmaf(p, t, 1.340063871e-03f);
         p = fmaf(p, t, -3.675155109e-03f);
         p = fmaf(p, t, 5.743755959e-03f);

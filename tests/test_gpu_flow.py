@@ -75,8 +75,9 @@ def oracle_y(orc, w, nh, t, ks):
 
 def roundtrip_bound(y):
     """|Phi(Phi^-1(y)) - y| in FP32 for the warp's sampling pass: min(y,
-    1 - y) rounded to FP32 (2^-24 relative), erfcinv and erfc to a few ulps
-    each (8 allowed), each relative error of z = Phi^-1(y) moving the tail
+    1 - y) rounded to FP32 (2^-24 relative), the device's fitted Phi^-1 and
+    Phi to 3.5 and about 6 ulps plus the hardware exp2's and reciprocal's
+    (16 allowed in all), each relative error of z = Phi^-1(y) moving the tail
     probability m = min(y, 1 - y) by z^2 + 1 times itself at most (the
     tail's log-derivative d ln m / d ln z is about z^2), and the rounding of
     w itself (2^-25 absolute at most)."""
