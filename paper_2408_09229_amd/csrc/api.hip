@@ -277,7 +277,7 @@ struct vegas_ctx {
     vegas_flow_config fcfg{};
     unsigned char* fws = nullptr;
     size_t f_theta = 0, f_packed = 0, f_w = 0, f_z = 0, f_lj = 0, f_om = 0, f_U = 0, f_G0 = 0, f_G1 = 0, f_part = 0,
-           f_grad = 0, f_m = 0, f_v = 0, f_sumsq = 0, f_done = 0;
+           f_grad = 0, f_m = 0, f_v = 0, f_sumsq = 0;
     int f_nwg = 0;                     // workgroups of the training passes
     int f_step = 0;                    // Adam steps taken
     size_t f_acc = 0;                  // last accepted parameters
@@ -1226,7 +1226,7 @@ vegas_status vegas_sample_probe(vegas_ctx* c, uint32_t t, uint64_t k0, int64_t n
 namespace {
 
 struct FlowPlan {
-    size_t theta, packed, w, z, lj, om, U, G0, G1, part, seg, grad, m, v, sumsq, done, acc, total;
+    size_t theta, packed, w, z, lj, om, U, G0, G1, part, seg, grad, m, v, sumsq, acc, total;
 };
 
 FlowPlan flow_plan(uint32_t n_eval, int n_wg)
@@ -1253,7 +1253,6 @@ FlowPlan flow_plan(uint32_t n_eval, int n_wg)
     p.m = take(sizeof(float) * kFParams);
     p.v = take(sizeof(float) * kFParams);
     p.sumsq = take(sizeof(double) * (1 + 256));
-    p.done = take(sizeof(uint32_t) * kFlowLayers);
     p.acc = take(sizeof(float) * kFParams);
     p.total = o;
     return p;
@@ -1439,7 +1438,6 @@ vegas_status flow_train_step(vegas_ctx* c)
     adam.m = reinterpret_cast<float*>(c->fws + c->f_m);
     adam.v = reinterpret_cast<float*>(c->fws + c->f_v);
     adam.packed = c->fws + c->f_packed;
-    adam.done = reinterpret_cast<uint32_t*>(c->fws + c->f_done);
     adam.lr = c->fcfg.lr;
     adam.step = (int)(c->f_step + 1);
     vegas_status s = flow_gradient(c, stride, (uint32_t)(c->f_step % stride), &adam);
@@ -1523,7 +1521,6 @@ vegas_status vegas_flow_attach(vegas_ctx* c, const vegas_flow_config* cfg, const
     c->f_m = p.m;
     c->f_v = p.v;
     c->f_sumsq = p.sumsq;
-    c->f_done = p.done;
     c->f_acc = p.acc;
     c->f_seg = p.seg;
     c->f_nwg = nwg;
@@ -1533,7 +1530,6 @@ vegas_status vegas_flow_attach(vegas_ctx* c, const vegas_flow_config* cfg, const
     HIPCHK(launch_reset(reinterpret_cast<unsigned long long*>(c->fws + p.m), kFParams / 2, c->stream));
     HIPCHK(launch_reset(reinterpret_cast<unsigned long long*>(c->fws + p.v), kFParams / 2, c->stream));
     HIPCHK(launch_reset(reinterpret_cast<unsigned long long*>(c->fws + p.om), (int)((c->g.n_eval + 1) / 2), c->stream));
-    HIPCHK(launch_reset(reinterpret_cast<unsigned long long*>(c->fws + p.done), kFlowLayers / 2, c->stream));
     if (params) return vegas_flow_set_params(c, params);
     // the library's own starting weights
     float* th = reinterpret_cast<float*>(c->fws + c->f_theta);

@@ -187,7 +187,6 @@ struct FlowAdamArgs {
     float* m;
     float* v;
     void* packed;                 // repacked BF16 operands
-    uint32_t* done;               // [layers] workgroups finished with each layer (zero between launches)
     float lr;
     int step;                     // counts from 1
 };

@@ -9,16 +9,17 @@
 // u_4 = z_4 -> u_3 -> u_2 -> u_1 -> u_0, where log J_F depends on the
 // parameters through each layer's log-scales and through u_0 (the term
 // u_0^2 / 2):
-//   k_flow_sumsq    sum of |omega|^gamma (block partials; the inverse pass
-//                   adds them in order)
-//   k_flow_inverse  u_3, u_2, u_1 of every training sample (MLP on MFMA) and
-//                   the upstream gradient dL/du_0 = c u_0
-//   k_flow_grad     the coupling layers l = 0..3 in turn: from g = dL/du_l,
-//                   the layer's log-scales and inverse transform give
-//                   dL/d(a, t); the MLP backward and the weight gradients
-//                   dW = sum_samples delta^T activation run on MFMA with
-//                   every activation and delta in registers, each wave
-//                   summing its samples, the waves added in LDS
+//   k_flow_sumsq    sum of |omega|^gamma (block partials; the gradient
+//                   kernel adds them in order)
+//   k_flow_grad     first the inverse pass: u_3, u_2, u_1 of the
+//                   workgroup's training samples (MLP on MFMA) and the
+//                   upstream gradient dL/du_0 = c u_0; then the coupling
+//                   layers l = 0..3 in turn: from g = dL/du_l, the layer's
+//                   log-scales and inverse transform give dL/d(a, t); the
+//                   MLP backward and the weight gradients dW = sum_samples
+//                   delta^T activation run on MFMA with every activation
+//                   and delta in registers, each wave summing its samples,
+//                   the waves added in LDS
 //   k_flow_reduce_seg, k_flow_update  per-workgroup gradients summed in a
 //                   fixed order, Adam on the FP32 parameters and their BF16
 //                   repacking
@@ -68,53 +69,6 @@ __device__ __forceinline__ float train_coef(const FlowTrainArgs& a, uint32_t k, 
     return (float)((a.gamma == 2 ? om * om : om) * inv_ss);
 }
 
-__global__ __launch_bounds__(kFlowSampleThreads) void k_flow_inverse(FlowTrainArgs a)
-{
-    __shared__ FlowFwdLds S;
-    __shared__ double red[kSumThreads];
-    flow_stage_fwd(S, reinterpret_cast<const bf16x8*>(a.packed), a.theta);
-    // the total of the sums' block partials, by every workgroup in the same
-    // order (workgroup 0 keeps it for the backward pass)
-    if (threadIdx.x < kSumThreads) red[threadIdx.x] = threadIdx.x < kSumBlocks ? a.sumsq[1 + threadIdx.x] : 0.0;
-    __syncthreads();
-    for (int w = kSumThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    const double ss = red[0];
-    if (blockIdx.x == 0 && threadIdx.x == 0) const_cast<double*>(a.sumsq)[0] = ss;
-    const int lane = threadIdx.x & 63;
-    const int half = lane >> 5;
-    const int n32 = lane & 31;
-    const uint32_t N = a.n;
-    const uint32_t chunks = (N + 31u) / 32u;
-    const uint32_t n_waves = gridDim.x * kFlowSampleWaves;
-    // waves run independently: no barrier inside the loop
-    for (uint32_t chunk = blockIdx.x * kFlowSampleWaves + (threadIdx.x >> 6); chunk < chunks; chunk += n_waves) {
-        const uint32_t k = min(chunk * 32u + (uint32_t)n32, N - 1u);
-        const bool valid = chunk * 32u + (uint32_t)n32 < N;
-        float z[8];
-        flow_lane_load(a.zf + ((size_t)a.off + (size_t)k * a.stride) * kFlowDim, half, z);
-        float* U = a.U + (size_t)k * kFlowDim;
-        const size_t lay = (size_t)N * kFlowDim;
-        flow_layer_inv<3>(z, S);
-        if (valid) flow_lane_store(U + 2 * lay, half, z);
-        flow_layer_inv<2>(z, S);
-        if (valid) flow_lane_store(U + lay, half, z);
-        flow_layer_inv<1>(z, S);
-        if (valid) flow_lane_store(U, half, z);
-        flow_layer_inv<0>(z, S);
-        // dL/du_0 = c u_0 (the term u_0^2 / 2 of log J_F)
-        if (valid) {
-            const float c = train_coef(a, k, true, ss);
-            float g[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) g[j] = c * z[j];
-            flow_lane_store(a.g_out + (size_t)k * kFlowDim, half, g);
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // backward pass of the coupling layers
 // ---------------------------------------------------------------------------
@@ -131,8 +85,13 @@ __global__ __launch_bounds__(kFlowSampleThreads) void k_flow_inverse(FlowTrainAr
 struct __align__(16) FlowBwdLds {
     bf16x8 w[kPLayer];                         // this layer's operands
     float b[2 * kFlowHidden + kFlowOut];       // b1, b2, b3
-    float red[kFlowWaves][kFLayer];            // per-wave gradients of the layer
+    union {
+        float red[kFlowWaves][kFLayer];        // per-wave gradients of the layer
+        FlowFwdLds fwd;                        // the inverse pass: every layer's forward operands
+    };
+    double sum[kSumThreads];                   // the total of the sums' block partials
 };
+static_assert(kFlowThreads == kSumThreads, "one partial per thread");
 
 // sum of a lane's 16 registers
 __device__ __forceinline__ float reg_sum(const f32x16& a)
@@ -363,7 +322,7 @@ __device__ __forceinline__ void grad_to_lds(const LayerGrad& G, float* __restric
 
 // layer L: every chunk of the workgroup, then its part of the gradient
 template <int L>
-__device__ void grad_layer(const FlowTrainArgs& a, FlowBwdLds& S, float* const (&gbuf)[2])
+__device__ void grad_layer(const FlowTrainArgs& a, FlowBwdLds& S, float* const (&gbuf)[2], double ss)
 {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -407,15 +366,17 @@ __device__ void grad_layer(const FlowTrainArgs& a, FlowBwdLds& S, float* const (
     for (uint32_t chunk = blockIdx.x * kFlowWaves + wave; chunk < chunks; chunk += n_waves) {
         const uint32_t k = min(chunk * 32u + (uint32_t)n32, N - 1u);
         const bool valid = chunk * 32u + (uint32_t)n32 < N;
+        // lanes past the end take u = 0 and g = 0 (finite: their zero
+        // deltas then add nothing to the sums over samples)
         float u[8], g[8];
-        flow_lane_load(uin + (from_z ? (size_t)a.off + (size_t)k * a.stride : (size_t)k) * kFlowDim, half, u);
         if (valid) {
+            flow_lane_load(uin + (from_z ? (size_t)a.off + (size_t)k * a.stride : (size_t)k) * kFlowDim, half, u);
             flow_lane_load(g_in + (size_t)k * kFlowDim, half, g);
         } else {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) g[j] = 0.f;
+            for (int j = 0; j < 8; ++j) u[j] = g[j] = 0.f;
         }
-        const float coef = train_coef(a, k, valid, *a.sumsq);
+        const float coef = train_coef(a, k, valid, ss);
         grad_chunk<L>(u, g, coef, S.w, S.b, G);
         if (valid) flow_lane_store(g_out + (size_t)k * kFlowDim, half, g);
     }
@@ -431,16 +392,67 @@ __device__ void grad_layer(const FlowTrainArgs& a, FlowBwdLds& S, float* const (
     __syncthreads();
 }
 
+// The inverse pass of the workgroup's training samples, with the chunk of
+// every wave the one it takes in each layer of the backward pass, so that
+// u_1..u_3 and dL/du_0 are read back by the lanes that wrote them.  Returns
+// the total of the sums' block partials, added by every workgroup in the
+// same order (workgroup 0 keeps it).
+__device__ double inverse_pass(const FlowTrainArgs& a, FlowBwdLds& S, float* g0)
+{
+    flow_stage_fwd(S.fwd, reinterpret_cast<const bf16x8*>(a.packed), a.theta);
+    S.sum[threadIdx.x] = threadIdx.x < kSumBlocks ? a.sumsq[1 + threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int w = kSumThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) S.sum[threadIdx.x] += S.sum[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double ss = S.sum[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) const_cast<double*>(a.sumsq)[0] = ss;
+    const int lane = threadIdx.x & 63;
+    const int half = lane >> 5;
+    const int n32 = lane & 31;
+    const uint32_t N = a.n;
+    const uint32_t chunks = (N + 31u) / 32u;
+    const uint32_t n_waves = gridDim.x * kFlowWaves;
+    for (uint32_t chunk = blockIdx.x * kFlowWaves + (threadIdx.x >> 6); chunk < chunks; chunk += n_waves) {
+        const uint32_t k = min(chunk * 32u + (uint32_t)n32, N - 1u);
+        const bool valid = chunk * 32u + (uint32_t)n32 < N;
+        float z[8];
+        flow_lane_load(a.zf + ((size_t)a.off + (size_t)k * a.stride) * kFlowDim, half, z);
+        float* U = a.U + (size_t)k * kFlowDim;
+        const size_t lay = (size_t)N * kFlowDim;
+        flow_layer_inv<3>(z, S.fwd);
+        if (valid) flow_lane_store(U + 2 * lay, half, z);
+        flow_layer_inv<2>(z, S.fwd);
+        if (valid) flow_lane_store(U + lay, half, z);
+        flow_layer_inv<1>(z, S.fwd);
+        if (valid) flow_lane_store(U, half, z);
+        flow_layer_inv<0>(z, S.fwd);
+        // dL/du_0 = c u_0 (the term u_0^2 / 2 of log J_F)
+        if (valid) {
+            const float c = train_coef(a, k, true, ss);
+            float g[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) g[j] = c * z[j];
+            flow_lane_store(g0 + (size_t)k * kFlowDim, half, g);
+        }
+    }
+    // the first layer's staging ends with a barrier before the per-wave
+    // gradients (which share the forward operands' LDS) are written
+    return ss;
+}
+
 __global__ __launch_bounds__(kFlowThreads) void k_flow_grad(FlowTrainArgs a)
 {
     __shared__ FlowBwdLds S;
     // dL/du_l passes between the layers through two buffers: the inverse
-    // pass left dL/du_0 in g_in
+    // pass leaves dL/du_0 in g_in
     float* const gbuf[2] = {const_cast<float*>(a.g_in), a.g_out};
-    grad_layer<0>(a, S, gbuf);
-    grad_layer<1>(a, S, gbuf);
-    grad_layer<2>(a, S, gbuf);
-    grad_layer<3>(a, S, gbuf);
+    const double ss = inverse_pass(a, S, gbuf[0]);
+    grad_layer<0>(a, S, gbuf, ss);
+    grad_layer<1>(a, S, gbuf, ss);
+    grad_layer<2>(a, S, gbuf, ss);
+    grad_layer<3>(a, S, gbuf, ss);
 }
 
 // per-workgroup gradients summed in a fixed order: segments of consecutive
@@ -472,47 +484,23 @@ __device__ __forceinline__ float adam_update(float* theta, float* m, float* v, i
     return t;
 }
 
-// The segments in order into grad, one thread per parameter; with adam
-// set, the Adam step on it too.  The workgroup that finishes last with a
-// layer (a counter per layer, after a device-scope fence) repacks that
-// layer's BF16 operands and clears the counter for the next launch.
 constexpr int kUpdThreads = 256;
 constexpr int kUpdBlocks = (kFParams + kUpdThreads - 1) / kUpdThreads;
 
+// The segments in order into grad, one thread per parameter; with adam set,
+// the Adam step on it too.  The BF16 repacking follows as a launch of its
+// own over every layer's entries at once (done inside this kernel by the
+// last workgroup to finish each layer, it made the kernel 16-20 us long,
+// against 9 for the two launches).
 __global__ __launch_bounds__(kUpdThreads) void k_flow_update(const float* seg, float* grad, FlowAdamArgs adam,
                                                              float c1, float c2)
 {
-    __shared__ uint32_t last[2];
     const int i = blockIdx.x * kUpdThreads + threadIdx.x;
-    if (i < kFParams) {
-        float s = 0.f;
-        for (int g = 0; g < kRedSegs; ++g) s += seg[(size_t)g * kFParams + i];
-        grad[i] = s;
-        if (adam.theta) (void)adam_update(adam.theta, adam.m, adam.v, i, s, adam.lr, c1, c2);
-    }
-    if (!adam.theta) return;
-    // layers this workgroup's parameters belong to, and how many
-    // workgroups hold parameters of each
-    const int i0 = blockIdx.x * kUpdThreads;
-    const int i1 = min(i0 + kUpdThreads, kFParams) - 1;
-    const int l0 = i0 / kFLayer, l1 = i1 / kFLayer;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int l = l0; l <= l1; ++l) {
-            const int n_blk = ((l + 1) * kFLayer - 1) / kUpdThreads - (l * kFLayer) / kUpdThreads + 1;
-            last[l - l0] = atomicAdd(adam.done + l, 1u) + 1u == (uint32_t)n_blk ? 1u : 0u;
-        }
-    }
-    __syncthreads();
-    for (int l = l0; l <= l1; ++l) {
-        if (!last[l - l0]) continue;
-        __threadfence();
-        const float* P = adam.theta + (size_t)l * kFLayer;
-        bf16x8* pk = reinterpret_cast<bf16x8*>(adam.packed) + (size_t)l * kPLayer;
-        for (int r = threadIdx.x; r < kPLayer; r += kUpdThreads) pk[r] = flow_pack_entry(l, r, P);
-        if (threadIdx.x == 0) adam.done[l] = 0u;
-    }
+    if (i >= kFParams) return;
+    float s = 0.f;
+    for (int g = 0; g < kRedSegs; ++g) s += seg[(size_t)g * kFParams + i];
+    grad[i] = s;
+    if (adam.theta) (void)adam_update(adam.theta, adam.m, adam.v, i, s, adam.lr, c1, c2);
 }
 
 __global__ void k_flow_adam(float* theta, const float* grad, float* m, float* v, float lr, float c1, float c2)
@@ -541,13 +529,10 @@ hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, 
     double* ss = const_cast<double*>(base.sumsq);
     hipLaunchKernelGGL(k_flow_sumsq, dim3(kSumBlocks), dim3(kSumThreads), 0, st, base.om, base.n, base.stride,
                        base.off, base.gamma, ss);
-    // the inverse pass totals those sums, writes u_1..u_3 and dL/du_0 (into
-    // G1); then every layer's backward pass in one launch, alternating G1
-    // and G0
+    // one launch totals those sums, runs the inverse pass (u_1..u_3, and
+    // dL/du_0 into G1) and every layer's backward pass, alternating G1 and G0
     FlowTrainArgs a = base;
     a.g_in = G1;
-    a.g_out = G1;
-    hipLaunchKernelGGL(k_flow_inverse, dim3(2 * n_wg), dim3(kFlowSampleThreads), 0, st, a);
     a.g_out = G0;
     hipLaunchKernelGGL(k_flow_grad, dim3(n_wg), dim3(kFlowThreads), 0, st, a);
     hipLaunchKernelGGL(k_flow_reduce_seg, dim3((kFParams + 255) / 256, kRedSegs), dim3(256), 0, st,
@@ -557,6 +542,7 @@ hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, 
     if (adam) adam_corrections(adam->step, &c1, &c2);
     hipLaunchKernelGGL(k_flow_update, dim3(kUpdBlocks), dim3(kUpdThreads), 0, st, (const float*)seg, grad,
                        adam ? *adam : none, c1, c2);
+    if (adam) return launch_flow_pack(adam->theta, adam->packed, st);
     return hipGetLastError();
 }
 
