@@ -78,7 +78,7 @@ WORKLOADS = {
 
 
 FILL_SOURCES = ["fill.hip", "fill_dev.hpp", "batch.hip", "sample.hpp", "common.hpp", "families.hpp", "layout.hpp"]
-FLOW_SOURCES = ["flow.hip", "flow.hpp", "flow_dev.hpp", "common.hpp", "fill_dev.hpp", "layout.hpp"]
+FLOW_SOURCES = ["flow.hip", "flow_train.hip", "flow.hpp", "flow_dev.hpp", "common.hpp", "fill_dev.hpp", "layout.hpp"]
 
 
 def source_hash(files=FILL_SOURCES) -> str:
@@ -95,19 +95,25 @@ def fill_source_hash() -> str:
     return source_hash(FILL_SOURCES)
 
 
-def profiled_traffic(workload: str, kernel: str = "k_fill", files=FILL_SOURCES):
+def profiled_traffic(workload: str, prefix: str = "k_fill", files=FILL_SOURCES, kernel=None):
     """HBM bytes per launch of a kernel from the rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary in profiles/ (scaled by a device copy of known size),
-    or None when there is none or the kernel changed since it was taken."""
+    WRITE_SIZE summary profiles/<prefix>_<workload>.md (scaled by a device
+    copy of known size; with kernel given, that kernel's entry of the
+    summary's record), or None when there is none or the sources changed
+    since it was taken."""
     import re
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
+    path = os.path.join(ROOT, "profiles", f"{prefix}_{workload}.md")
     if not os.path.exists(path):
         return None
     m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
     if not m:
         return None
     rec = json.loads(m.group(1))
-    return rec.get("traffic_bytes") if rec.get("source_hash") == source_hash(files) else None
+    if rec.get("source_hash") != source_hash(files):
+        return None
+    if kernel is not None:
+        rec = rec.get("kernels", {}).get(kernel, {})
+    return rec.get("traffic_bytes")
 
 
 def host_info():
@@ -476,19 +482,28 @@ def run_warp_compare(args, w):
     kinds = v.flow_kinds()[-args.steps:]
     ft = v.flow_timing()
     v.close()
-    # the warp's two MFMA phases per warped iteration: the sampling pass over
-    # every sample, and the training steps over 1/stride of them each; the
-    # roofline line names the longer one
-    samp_ms, train_ms = ft["sample_ms"], ft["train_ms"]
+    # the warp's two MFMA kernels: the sampling pass over every sample (one
+    # launch per warped iteration), and the gradient kernel (inverse pass
+    # and every layer's backward pass) over 1/stride of them, once per Adam
+    # step; the roofline line names the one with the most time per
+    # iteration, at its own per-launch duration.  The whole training (its
+    # five launches per Adam step) is reported beside them.
+    samp_ms, train_ms, grad_ms = ft["sample_ms"], ft["train_ms"], ft["grad_launch_ms"]
     n_train = (w.n_eval + args.train_stride - 1) // args.train_stride
-    phases = {
-        "k_flow_sample": (FLOW_SAMPLE_FLOPS * w.n_eval, samp_ms),
-        "training (k_flow_inverse, 4 x k_flow_grad, reductions, Adam)":
-            (FLOW_TRAIN_FLOPS * n_train * args.flow_steps_final, train_ms),
+    kernels = {
+        "k_flow_sample": (FLOW_SAMPLE_FLOPS * w.n_eval, samp_ms, 1),
+        "k_flow_grad": (FLOW_TRAIN_FLOPS * n_train, grad_ms, args.flow_steps_final),
     }
-    dom = max(phases, key=lambda k: phases[k][1] or 0.0)
-    flops, dom_ms = phases[dom]
+    dom = max(kernels, key=lambda k: (kernels[k][1] or 0.0) * kernels[k][2])
+    flops, dom_ms, _ = kernels[dom]
     ach = flops / (dom_ms / 1e3) if dom_ms else None
+    phases = {k: {"ms_per_launch": m, "launches_per_iteration": n,
+                  "tflops": (f / (m / 1e3) / 1e12) if m else None,
+                  "frac": (f / (m / 1e3) / 2.5e15) if m else None} for k, (f, m, n) in kernels.items()}
+    tf = FLOW_TRAIN_FLOPS * n_train * args.flow_steps_final
+    phases["training (per iteration: k_flow_sumsq, k_flow_grad, k_flow_reduce_seg, k_flow_update, k_flow_pack "
+           "per Adam step)"] = {"ms": train_ms, "tflops": (tf / (train_ms / 1e3) / 1e12) if train_ms else None,
+                                "frac": (tf / (train_ms / 1e3) / 2.5e15) if train_ms else None}
     pl, wp = out["plain"], out["warp"]
     line = {
         "metric": "integrand evals/sec and wall time to 1e-4 rel. error; learned warp vs plain VEGAS+",
@@ -523,11 +538,8 @@ def run_warp_compare(args, w):
                              "plain": int((kinds == 0).sum())},
         "roofline": {"bound": "mfma", "achieved": ach / 1e12 if ach else None, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": ach / 2.5e15 if ach else None,
-                     "traffic": profiled_traffic(w.name, "k_flow", FLOW_SOURCES), "kernel": dom,
-                     "kernel_ms": dom_ms, "flops_per_launch": flops,
-                     "phases": {k: {"ms": m, "tflops": (f / (m / 1e3) / 1e12) if m else None,
-                                    "frac": (f / (m / 1e3) / 2.5e15) if m else None}
-                                for k, (f, m) in phases.items()}},
+                     "traffic": profiled_traffic(w.name, "k_flow", FLOW_SOURCES, kernel=dom), "kernel": dom,
+                     "kernel_ms": dom_ms, "flops_per_launch": flops, "phases": phases},
     }
     if args.copy_calibration:
         line["copy_calibration_bytes"] = copy_calibration()

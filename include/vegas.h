@@ -352,6 +352,12 @@ vegas_status vegas_flow_enable(vegas_ctx* ctx, int32_t on);
  * repack), and *n_iter their count.  ms: host array of 2 doubles. */
 vegas_status vegas_flow_set_timing(vegas_ctx* ctx, int32_t on);
 vegas_status vegas_flow_get_timing(vegas_ctx* ctx, double* ms, int32_t* n_iter);
+/* With the same timing on: the gradient kernel alone (the training's
+ * dominant kernel: inverse pass and every layer's backward pass), events
+ * just before and after each of its launches.  Synchronises; *ms receives
+ * the summed duration in ms and *n_launch the launch count.  ms: host
+ * pointer to one double. */
+vegas_status vegas_flow_get_grad_timing(vegas_ctx* ctx, double* ms, int32_t* n_launch);
 /* Kind of every iteration run so far: 0 plain, 1 through the warp, 2 plain
  * control of the judge.  kinds: host array of capacity cap; *n receives
  * the iteration count.  No HIP call. */

@@ -114,6 +114,7 @@ _DECL = {
     "vegas_flow_get_kinds": (_st, [_vp, _vp, C.c_int32, C.POINTER(C.c_int32)]),
     "vegas_flow_set_timing": (_st, [_vp, C.c_int32]),
     "vegas_flow_get_timing": (_st, [_vp, _vp, C.POINTER(C.c_int32)]),
+    "vegas_flow_get_grad_timing": (_st, [_vp, _vp, C.POINTER(C.c_int32)]),
     "vegas_flow_status": (_st, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "vegas_flow_get_params": (_st, [_vp, _vp]),
     "vegas_flow_set_params": (_st, [_vp, _vp]),
@@ -401,13 +402,17 @@ class Vegas:
         check(vegas_flow_set_timing(self.h, int(on)), "vegas_flow_set_timing")
 
     def flow_timing(self):
-        """Per warped iteration, ms of the sampling pass and of the training."""
+        """Per warped iteration, ms of the sampling pass and of the training;
+        per launch, ms of the gradient kernel."""
         ms = np.zeros(2)
         n = C.c_int32()
         check(vegas_flow_get_timing(self.h, _dptr(ms), C.byref(n)), "vegas_flow_get_timing")
         k = max(n.value, 1)
+        g = np.zeros(1)
+        ng = C.c_int32()
+        check(vegas_flow_get_grad_timing(self.h, _dptr(g), C.byref(ng)), "vegas_flow_get_grad_timing")
         return {"sample_ms": ms[0] / k if n.value else None, "train_ms": ms[1] / k if n.value else None,
-                "n": n.value}
+                "n": n.value, "grad_launch_ms": g[0] / ng.value if ng.value else None, "grad_launches": ng.value}
 
     def flow_kinds(self):
         """Per iteration: 0 plain, 1 through the warp, 2 plain control of the judge."""

@@ -298,6 +298,7 @@ struct vegas_ctx {
     double kw_sum = 0.0, kw_w = 0.0;   // kept warped iterations of the cost phase: sum I/s2, sum 1/s2
     bool f_timing = false;             // events around the sampling pass and the training
     std::vector<hipEvent_t> f_tev;     // 4 per timed warped iteration
+    std::vector<hipEvent_t> f_gev;     // 2 per timed launch of the gradient kernel
     int strikes = 0;                   // consecutive control checks the warp lost
     int rejects = 0;                   // consecutive rejected warped iterations
     int n_accepted = 0, n_rejected = 0, n_control = 0;
@@ -307,6 +308,7 @@ struct vegas_ctx {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         for (hipEvent_t e : f_ev) (void)hipEventDestroy(e);
         for (hipEvent_t e : f_tev) (void)hipEventDestroy(e);
+        for (hipEvent_t e : f_gev) (void)hipEventDestroy(e);
     }
     hipError_t fmark()
     {
@@ -1290,9 +1292,18 @@ FlowTrainArgs flow_train_args(vegas_ctx* c, uint32_t stride, uint32_t off)
 // off, off + stride, ...; with adam set, the Adam step on it too
 vegas_status flow_gradient(vegas_ctx* c, uint32_t stride, uint32_t off, const FlowAdamArgs* adam)
 {
+    hipEvent_t* ev = nullptr;
+    if (c->f_timing) {
+        for (int i = 0; i < 2; ++i) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            c->f_gev.push_back(e);
+        }
+        ev = c->f_gev.data() + c->f_gev.size() - 2;
+    }
     HIPCHK(launch_flow_gradient(flow_train_args(c, stride, off), c->f_nwg, reinterpret_cast<float*>(c->fws + c->f_G0),
                                 reinterpret_cast<float*>(c->fws + c->f_G1), reinterpret_cast<float*>(c->fws + c->f_grad),
-                                reinterpret_cast<float*>(c->fws + c->f_seg), adam, c->stream));
+                                reinterpret_cast<float*>(c->fws + c->f_seg), adam, c->stream, ev));
     return VEGAS_OK;
 }
 
@@ -1580,6 +1591,8 @@ vegas_status vegas_flow_set_timing(vegas_ctx* c, int32_t on)
     HIPCHK(hipStreamSynchronize(c->stream));
     for (hipEvent_t e : c->f_tev) (void)hipEventDestroy(e);
     c->f_tev.clear();
+    for (hipEvent_t e : c->f_gev) (void)hipEventDestroy(e);
+    c->f_gev.clear();
     c->f_timing = on != 0;
     return VEGAS_OK;
 }
@@ -1598,6 +1611,21 @@ vegas_status vegas_flow_get_timing(vegas_ctx* c, double* ms, int32_t* n_iter)
         ms[1] += b;
     }
     if (n_iter) *n_iter = n;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_flow_get_grad_timing(vegas_ctx* c, double* ms, int32_t* n_launch)
+{
+    if (!c || !ms) return fail(VEGAS_EINVAL, "bad arguments");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *ms = 0.0;
+    int n = 0;
+    for (size_t i = 0; i + 2 <= c->f_gev.size(); i += 2, ++n) {
+        float a = 0.f;
+        HIPCHK(hipEventElapsedTime(&a, c->f_gev[i], c->f_gev[i + 1]));
+        *ms += a;
+    }
+    if (n_launch) *n_launch = n;
     return VEGAS_OK;
 }
 

@@ -524,7 +524,7 @@ void adam_corrections(int step, float* c1, float* c2)
 }  // namespace
 
 hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, float* G1, float* grad,
-                                float* seg, const FlowAdamArgs* adam, hipStream_t st)
+                                float* seg, const FlowAdamArgs* adam, hipStream_t st, hipEvent_t* ev)
 {
     double* ss = const_cast<double*>(base.sumsq);
     hipLaunchKernelGGL(k_flow_sumsq, dim3(kSumBlocks), dim3(kSumThreads), 0, st, base.om, base.n, base.stride,
@@ -534,7 +534,15 @@ hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, 
     FlowTrainArgs a = base;
     a.g_in = G1;
     a.g_out = G0;
+    if (ev) {
+        const hipError_t r = hipEventRecord(ev[0], st);
+        if (r != hipSuccess) return r;
+    }
     hipLaunchKernelGGL(k_flow_grad, dim3(n_wg), dim3(kFlowThreads), 0, st, a);
+    if (ev) {
+        const hipError_t r = hipEventRecord(ev[1], st);
+        if (r != hipSuccess) return r;
+    }
     hipLaunchKernelGGL(k_flow_reduce_seg, dim3((kFParams + 255) / 256, kRedSegs), dim3(256), 0, st,
                        (const float*)a.part, n_wg, seg);
     FlowAdamArgs none = {};

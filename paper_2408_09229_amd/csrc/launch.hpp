@@ -86,8 +86,10 @@ hipError_t launch_mfma_probe(const float* A, const float* B, float* D, hipStream
 hipError_t launch_flow_sample(const FlowSampleArgs& a, int n_wg, hipStream_t st);
 hipError_t launch_fill_flow(const FillArgs& a, const float* w, const float* lj, float* om, int n_wg, size_t lds,
                             hipStream_t st);
+// ev: null, or two events recorded on st just before and after the
+// gradient kernel (its own duration)
 hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, float* G1, float* grad,
-                                float* seg, const FlowAdamArgs* adam, hipStream_t st);
+                                float* seg, const FlowAdamArgs* adam, hipStream_t st, hipEvent_t* ev = nullptr);
 hipError_t launch_flow_adam(float* theta, const float* grad, float* m, float* v, float lr, int step, hipStream_t st);
 
 constexpr int kAllocThreads = 1024;
