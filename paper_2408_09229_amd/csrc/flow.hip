@@ -123,25 +123,38 @@ __global__ __launch_bounds__(kFlowSampleThreads, 4) void k_flow_sample(FlowSampl
     const uint32_t n_waves = gridDim.x * kFlowSampleWaves;
     const double den = (double)sc.nst * 0x1p33;
     const double inv_den = 1.0 / den;
+    // N_st^16 cubes fit in 32 bits, so N_st <= 4 and every shift below is
+    // at most 30
+    const bool pow2 = (sc.nst & (sc.nst - 1u)) == 0u;
+    const uint32_t lg = (uint32_t)__builtin_ctz(sc.nst);
     // waves run independently: no barrier inside the loop
     for (uint32_t chunk = blockIdx.x * kFlowSampleWaves + (threadIdx.x >> 6); chunk < chunks; chunk += n_waves) {
         const uint32_t k0 = chunk * 32u;
         const uint32_t k = min(k0 + (uint32_t)n32, N - 1u);
-        // the stratum digits of the lane's axes: axis d sits in register
-        // 4 (d / 8) + d % 4 of half (d / 4) % 2 (written per register, as an
-        // index into all 16 digits that depends on the lane would be a
-        // 16-way select chain)
+        // the stratum digits of the lane's axes (axis d sits in register
+        // 4 (d / 8) + d % 4 of half (d / 4) % 2).  N_st a power of two (the
+        // usual case at d = 16: 2^16 or 4^16 cubes): each digit is a shift
+        // and a mask.  Otherwise division by N_st, one digit after the
+        // other, each kept by the half that holds it (written per register:
+        // an index into all 16 digits that depends on the lane would be a
+        // 16-way select chain).
         uint32_t hc = flow_cube(a.start, sc.n_cubes, k0, k, lane), dig[8];
+        if (pow2) {
+            const uint32_t hb = hc >> (4u * lg * (uint32_t)half);
 #pragma unroll
-        for (int d = 0; d < kFlowDim; ++d) {
-            const uint32_t q = div_magic(hc, sc.nst_magic, sc.nst_shift);
-            const uint32_t digit = hc - q * sc.nst;
-            hc = q;
-            const int j = 4 * (d >> 3) + (d & 3);
-            if ((d >> 2) & 1) {
-                if (half) dig[j] = digit;
-            } else {
-                dig[j] = digit;
+            for (int j = 0; j < 8; ++j) dig[j] = (hb >> ((uint32_t)flow_axis(0, j) * lg)) & (sc.nst - 1u);
+        } else {
+#pragma unroll
+            for (int d = 0; d < kFlowDim; ++d) {
+                const uint32_t q = div_magic(hc, sc.nst_magic, sc.nst_shift);
+                const uint32_t digit = hc - q * sc.nst;
+                hc = q;
+                const int j = 4 * (d >> 3) + (d & 3);
+                if ((d >> 2) & 1) {
+                    if (half) dig[j] = digit;
+                } else {
+                    dig[j] = digit;
+                }
             }
         }
         // the stratified point y = (s 2^33 + 2r + 1) / (N_st 2^33) and

@@ -87,9 +87,15 @@ def roundtrip_bound(y):
     return 16 * 2.0 ** -24 * (z * z + 1.0) * m + 2.0 ** -25
 
 
-def test_flow_sample_parity(orc):
-    w = corr16()
-    say("[flow sample]")
+# N_st = 1 (every cube digit 0) and N_st = 2 (2^16 cubes: digits by shifts)
+STRATA_CASES = [(20_011, 1), (270_001, 2)]
+
+
+@pytest.mark.parametrize("n_eval,n_st", STRATA_CASES)
+def test_flow_sample_parity(orc, n_eval, n_st):
+    w = corr16(n_eval)
+    assert orc.strata(w.n_eval, w.dim, w.n_min, w.n_strat)[0] == n_st
+    say(f"[flow sample] n_eval {n_eval}, N_st {n_st}")
     v = make(w)
     th = random_theta(1)
     v.attach_flow(th.astype(np.float32))
@@ -111,13 +117,15 @@ def test_flow_sample_parity(orc):
     v.close()
 
 
-def test_library_init_is_identity(orc):
+@pytest.mark.parametrize("n_eval,n_st", STRATA_CASES)
+def test_library_init_is_identity(orc, n_eval, n_st):
     """The library's own starting weights (no parameters passed): W1 and W2
     inside +-1/sqrt(fan_in) and spread over it, the last layer zero; the warp
     is then the identity: log J_F = 0 exactly, and w = Phi(Phi^-1(y)) in
     FP32 equals y up to the roundings of the two FP32 functions."""
-    w = corr16()
-    say("[flow init]")
+    w = corr16(n_eval)
+    assert orc.strata(w.n_eval, w.dim, w.n_min, w.n_strat)[0] == n_st
+    say(f"[flow init] n_eval {n_eval}, N_st {n_st}")
     v = make(w)
     v.attach_flow(None, init_seed=7)
     th = v.flow_params().astype(np.float64)
