@@ -434,7 +434,9 @@ vegas_status run_update(vegas_ctx* c, int t, int n_slots, bool timed)
     return VEGAS_OK;
 }
 
-vegas_status flow_train_step(vegas_ctx* c);
+vegas_status flow_train_step(vegas_ctx* c, int slice = -1);
+hipError_t flow_step_sums(vegas_ctx* c, int n_steps);
+constexpr int kFlowSumSlices = 32;       // training steps of an iteration whose sums are taken together
 vegas_status flow_judge(vegas_ctx* c, int t, bool* keep);
 hipError_t judge_mark(vegas_ctx* c, int t, int end);
 
@@ -606,8 +608,13 @@ vegas_status run_iteration(vegas_ctx* c, bool integrate)
         }
         HIPCHK(c->fmark());
         if (keep && c->flow_on && c->fcfg.train) {
-            for (int st = 0; st < c->fcfg.steps_per_iter; ++st) {
-                const vegas_status s = flow_train_step(c);
+            // the sums of every step's slice in one launch (omega is fixed
+            // for the iteration), each step reading its own
+            const int n = c->fcfg.steps_per_iter;
+            const bool together = n <= kFlowSumSlices;
+            if (together) HIPCHK(flow_step_sums(c, n));
+            for (int st = 0; st < n; ++st) {
+                const vegas_status s = flow_train_step(c, together ? st : -1);
                 if (s != VEGAS_OK) return s;
             }
         }
@@ -1254,7 +1261,7 @@ FlowPlan flow_plan(uint32_t n_eval, int n_wg)
     p.grad = take(sizeof(float) * kFParams);
     p.m = take(sizeof(float) * kFParams);
     p.v = take(sizeof(float) * kFParams);
-    p.sumsq = take(sizeof(double) * (1 + 256));
+    p.sumsq = take(sizeof(double) * kFlowSumRecord * kFlowSumSlices);
     p.acc = take(sizeof(float) * kFParams);
     p.total = o;
     return p;
@@ -1288,10 +1295,34 @@ FlowTrainArgs flow_train_args(vegas_ctx* c, uint32_t stride, uint32_t off)
     return a;
 }
 
-// gradient of the warp's loss on the last warped iteration's samples
-// off, off + stride, ...; with adam set, the Adam step on it too
-vegas_status flow_gradient(vegas_ctx* c, uint32_t stride, uint32_t off, const FlowAdamArgs* adam)
+uint32_t flow_train_stride(const vegas_ctx* c)
 {
+    return (uint32_t)std::min<int64_t>(c->fcfg.train_stride, c->g.n_eval);
+}
+
+// the sums of the next n_steps training steps' slices (flow_train_step's
+// offsets), one record each
+hipError_t flow_step_sums(vegas_ctx* c, int n_steps)
+{
+    const uint32_t stride = flow_train_stride(c);
+    return launch_flow_sums(reinterpret_cast<const float*>(c->fws + c->f_om), (uint32_t)c->g.n_eval, stride,
+                            (uint32_t)(c->f_step % stride), n_steps, c->fcfg.loss == 1 ? 1 : 2,
+                            reinterpret_cast<double*>(c->fws + c->f_sumsq), c->stream);
+}
+
+// gradient of the warp's loss on the last warped iteration's samples
+// off, off + stride, ...; with adam set, the Adam step on it too.  slice:
+// the record of flow_step_sums holding this slice's sums, or -1 to take
+// them here.
+vegas_status flow_gradient(vegas_ctx* c, uint32_t stride, uint32_t off, const FlowAdamArgs* adam, int slice = -1)
+{
+    FlowTrainArgs a = flow_train_args(c, stride, off);
+    double* sums = reinterpret_cast<double*>(c->fws + c->f_sumsq);
+    if (slice < 0) {
+        HIPCHK(launch_flow_sums(a.om, (uint32_t)c->g.n_eval, stride, off, 1, a.gamma, sums, c->stream));
+    } else {
+        a.sumsq = sums + (size_t)slice * kFlowSumRecord;
+    }
     hipEvent_t* ev = nullptr;
     if (c->f_timing) {
         for (int i = 0; i < 2; ++i) {
@@ -1301,7 +1332,7 @@ vegas_status flow_gradient(vegas_ctx* c, uint32_t stride, uint32_t off, const Fl
         }
         ev = c->f_gev.data() + c->f_gev.size() - 2;
     }
-    HIPCHK(launch_flow_gradient(flow_train_args(c, stride, off), c->f_nwg, reinterpret_cast<float*>(c->fws + c->f_G0),
+    HIPCHK(launch_flow_gradient(a, c->f_nwg, reinterpret_cast<float*>(c->fws + c->f_G0),
                                 reinterpret_cast<float*>(c->fws + c->f_G1), reinterpret_cast<float*>(c->fws + c->f_grad),
                                 reinterpret_cast<float*>(c->fws + c->f_seg), adam, c->stream, ev));
     return VEGAS_OK;
@@ -1438,11 +1469,12 @@ vegas_status flow_judge(vegas_ctx* c, int t, bool* keep)
     return VEGAS_OK;
 }
 
-// one training step: gradient, Adam and the BF16 repack
-vegas_status flow_train_step(vegas_ctx* c)
+// one training step: gradient, Adam and the BF16 repack; slice as in
+// flow_gradient
+vegas_status flow_train_step(vegas_ctx* c, int slice)
 {
     // a strided subset of the samples, its offset turning with the steps
-    const uint32_t stride = (uint32_t)std::min<int64_t>(c->fcfg.train_stride, c->g.n_eval);
+    const uint32_t stride = flow_train_stride(c);
     float* th = reinterpret_cast<float*>(c->fws + c->f_theta);
     FlowAdamArgs adam;
     adam.theta = th;
@@ -1451,7 +1483,7 @@ vegas_status flow_train_step(vegas_ctx* c)
     adam.packed = c->fws + c->f_packed;
     adam.lr = c->fcfg.lr;
     adam.step = (int)(c->f_step + 1);
-    vegas_status s = flow_gradient(c, stride, (uint32_t)(c->f_step % stride), &adam);
+    vegas_status s = flow_gradient(c, stride, (uint32_t)(c->f_step % stride), &adam, slice);
     if (s != VEGAS_OK) return s;
     c->f_step += 1;
     return VEGAS_OK;

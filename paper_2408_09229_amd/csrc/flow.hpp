@@ -182,6 +182,11 @@ struct FlowTrainArgs {
 
 // Adam step fused into the gradient's last reduction (training), or none
 // (the gradient alone)
+// sums of |omega|^gamma of one training step's slice: the total, then 256
+// block partials (doubles)
+constexpr int kFlowSumBlocks = 256;
+constexpr int kFlowSumRecord = 1 + kFlowSumBlocks;
+
 struct FlowAdamArgs {
     float* theta;                 // null: the gradient alone
     float* m;

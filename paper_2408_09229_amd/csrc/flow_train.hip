@@ -35,14 +35,19 @@
 namespace vg {
 
 constexpr int kSumThreads = 256;
-constexpr int kSumBlocks = 256;
+constexpr int kSumBlocks = kFlowSumBlocks;
 
-// sum of |omega|^gamma, gamma = 2 (variance loss) or 1 (KL loss): block
-// partials (strided samples), then the partials in block order
-__global__ __launch_bounds__(kSumThreads) void k_flow_sumsq(const float* om, uint32_t n, uint32_t stride, uint32_t off,
-                                                            int gamma, double* part)
+// sum of |omega|^gamma, gamma = 2 (variance loss) or 1 (KL loss), over the
+// samples off, off + stride, ... of each slice y = blockIdx.y (off =
+// (off0 + y) mod stride): block partials (strided samples) into
+// part[y kFlowSumRecord + 1 + block], which the gradient kernel adds in
+// block order
+__global__ __launch_bounds__(kSumThreads) void k_flow_sumsq(const float* om, uint32_t n_eval, uint32_t stride,
+                                                            uint32_t off0, int gamma, double* part)
 {
     __shared__ double red[kSumThreads];
+    const uint32_t off = (off0 + blockIdx.y) % stride;
+    const uint32_t n = (n_eval - off + stride - 1) / stride;
     double s = 0.0;
     for (uint32_t i = blockIdx.x * kSumThreads + threadIdx.x; i < n; i += kSumThreads * kSumBlocks) {
         const double v = fabs((double)om[(size_t)off + (size_t)i * stride]);
@@ -54,12 +59,9 @@ __global__ __launch_bounds__(kSumThreads) void k_flow_sumsq(const float* om, uin
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[1 + blockIdx.x] = red[0];
+    if (threadIdx.x == 0) part[(size_t)blockIdx.y * kFlowSumRecord + 1 + blockIdx.x] = red[0];
 }
 
-// ---------------------------------------------------------------------------
-// inverse pass
-// ---------------------------------------------------------------------------
 // c_k of a training sample in double, rounded to FP32: tiny weights (an
 // integrand that underflows almost everywhere) put 1/sum beyond FP32
 __device__ __forceinline__ float train_coef(const FlowTrainArgs& a, uint32_t k, bool valid, double ss)
@@ -523,12 +525,17 @@ void adam_corrections(int step, float* c1, float* c2)
 }
 }  // namespace
 
+hipError_t launch_flow_sums(const float* om, uint32_t n_eval, uint32_t stride, uint32_t off0, int n_slices,
+                            int gamma, double* sumsq, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_flow_sumsq, dim3(kSumBlocks, n_slices), dim3(kSumThreads), 0, st, om, n_eval, stride, off0,
+                       gamma, sumsq);
+    return hipGetLastError();
+}
+
 hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, float* G1, float* grad,
                                 float* seg, const FlowAdamArgs* adam, hipStream_t st, hipEvent_t* ev)
 {
-    double* ss = const_cast<double*>(base.sumsq);
-    hipLaunchKernelGGL(k_flow_sumsq, dim3(kSumBlocks), dim3(kSumThreads), 0, st, base.om, base.n, base.stride,
-                       base.off, base.gamma, ss);
     // one launch totals those sums, runs the inverse pass (u_1..u_3, and
     // dL/du_0 into G1) and every layer's backward pass, alternating G1 and G0
     FlowTrainArgs a = base;

@@ -86,8 +86,15 @@ hipError_t launch_mfma_probe(const float* A, const float* B, float* D, hipStream
 hipError_t launch_flow_sample(const FlowSampleArgs& a, int n_wg, hipStream_t st);
 hipError_t launch_fill_flow(const FillArgs& a, const float* w, const float* lj, float* om, int n_wg, size_t lds,
                             hipStream_t st);
-// ev: null, or two events recorded on st just before and after the
-// gradient kernel (its own duration)
+// Block partials of sum |omega|^gamma for n_slices slices of the samples,
+// slice y holding off, off + stride, ... with off = (off0 + y) mod stride:
+// sumsq[y kFlowSumRecord + 1 ..], one slice's record per training step.
+hipError_t launch_flow_sums(const float* om, uint32_t n_eval, uint32_t stride, uint32_t off0, int n_slices,
+                            int gamma, double* sumsq, hipStream_t st);
+// One training step on the slice base.off, base.stride, whose sums'
+// partials base.sumsq holds (launch_flow_sums).  ev: null, or two events
+// recorded on st just before and after the gradient kernel (its own
+// duration)
 hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, float* G1, float* grad,
                                 float* seg, const FlowAdamArgs* adam, hipStream_t st, hipEvent_t* ev = nullptr);
 hipError_t launch_flow_adam(float* theta, const float* grad, float* m, float* v, float lr, int step, hipStream_t st);
