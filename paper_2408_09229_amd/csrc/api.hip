@@ -281,7 +281,6 @@ struct vegas_ctx {
     int f_nwg = 0;                     // workgroups of the training passes
     int f_step = 0;                    // Adam steps taken
     size_t f_acc = 0;                  // last accepted parameters
-    size_t f_seg = 0;                  // segment sums of the gradient reduction
     int n_cus = 1;
     bool fused = false;                // small problem: one launch after the fill
     std::vector<uint8_t> warped;       // per iteration: 0 plain, 1 through the warp, 2 plain control
@@ -1235,7 +1234,7 @@ vegas_status vegas_sample_probe(vegas_ctx* c, uint32_t t, uint64_t k0, int64_t n
 namespace {
 
 struct FlowPlan {
-    size_t theta, packed, w, z, lj, om, U, G0, G1, part, seg, grad, m, v, sumsq, acc, total;
+    size_t theta, packed, w, z, lj, om, U, G0, G1, part, grad, m, v, sumsq, acc, total;
 };
 
 FlowPlan flow_plan(uint32_t n_eval, int n_wg)
@@ -1257,7 +1256,6 @@ FlowPlan flow_plan(uint32_t n_eval, int n_wg)
     p.G0 = take(sizeof(float) * kFlowDim * (size_t)n_eval);
     p.G1 = take(sizeof(float) * kFlowDim * (size_t)n_eval);
     p.part = take(sizeof(float) * kFParams * (size_t)n_wg);
-    p.seg = take(sizeof(float) * kFParams * 16);
     p.grad = take(sizeof(float) * kFParams);
     p.m = take(sizeof(float) * kFParams);
     p.v = take(sizeof(float) * kFParams);
@@ -1271,7 +1269,7 @@ FlowPlan flow_plan(uint32_t n_eval, int n_wg)
 int flow_train_wg(const vegas_ctx* c)
 {
     const int chunks = (int)((c->g.n_eval + 127) / 128);
-    return std::max(1, std::min(c->n_cus, chunks));
+    return std::max(1, std::min({c->n_cus, chunks, kFlowMaxTrainWG}));
 }
 
 // the training samples are off, off + stride, ... of the iteration's samples
@@ -1334,7 +1332,7 @@ vegas_status flow_gradient(vegas_ctx* c, uint32_t stride, uint32_t off, const Fl
     }
     HIPCHK(launch_flow_gradient(a, c->f_nwg, reinterpret_cast<float*>(c->fws + c->f_G0),
                                 reinterpret_cast<float*>(c->fws + c->f_G1), reinterpret_cast<float*>(c->fws + c->f_grad),
-                                reinterpret_cast<float*>(c->fws + c->f_seg), adam, c->stream, ev));
+                                adam, c->stream, ev));
     return VEGAS_OK;
 }
 
@@ -1565,7 +1563,6 @@ vegas_status vegas_flow_attach(vegas_ctx* c, const vegas_flow_config* cfg, const
     c->f_v = p.v;
     c->f_sumsq = p.sumsq;
     c->f_acc = p.acc;
-    c->f_seg = p.seg;
     c->f_nwg = nwg;
     c->f_step = 0;
     c->flow_attached = true;

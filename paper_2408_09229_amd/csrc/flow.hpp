@@ -186,6 +186,9 @@ struct FlowTrainArgs {
 // block partials (doubles)
 constexpr int kFlowSumBlocks = 256;
 constexpr int kFlowSumRecord = 1 + kFlowSumBlocks;
+// workgroups of the training kernel at most (their partial gradients are
+// summed by a fixed-order reduction sized for this many)
+constexpr int kFlowMaxTrainWG = 256;
 
 struct FlowAdamArgs {
     float* theta;                 // null: the gradient alone

@@ -20,9 +20,9 @@
 //                   delta^T activation run on MFMA with every activation
 //                   and delta in registers, each wave summing its samples,
 //                   the waves added in LDS
-//   k_flow_reduce_seg, k_flow_update  per-workgroup gradients summed in a
-//                   fixed order, Adam on the FP32 parameters and their BF16
-//                   repacking
+//   k_flow_update   per-workgroup gradients summed in a fixed order, and
+//                   Adam on the FP32 parameters
+//   k_flow_pack     (flow.hip) their BF16 repacking
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -457,23 +457,6 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_grad(FlowTrainArgs a)
     grad_layer<3>(a, S, gbuf, ss);
 }
 
-// per-workgroup gradients summed in a fixed order: segments of consecutive
-// workgroups first (one thread per parameter and segment), then the
-// segments in order
-constexpr int kRedSegs = 16;
-
-__global__ void k_flow_reduce_seg(const float* part, int n_wg, float* seg)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= kFParams) return;
-    const int per = (n_wg + kRedSegs - 1) / kRedSegs;
-    const int w0 = blockIdx.y * per;
-    const int w1 = min(w0 + per, n_wg);
-    float s = 0.f;
-    for (int w = w0; w < w1; ++w) s += part[(size_t)w * kFParams + i];
-    seg[(size_t)blockIdx.y * kFParams + i] = s;
-}
-
 __device__ __forceinline__ float adam_update(float* theta, float* m, float* v, int i, float gi, float lr, float c1,
                                              float c2)
 {
@@ -486,23 +469,48 @@ __device__ __forceinline__ float adam_update(float* theta, float* m, float* v, i
     return t;
 }
 
-constexpr int kUpdThreads = 256;
-constexpr int kUpdBlocks = (kFParams + kUpdThreads - 1) / kUpdThreads;
+// The per-workgroup gradients summed in a fixed order into grad: 64
+// parameters per workgroup of 1024 threads, each parameter summed by 16
+// threads over every 16th workgroup's part (so that each load instruction
+// reads 64 consecutive parameters, and a thread's 16 loads are all in
+// flight at once), the 16 sums added in LDS in a fixed order; with adam
+// set, the Adam step on it too.  (Two launches before: segments of 16
+// workgroups, then the segments, 6.8 + 4.9 us; one launch with 4 threads
+// per parameter looping over 64 workgroups each took 18.8 us.)  The BF16
+// repacking follows as a launch of its own over every layer's entries at
+// once (done inside this kernel by the last workgroup to finish each layer,
+// it made the kernel 16-20 us long).
+constexpr int kUpdSplit = 16;
+constexpr int kUpdParams = 64;
+constexpr int kUpdPer = 16;                    // workgroup parts per thread
+constexpr int kUpdMaxWG = kUpdSplit * kUpdPer;
+constexpr int kUpdBlocks = (kFParams + kUpdParams - 1) / kUpdParams;
+static_assert(kUpdMaxWG >= kFlowMaxTrainWG, "one part per training workgroup");
 
-// The segments in order into grad, one thread per parameter; with adam set,
-// the Adam step on it too.  The BF16 repacking follows as a launch of its
-// own over every layer's entries at once (done inside this kernel by the
-// last workgroup to finish each layer, it made the kernel 16-20 us long,
-// against 9 for the two launches).
-__global__ __launch_bounds__(kUpdThreads) void k_flow_update(const float* seg, float* grad, FlowAdamArgs adam,
-                                                             float c1, float c2)
+__global__ __launch_bounds__(kUpdSplit * kUpdParams) void k_flow_update(const float* part, int n_wg, float* grad,
+                                                                        FlowAdamArgs adam, float c1, float c2)
 {
-    const int i = blockIdx.x * kUpdThreads + threadIdx.x;
-    if (i >= kFParams) return;
+    __shared__ float red[kUpdSplit][kUpdParams];
+    const int lp = threadIdx.x % kUpdParams;
+    const int q = threadIdx.x / kUpdParams;
+    const int i = blockIdx.x * kUpdParams + lp;
+    float v[kUpdPer];
+#pragma unroll
+    for (int j = 0; j < kUpdPer; ++j) {
+        const int w = q + kUpdSplit * j;
+        v[j] = i < kFParams && w < n_wg ? part[(size_t)w * kFParams + i] : 0.f;
+    }
     float s = 0.f;
-    for (int g = 0; g < kRedSegs; ++g) s += seg[(size_t)g * kFParams + i];
-    grad[i] = s;
-    if (adam.theta) (void)adam_update(adam.theta, adam.m, adam.v, i, s, adam.lr, c1, c2);
+#pragma unroll
+    for (int j = 0; j < kUpdPer; ++j) s += v[j];
+    red[q][lp] = s;
+    __syncthreads();
+    if (q != 0 || i >= kFParams) return;
+    float g = 0.f;
+#pragma unroll
+    for (int t = 0; t < kUpdSplit; ++t) g += red[t][lp];
+    grad[i] = g;
+    if (adam.theta) (void)adam_update(adam.theta, adam.m, adam.v, i, g, adam.lr, c1, c2);
 }
 
 __global__ void k_flow_adam(float* theta, const float* grad, float* m, float* v, float lr, float c1, float c2)
@@ -534,7 +542,7 @@ hipError_t launch_flow_sums(const float* om, uint32_t n_eval, uint32_t stride, u
 }
 
 hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, float* G1, float* grad,
-                                float* seg, const FlowAdamArgs* adam, hipStream_t st, hipEvent_t* ev)
+                                const FlowAdamArgs* adam, hipStream_t st, hipEvent_t* ev)
 {
     // one launch totals those sums, runs the inverse pass (u_1..u_3, and
     // dL/du_0 into G1) and every layer's backward pass, alternating G1 and G0
@@ -550,13 +558,12 @@ hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, 
         const hipError_t r = hipEventRecord(ev[1], st);
         if (r != hipSuccess) return r;
     }
-    hipLaunchKernelGGL(k_flow_reduce_seg, dim3((kFParams + 255) / 256, kRedSegs), dim3(256), 0, st,
-                       (const float*)a.part, n_wg, seg);
+    if (n_wg > kUpdMaxWG) return hipErrorInvalidValue;
     FlowAdamArgs none = {};
     float c1 = 0.f, c2 = 0.f;
     if (adam) adam_corrections(adam->step, &c1, &c2);
-    hipLaunchKernelGGL(k_flow_update, dim3(kUpdBlocks), dim3(kUpdThreads), 0, st, (const float*)seg, grad,
-                       adam ? *adam : none, c1, c2);
+    hipLaunchKernelGGL(k_flow_update, dim3(kUpdBlocks), dim3(kUpdSplit * kUpdParams), 0, st, (const float*)a.part,
+                       n_wg, grad, adam ? *adam : none, c1, c2);
     if (adam) return launch_flow_pack(adam->theta, adam->packed, st);
     return hipGetLastError();
 }

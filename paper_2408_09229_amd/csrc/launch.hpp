@@ -96,7 +96,7 @@ hipError_t launch_flow_sums(const float* om, uint32_t n_eval, uint32_t stride, u
 // recorded on st just before and after the gradient kernel (its own
 // duration)
 hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, float* G1, float* grad,
-                                float* seg, const FlowAdamArgs* adam, hipStream_t st, hipEvent_t* ev = nullptr);
+                                const FlowAdamArgs* adam, hipStream_t st, hipEvent_t* ev = nullptr);
 hipError_t launch_flow_adam(float* theta, const float* grad, float* m, float* v, float lr, int step, hipStream_t st);
 
 constexpr int kAllocThreads = 1024;
