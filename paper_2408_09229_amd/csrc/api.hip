@@ -277,7 +277,7 @@ struct vegas_ctx {
     vegas_flow_config fcfg{};
     unsigned char* fws = nullptr;
     size_t f_theta = 0, f_packed = 0, f_w = 0, f_z = 0, f_lj = 0, f_om = 0, f_U = 0, f_G0 = 0, f_G1 = 0, f_part = 0,
-           f_grad = 0, f_m = 0, f_v = 0, f_sumsq = 0;
+           f_grad = 0, f_m = 0, f_v = 0, f_sumsq = 0, f_slots = 0;
     int f_nwg = 0;                     // workgroups of the training passes
     int f_step = 0;                    // Adam steps taken
     size_t f_acc = 0;                  // last accepted parameters
@@ -1234,8 +1234,36 @@ vegas_status vegas_sample_probe(vegas_ctx* c, uint32_t t, uint64_t k0, int64_t n
 namespace {
 
 struct FlowPlan {
-    size_t theta, packed, w, z, lj, om, U, G0, G1, part, grad, m, v, sumsq, acc, total;
+    size_t theta, packed, slots, w, z, lj, om, U, G0, G1, part, grad, m, v, sumsq, acc, total;
 };
+
+// Each weight's forward and backward BF16 copy in the packed operands
+// (value index, -1 none), from the packing's source map, which must give
+// every weight exactly one of each and the biases none (checked once).
+const std::vector<int32_t>* flow_slot_table()
+{
+    static const std::vector<int32_t> table = [] {
+        std::vector<int32_t> t(2 * (size_t)kFParams, -1);
+        std::vector<int> count(2 * (size_t)kFParams, 0);
+        for (int l = 0; l < kFlowLayers; ++l)
+            for (int r = 0; r < kPLayer; ++r)
+                for (int j = 0; j < 8; ++j) {
+                    const int src = flow_pack_src(l, r, j);
+                    if (src < 0) continue;
+                    const size_t at = 2 * ((size_t)l * kFLayer + src) + (r >= kPFwdT ? 1 : 0);
+                    t[at] = (int32_t)(((size_t)l * kPLayer + r) * 8 + j);
+                    count[at] += 1;
+                }
+        for (int l = 0; l < kFlowLayers; ++l)
+            for (int i = 0; i < kFLayer; ++i) {
+                const bool bias = (i >= kFB1 && i < kFW2) || (i >= kFB2 && i < kFW3) || i >= kFB3;
+                for (int d = 0; d < 2; ++d)
+                    if (count[2 * ((size_t)l * kFLayer + i) + d] != (bias ? 0 : 1)) return std::vector<int32_t>();
+            }
+        return t;
+    }();
+    return table.empty() ? nullptr : &table;
+}
 
 FlowPlan flow_plan(uint32_t n_eval, int n_wg)
 {
@@ -1248,6 +1276,7 @@ FlowPlan flow_plan(uint32_t n_eval, int n_wg)
     };
     p.theta = take(sizeof(float) * kFParams);
     p.packed = take((size_t)16 * kFlowLayers * kPLayer);
+    p.slots = take(sizeof(int32_t) * 2 * kFParams);
     p.w = take(sizeof(float) * kFlowDim * (size_t)n_eval);
     p.z = take(sizeof(float) * kFlowDim * (size_t)n_eval);
     p.lj = take(sizeof(float) * (size_t)n_eval);
@@ -1479,6 +1508,7 @@ vegas_status flow_train_step(vegas_ctx* c, int slice)
     adam.m = reinterpret_cast<float*>(c->fws + c->f_m);
     adam.v = reinterpret_cast<float*>(c->fws + c->f_v);
     adam.packed = c->fws + c->f_packed;
+    adam.slots = reinterpret_cast<const int32_t*>(c->fws + c->f_slots);
     adam.lr = c->fcfg.lr;
     adam.step = (int)(c->f_step + 1);
     vegas_status s = flow_gradient(c, stride, (uint32_t)(c->f_step % stride), &adam, slice);
@@ -1550,6 +1580,7 @@ vegas_status vegas_flow_attach(vegas_ctx* c, const vegas_flow_config* cfg, const
     c->fws = (unsigned char*)d_ws;
     c->f_theta = p.theta;
     c->f_packed = p.packed;
+    c->f_slots = p.slots;
     c->f_w = p.w;
     c->f_z = p.z;
     c->f_lj = p.lj;
@@ -1570,6 +1601,10 @@ vegas_status vegas_flow_attach(vegas_ctx* c, const vegas_flow_config* cfg, const
     HIPCHK(launch_reset(reinterpret_cast<unsigned long long*>(c->fws + p.m), kFParams / 2, c->stream));
     HIPCHK(launch_reset(reinterpret_cast<unsigned long long*>(c->fws + p.v), kFParams / 2, c->stream));
     HIPCHK(launch_reset(reinterpret_cast<unsigned long long*>(c->fws + p.om), (int)((c->g.n_eval + 1) / 2), c->stream));
+    const std::vector<int32_t>* slots = flow_slot_table();
+    if (!slots) return fail(VEGAS_EUNSUPPORTED, "warp operand packing: a weight without exactly one copy per direction");
+    HIPCHK(hipMemcpyAsync(c->fws + p.slots, slots->data(), sizeof(int32_t) * slots->size(), hipMemcpyHostToDevice,
+                          c->stream));
     if (params) return vegas_flow_set_params(c, params);
     // the library's own starting weights
     float* th = reinterpret_cast<float*>(c->fws + c->f_theta);

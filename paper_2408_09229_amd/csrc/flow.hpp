@@ -132,6 +132,53 @@ __host__ __device__ inline int flow_dx_row(int l, int m)
     return flow_pos(l, c);
 }
 
+// Source of value j of entry r of layer l's packed operands: the offset of
+// the layer parameter it copies, or -1 for a constant 0, -2 for a constant
+// 1 (the 0/1 transposes P and I).  Every weight has exactly one forward
+// (F1, T2, T3) and one backward (U3, U2, U1) copy; biases have none.
+__host__ __device__ inline int flow_pack_src(int l, int r, int j)
+{
+    const int lane = r & 63;
+    const int h = lane >> 5;              // k half of this lane
+    const int n32 = lane & 31;            // its row (A operand) or column (B operand)
+    if (r < kPT2) {                       // F1[mt]: W1[unit][pos(axis of (h, j))], axes in A
+        const int m = (r >> 6) * 32 + n32;
+        const int c = flow_axis(h, j);
+        return flow_in_a(l, c) ? kFW1 + m * kFlowHalf + flow_pos(l, c) : -1;
+    }
+    if (r < kPT3) {                       // T2[mt][ks]: W2[unit2][unit1(ks, k)]
+        r -= kPT2;
+        const int m = (r >> 8) * 32 + n32, ks = (r >> 6) & 3;
+        return kFW2 + m * kFlowHidden + flow_t_unit(ks, h, j);
+    }
+    if (r < kPU3) {                       // T3[ks]: W3[row(m)][unit2(ks, k)]
+        r -= kPT3;
+        const int o = flow_t3_row(l, n32);
+        return o >= 0 ? kFW3 + o * kFlowHidden + flow_t_unit(r >> 6, h, j) : -1;
+    }
+    if (r < kPU2) {                       // U3[mt][ks]: W3[row(k)][unit2 = m]
+        r -= kPU3;
+        const int m = (r >> 7) * 32 + n32, ks = (r >> 6) & 1;
+        const int o = flow_t3_row(l, flow_t_unit(ks, h, j));
+        return o >= 0 ? kFW3 + o * kFlowHidden + m : -1;
+    }
+    if (r < kPU1) {                       // U2[mt][ks]: W2[unit2(ks, k)][unit1 = m]
+        r -= kPU2;
+        const int m = (r >> 8) * 32 + n32, ks = (r >> 6) & 3;
+        return kFW2 + flow_t_unit(ks, h, j) * kFlowHidden + m;
+    }
+    if (r < kPP) {                        // U1[ks]: W1[unit1(ks, k)][pos of row m's axis]
+        r -= kPU1;
+        const int p = flow_dx_row(l, n32);
+        return p >= 0 ? kFW1 + flow_t_unit(r >> 6, h, j) * kFlowHalf + p : -1;
+    }
+    if (r < kPI) {                        // P[ks]: 1 where T3's row (ks, k) carries output n
+        r -= kPP;
+        return flow_t3_row(l, flow_t_unit(r >> 6, h, j)) == n32 ? -2 : -1;
+    }
+    return flow_axis(h, j) == n32 ? -2 : -1;   // I: 1 where the axis of (h, j) is column n
+}
+
 // the lane's 8 axes of a sample's 16 values (row: the sample's first value)
 __host__ __device__ inline void flow_lane_load(const float* row, int half, float (&v)[8])
 {
@@ -195,6 +242,8 @@ struct FlowAdamArgs {
     float* m;
     float* v;
     void* packed;                 // repacked BF16 operands
+    const int* slots;             // [n_params][2]: each weight's forward and backward BF16 copy in packed
+                                  // (value index, -1 none); null: repack every entry after the step
     float lr;
     int step;                     // counts from 1
 };

@@ -125,53 +125,11 @@ __device__ __forceinline__ float flow_phi_inv(float m, bool upper)
 // parameters P (global memory or LDS).
 __device__ inline bf16x8 flow_pack_entry(int l, int r, const float* __restrict__ P)
 {
-    const float* W1 = P + kFW1;
-    const float* W2 = P + kFW2;
-    const float* W3 = P + kFW3;
-    const int lane = r & 63;
-    const int h = lane >> 5;              // k half of this lane
-    const int n32 = lane & 31;            // its row (A operand) or column (B operand)
-    float v[8];
-    if (r < kPT2) {                       // F1[mt]: W1[unit][pos(axis of (h, j))], axes in A
-        const int m = (r >> 6) * 32 + n32;
-        for (int j = 0; j < 8; ++j) {
-            const int c = flow_axis(h, j);
-            v[j] = flow_in_a(l, c) ? W1[m * kFlowHalf + flow_pos(l, c)] : 0.f;
-        }
-    } else if (r < kPT3) {                // T2[mt][ks]: W2[unit2][unit1(ks, k)]
-        r -= kPT2;
-        const int m = (r >> 8) * 32 + n32, ks = (r >> 6) & 3;
-        for (int j = 0; j < 8; ++j) v[j] = W2[m * kFlowHidden + flow_t_unit(ks, h, j)];
-    } else if (r < kPU3) {                // T3[ks]: W3[row(m)][unit2(ks, k)]
-        r -= kPT3;
-        const int ks = r >> 6;
-        const int o = flow_t3_row(l, n32);
-        for (int j = 0; j < 8; ++j) v[j] = o >= 0 ? W3[o * kFlowHidden + flow_t_unit(ks, h, j)] : 0.f;
-    } else if (r < kPU2) {                // U3[mt][ks]: W3[row(k)][unit2 = m]
-        r -= kPU3;
-        const int m = (r >> 7) * 32 + n32, ks = (r >> 6) & 1;
-        for (int j = 0; j < 8; ++j) {
-            const int o = flow_t3_row(l, flow_t_unit(ks, h, j));
-            v[j] = o >= 0 ? W3[o * kFlowHidden + m] : 0.f;
-        }
-    } else if (r < kPU1) {                // U2[mt][ks]: W2[unit2(ks, k)][unit1 = m]
-        r -= kPU2;
-        const int m = (r >> 8) * 32 + n32, ks = (r >> 6) & 3;
-        for (int j = 0; j < 8; ++j) v[j] = W2[flow_t_unit(ks, h, j) * kFlowHidden + m];
-    } else if (r < kPP) {                 // U1[ks]: W1[unit1(ks, k)][pos of row m's axis]
-        r -= kPU1;
-        const int ks = r >> 6;
-        const int p = flow_dx_row(l, n32);
-        for (int j = 0; j < 8; ++j) v[j] = p >= 0 ? W1[flow_t_unit(ks, h, j) * kFlowHalf + p] : 0.f;
-    } else if (r < kPI) {                 // P[ks]: 1 where T3's row (ks, k) carries output n
-        r -= kPP;
-        const int ks = r >> 6;
-        for (int j = 0; j < 8; ++j) v[j] = flow_t3_row(l, flow_t_unit(ks, h, j)) == n32 ? 1.f : 0.f;
-    } else {                              // I: 1 where the axis of (h, j) is column n
-        for (int j = 0; j < 8; ++j) v[j] = flow_axis(h, j) == n32 ? 1.f : 0.f;
-    }
     bf16x8 o;
-    for (int j = 0; j < 8; ++j) o[j] = (__bf16)v[j];
+    for (int j = 0; j < 8; ++j) {
+        const int src = flow_pack_src(l, r, j);
+        o[j] = (__bf16)(src >= 0 ? P[src] : src == -2 ? 1.f : 0.f);
+    }
     return o;
 }
 

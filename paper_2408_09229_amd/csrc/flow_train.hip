@@ -20,9 +20,11 @@
 //                   delta^T activation run on MFMA with every activation
 //                   and delta in registers, each wave summing its samples,
 //                   the waves added in LDS
-//   k_flow_update   per-workgroup gradients summed in a fixed order, and
-//                   Adam on the FP32 parameters
-//   k_flow_pack     (flow.hip) their BF16 repacking
+//   k_flow_update   per-workgroup gradients summed in a fixed order, Adam
+//                   on the FP32 parameters, and each weight's two BF16
+//                   copies in the packed operands written in place (the
+//                   full repack, k_flow_pack in flow.hip, runs when the
+//                   parameters are set)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -474,12 +476,12 @@ __device__ __forceinline__ float adam_update(float* theta, float* m, float* v, i
 // threads over every 16th workgroup's part (so that each load instruction
 // reads 64 consecutive parameters, and a thread's 16 loads are all in
 // flight at once), the 16 sums added in LDS in a fixed order; with adam
-// set, the Adam step on it too.  (Two launches before: segments of 16
-// workgroups, then the segments, 6.8 + 4.9 us; one launch with 4 threads
-// per parameter looping over 64 workgroups each took 18.8 us.)  The BF16
-// repacking follows as a launch of its own over every layer's entries at
-// once (done inside this kernel by the last workgroup to finish each layer,
-// it made the kernel 16-20 us long).
+// set, the Adam step on it too, and with adam.slots the weight's two BF16
+// copies written in place (else a full repack follows: a launch of its
+// own, 4.8 us; done inside this kernel by the last workgroup to finish each
+// layer, it made the kernel 16-20 us long).  (Two launches before: segments
+// of 16 workgroups, then the segments, 6.8 + 4.9 us; one launch with 4
+// threads per parameter looping over 64 workgroups each took 18.8 us.)
 constexpr int kUpdSplit = 16;
 constexpr int kUpdParams = 64;
 constexpr int kUpdPer = 16;                    // workgroup parts per thread
@@ -510,7 +512,16 @@ __global__ __launch_bounds__(kUpdSplit * kUpdParams) void k_flow_update(const fl
 #pragma unroll
     for (int t = 0; t < kUpdSplit; ++t) g += red[t][lp];
     grad[i] = g;
-    if (adam.theta) (void)adam_update(adam.theta, adam.m, adam.v, i, g, adam.lr, c1, c2);
+    if (!adam.theta) return;
+    const float t = adam_update(adam.theta, adam.m, adam.v, i, g, adam.lr, c1, c2);
+    if (adam.slots) {
+        // the weight's two BF16 copies in the packed operands, in place
+        __bf16* pk = reinterpret_cast<__bf16*>(adam.packed);
+        const __bf16 b = (__bf16)t;
+        const int f = adam.slots[2 * i], k = adam.slots[2 * i + 1];
+        if (f >= 0) pk[f] = b;
+        if (k >= 0) pk[k] = b;
+    }
 }
 
 __global__ void k_flow_adam(float* theta, const float* grad, float* m, float* v, float lr, float c1, float c2)
@@ -564,7 +575,7 @@ hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, 
     if (adam) adam_corrections(adam->step, &c1, &c2);
     hipLaunchKernelGGL(k_flow_update, dim3(kUpdBlocks), dim3(kUpdSplit * kUpdParams), 0, st, (const float*)a.part,
                        n_wg, grad, adam ? *adam : none, c1, c2);
-    if (adam) return launch_flow_pack(adam->theta, adam->packed, st);
+    if (adam && !adam->slots) return launch_flow_pack(adam->theta, adam->packed, st);
     return hipGetLastError();
 }
 

@@ -291,6 +291,26 @@ def test_flow_grad_parity():
     v.close()
 
 
+def test_inplace_copies_equal_full_repack():
+    """Training steps write each updated weight's two BF16 copies into the
+    packed operands in place; those operands must equal a full repack of
+    the same parameters: the loss gradient (which runs on them) is the same
+    bit for bit before and after the parameters are loaded again."""
+    w = corr16()
+    say("[flow in-place repack]")
+    v = make(w)
+    v.attach_flow(None, lr=1e-2, train=True, steps_per_iter=4, init_seed=5)
+    v.enable_flow(True)
+    v.adapt(3)
+    g1 = v.flow_grad()
+    th = v.flow_params()
+    v.set_flow_params(th)
+    g2 = v.flow_grad()
+    assert np.all(np.isfinite(g1)) and np.any(g1 != 0)
+    assert np.array_equal(g1, g2)
+    v.close()
+
+
 def test_flow_training_gain():
     """Trained warp against plain VEGAS+ on a correlated 16-d Gaussian
     (s 0.2, rho 0.5), from the library's own starting weights: after 100
