@@ -487,8 +487,7 @@ def run_warp_compare(args, w):
     # and every layer's backward pass) over 1/stride of them, once per Adam
     # step; the roofline line names the one with the most time per
     # iteration, at its own per-launch duration.  The whole training (one
-    # sums launch, then three launches per Adam step) is reported beside
-    # them.
+    # sums launch, then two launches per Adam step) is reported beside them.
     samp_ms, train_ms, grad_ms = ft["sample_ms"], ft["train_ms"], ft["grad_launch_ms"]
     n_train = (w.n_eval + args.train_stride - 1) // args.train_stride
     kernels = {
@@ -502,8 +501,7 @@ def run_warp_compare(args, w):
                   "tflops": (f / (m / 1e3) / 1e12) if m else None,
                   "frac": (f / (m / 1e3) / 2.5e15) if m else None} for k, (f, m, n) in kernels.items()}
     tf = FLOW_TRAIN_FLOPS * n_train * args.flow_steps_final
-    phases["training (per iteration: k_flow_sumsq once, then k_flow_grad, k_flow_update and k_flow_pack "
-           "per Adam step)"] = {"ms": train_ms, "tflops": (tf / (train_ms / 1e3) / 1e12) if train_ms else None,
+    phases["training (per iteration: k_flow_sumsq once, then k_flow_grad and k_flow_update per Adam step)"] = {"ms": train_ms, "tflops": (tf / (train_ms / 1e3) / 1e12) if train_ms else None,
                                 "frac": (tf / (train_ms / 1e3) / 2.5e15) if train_ms else None}
     pl, wp = out["plain"], out["warp"]
     line = {
