@@ -1294,7 +1294,8 @@ FlowPlan flow_plan(uint32_t n_eval, int n_wg)
     return p;
 }
 
-// one training workgroup per CU (the backward kernel takes 94 KB of LDS)
+// one training workgroup per CU (the gradient kernel takes 129 KB of LDS),
+// at most the 256 whose parts the update kernel sums
 int flow_train_wg(const vegas_ctx* c)
 {
     const int chunks = (int)((c->g.n_eval + 127) / 128);
