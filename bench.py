@@ -78,7 +78,8 @@ WORKLOADS = {
 
 
 FILL_SOURCES = ["fill.hip", "fill_dev.hpp", "batch.hip", "sample.hpp", "common.hpp", "families.hpp", "layout.hpp"]
-FLOW_SOURCES = ["flow.hip", "flow_train.hip", "flow.hpp", "flow_dev.hpp", "common.hpp", "fill_dev.hpp", "layout.hpp"]
+FLOW_SOURCES = ["flow.hip", "flow_train.hip", "flow.hpp", "flow_dev.hpp", "common.hpp", "fill_dev.hpp", "layout.hpp",
+                "../build.py"]                 # its per-file code generation options
 
 
 def source_hash(files=FILL_SOURCES) -> str:
