@@ -29,6 +29,7 @@
 #include <stdint.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "flow.hpp"
 #include "flow_dev.hpp"
@@ -107,13 +108,17 @@ __device__ __forceinline__ float reg_sum(const f32x16& a)
 }
 
 // relu mask of a register-order tile: where the activation (BF16, k-steps
-// 2 t and 2 t + 1 of a register-order input) is positive
+// 2 t and 2 t + 1 of a register-order input) is positive.  The activations
+// come out of relu_bf16, so each is +0 or positive: positive exactly where
+// its 16 bits are not zero (one 16-bit compare, no conversion to FP32).
 __device__ __forceinline__ void mask_by(f32x16& d, const bf16x8& a0, const bf16x8& a1)
 {
+    typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+    const u16x8 b0 = __builtin_bit_cast(u16x8, a0), b1 = __builtin_bit_cast(u16x8, a1);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        if (!((float)a0[i] > 0.f)) d[i] = 0.f;
-        if (!((float)a1[i] > 0.f)) d[8 + i] = 0.f;
+        if (b0[i] == 0) d[i] = 0.f;
+        if (b1[i] == 0) d[8 + i] = 0.f;
     }
 }
 
@@ -126,8 +131,10 @@ struct LayerGrad {
 };
 
 // one layer's backward pass for the wave's 32 samples; g holds dL/du_l of
-// the lane's axes and receives dL/du_{l+1}
-template <int L>
+// the lane's axes and receives dL/du_{l+1}.  FIRST: the wave's first chunk
+// of the layer, whose sums start G (the products then start from the
+// constant zero, with no accumulator to clear).
+template <int L, bool FIRST>
 __device__ __forceinline__ void grad_chunk(const float (&u)[8], float (&g)[8], float coef, const bf16x8* __restrict__ W,
                                            const float* __restrict__ B, LayerGrad& G)
 {
@@ -229,7 +236,7 @@ __device__ __forceinline__ void grad_chunk(const float (&u)[8], float (&g)[8], f
             acc = mfma(dOb[ks], W[kPP + ks * 64 + lane], acc);
             rem = mfma(lo, W[kPP + ks * 64 + lane], rem);
         }
-        G.b3 += reg_sum(acc) + reg_sum(rem);
+        G.b3 = (FIRST ? 0.f : G.b3) + (reg_sum(acc) + reg_sum(rem));
         dOr[0] = to_bf16(acc, 0);
         dOr[1] = to_bf16(acc, 1);
     }
@@ -245,7 +252,7 @@ __device__ __forceinline__ void grad_chunk(const float (&u)[8], float (&g)[8], f
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) acc = mfma(dOb[ks], W[kPU3 + (nt * 2 + ks) * 64 + lane], acc);
         mask_by(acc, h2r[nt][0], h2r[nt][1]);
-        G.b2[nt] += reg_sum(acc);
+        G.b2[nt] = (FIRST ? 0.f : G.b2[nt]) + reg_sum(acc);
         dA2r[nt][0] = to_bf16(acc, 0);
         dA2r[nt][1] = to_bf16(acc, 1);
     }
@@ -255,7 +262,7 @@ __device__ __forceinline__ void grad_chunk(const float (&u)[8], float (&g)[8], f
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) acc = mfma(dA2[ks], W[kPU2 + (nt * 4 + ks) * 64 + lane], acc);
         mask_by(acc, h1r[nt][0], h1r[nt][1]);
-        G.b1[nt] += reg_sum(acc);
+        G.b1[nt] = (FIRST ? 0.f : G.b1[nt]) + reg_sum(acc);
         dA1r[nt][0] = to_bf16(acc, 0);
         dA1r[nt][1] = to_bf16(acc, 1);
     }
@@ -264,17 +271,20 @@ __device__ __forceinline__ void grad_chunk(const float (&u)[8], float (&g)[8], f
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) G.w3[nt] = mfma(dOr[ks], h2r[nt][ks], G.w3[nt]);
+        for (int ks = 0; ks < 2; ++ks)
+            G.w3[nt] = mfma(dOr[ks], h2r[nt][ks], FIRST && ks == 0 ? f32x16{} : G.w3[nt]);
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-            for (int ks = 0; ks < 2; ++ks) G.w2[mt][nt] = mfma(dA2r[mt][ks], h1r[nt][ks], G.w2[mt][nt]);
+            for (int ks = 0; ks < 2; ++ks)
+                G.w2[mt][nt] = mfma(dA2r[mt][ks], h1r[nt][ks], FIRST && ks == 0 ? f32x16{} : G.w2[mt][nt]);
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) G.w1[mt] = mfma(dA1r[mt][ks], xr[ks], G.w1[mt]);
+        for (int ks = 0; ks < 2; ++ks)
+            G.w1[mt] = mfma(dA1r[mt][ks], xr[ks], FIRST && ks == 0 ? f32x16{} : G.w1[mt]);
 }
 
 // this wave's gradient of layer L into its LDS slice (every entry written)
@@ -325,7 +335,10 @@ __device__ __forceinline__ void grad_to_lds(const LayerGrad& G, float* __restric
 }
 
 // layer L: every chunk of the workgroup, then its part of the gradient
-template <int L>
+// SINGLE: every wave has one chunk at most (the grid covers the samples),
+// so no gradient accumulator lives across chunks: the kernel then fits the
+// architectural registers.
+template <int L, bool SINGLE>
 __device__ void grad_layer(const FlowTrainArgs& a, FlowBwdLds& S, float* const (&gbuf)[2], double ss)
 {
     const int lane = threadIdx.x & 63;
@@ -352,22 +365,12 @@ __device__ void grad_layer(const FlowTrainArgs& a, FlowBwdLds& S, float* const (
     constexpr bool from_z = L == kFlowLayers - 1;
     const float* uin = from_z ? a.zf : a.U + (size_t)L * N * kFlowDim;
     LayerGrad G;
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        G.w3[t] = {};
-        G.w1[t] = {};
-        G.w2[t][0] = {};
-        G.w2[t][1] = {};
-        G.b2[t] = 0.f;
-        G.b1[t] = 0.f;
-    }
-    G.b3 = 0.f;
     const uint32_t chunks = (N + 31u) / 32u;
     const uint32_t n_waves = gridDim.x * kFlowWaves;
     // waves run independently: no barrier inside the loop.  A sample's
     // dL/du is written and read again by the same lane, as every layer maps
     // chunks to waves alike.
-    for (uint32_t chunk = blockIdx.x * kFlowWaves + wave; chunk < chunks; chunk += n_waves) {
+    auto run = [&](uint32_t chunk, auto first) {
         const uint32_t k = min(chunk * 32u + (uint32_t)n32, N - 1u);
         const bool valid = chunk * 32u + (uint32_t)n32 < N;
         // lanes past the end take u = 0 and g = 0 (finite: their zero
@@ -381,8 +384,26 @@ __device__ void grad_layer(const FlowTrainArgs& a, FlowBwdLds& S, float* const (
             for (int j = 0; j < 8; ++j) u[j] = g[j] = 0.f;
         }
         const float coef = train_coef(a, k, valid, ss);
-        grad_chunk<L>(u, g, coef, S.w, S.b, G);
+        grad_chunk<L, decltype(first)::value>(u, g, coef, S.w, S.b, G);
         if (valid) flow_lane_store(g_out + (size_t)k * kFlowDim, half, g);
+    };
+    const uint32_t c0 = blockIdx.x * kFlowWaves + wave;
+    if (c0 < chunks) {
+        run(c0, std::true_type{});
+        if (!SINGLE)
+            for (uint32_t chunk = c0 + n_waves; chunk < chunks; chunk += n_waves) run(chunk, std::false_type{});
+    } else {
+        // no chunk: a zero gradient
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            G.w3[t] = {};
+            G.w1[t] = {};
+            G.w2[t][0] = {};
+            G.w2[t][1] = {};
+            G.b2[t] = 0.f;
+            G.b1[t] = 0.f;
+        }
+        G.b3 = 0.f;
     }
     grad_to_lds<L>(G, S.red[wave]);
     __syncthreads();
@@ -446,6 +467,7 @@ __device__ double inverse_pass(const FlowTrainArgs& a, FlowBwdLds& S, float* g0)
     return ss;
 }
 
+template <bool SINGLE>
 __global__ __launch_bounds__(kFlowThreads) void k_flow_grad(FlowTrainArgs a)
 {
     __shared__ FlowBwdLds S;
@@ -453,10 +475,10 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow_grad(FlowTrainArgs a)
     // pass leaves dL/du_0 in g_in
     float* const gbuf[2] = {const_cast<float*>(a.g_in), a.g_out};
     const double ss = inverse_pass(a, S, gbuf[0]);
-    grad_layer<0>(a, S, gbuf, ss);
-    grad_layer<1>(a, S, gbuf, ss);
-    grad_layer<2>(a, S, gbuf, ss);
-    grad_layer<3>(a, S, gbuf, ss);
+    grad_layer<0, SINGLE>(a, S, gbuf, ss);
+    grad_layer<1, SINGLE>(a, S, gbuf, ss);
+    grad_layer<2, SINGLE>(a, S, gbuf, ss);
+    grad_layer<3, SINGLE>(a, S, gbuf, ss);
 }
 
 __device__ __forceinline__ float adam_update(float* theta, float* m, float* v, int i, float gi, float lr, float c1,
@@ -564,7 +586,11 @@ hipError_t launch_flow_gradient(const FlowTrainArgs& base, int n_wg, float* G0, 
         const hipError_t r = hipEventRecord(ev[0], st);
         if (r != hipSuccess) return r;
     }
-    hipLaunchKernelGGL(k_flow_grad, dim3(n_wg), dim3(kFlowThreads), 0, st, a);
+    // one chunk of 32 samples per wave when the grid covers them all
+    if ((a.n + 31u) / 32u <= (uint32_t)n_wg * kFlowWaves)
+        hipLaunchKernelGGL(k_flow_grad<true>, dim3(n_wg), dim3(kFlowThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_flow_grad<false>, dim3(n_wg), dim3(kFlowThreads), 0, st, a);
     if (ev) {
         const hipError_t r = hipEventRecord(ev[1], st);
         if (r != hipSuccess) return r;

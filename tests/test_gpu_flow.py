@@ -266,12 +266,16 @@ def test_fixed_warp_unbiased():
     v.close()
 
 
-def test_flow_grad_parity():
+# 20 011 samples: one chunk of 32 per wave of the gradient kernel (its
+# single-chunk variant); 40 009: more chunks than waves (the variant that
+# sums several chunks per wave)
+@pytest.mark.parametrize("n_eval", [20_011, 40_009])
+def test_flow_grad_parity(n_eval):
     """GPU gradient of the warp's loss against the oracle with BF16
     emulation, per layer: relative L2 below 1e-4 (measured 3e-7 to 9e-7;
     FP32 arithmetic against FP64, with the same BF16 operands)."""
-    w = corr16()
-    say("[flow grad]")
+    w = corr16(n_eval)
+    say(f"[flow grad] n_eval {n_eval}")
     v = make(w)
     th = random_theta(3).astype(np.float32)
     v.attach_flow(th)
